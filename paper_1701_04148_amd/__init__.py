@@ -1,0 +1,253 @@
+"""Python binding of libsf.so, the MI355X SF-sketch hot path (see include/sf.h).
+
+Argument marshalling only: every step of insert, delete, query and export
+runs in the library's HIP kernels.  PyTorch supplies device memory and the
+HIP stream.  Importing this module does not need a GPU; the first call loads
+libsf.so and raises if it has not been built (there is no CPU fallback).
+
+Functions keep the C names (``sf_create``, ``sf_insert`` ...); ``Sketch``
+wraps them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsf.so")
+
+SF_OK, SF_EINVAL, SF_ENOMEM, SF_EDEVICE, SF_ESTATE, SF_EUNDERFLOW = 0, -1, -2, -3, -4, -5
+SLIM_MAX = 65535
+
+_lib = None
+
+
+class SFError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {sf_strerror(status)} ({status}){': ' + detail if detail else ''}")
+
+
+class sf_config(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_uint32), ("w", ctypes.c_uint32), ("z", ctypes.c_uint32),
+                ("key_bytes", ctypes.c_uint32), ("seed_base", ctypes.c_uint32),
+                ("batch_ops", ctypes.c_uint32)]
+
+
+# (name, restype, argtypes) of every entry point declared in include/sf.h
+_P, _U64, _I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+_CFG = ctypes.POINTER(sf_config)
+SIGNATURES = {
+    "sf_footprint": (_U64, [_CFG]),
+    "sf_create": (_I, [_CFG, _U64, _P, ctypes.POINTER(_P)]),
+    "sf_destroy": (_I, [_P]),
+    "sf_reset": (_I, [_P]),
+    "sf_set_stream": (_I, [_P, _P]),
+    "sf_insert": (_I, [_P, _P, _U64]),
+    "sf_delete": (_I, [_P, _P, _U64]),
+    "sf_update": (_I, [_P, _P, _P, _U64]),
+    "sf_query": (_I, [_P, _P, _U64, _P]),
+    "sf_query_slim": (_I, [_P, _CFG, _P, _U64, _P, _P]),
+    "sf_export_slim": (_I, [_P, _P, _U64]),
+    "sf_export_fat": (_I, [_P, _P, _U64]),
+    "sf_sync": (_I, [_P]),
+    "sf_strerror": (ctypes.c_char_p, [_I]),
+    "sf_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libsf.so; raise loudly when it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "(hipcc --offload-arch=gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype, fn.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def sf_strerror(status: int) -> str:
+    return lib().sf_strerror(status).decode()
+
+
+def sf_last_error() -> str:
+    return lib().sf_last_error().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != SF_OK:
+        raise SFError(rc, where, sf_last_error())
+
+
+def _stream_handle(stream) -> int | None:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def _keys_ptr(keys, key_bytes: int):
+    """(device pointer, n) of a contiguous GPU key tensor."""
+    import torch
+    if not isinstance(keys, torch.Tensor) or not keys.is_cuda:
+        raise TypeError("keys must be a GPU tensor")
+    if not keys.is_contiguous():
+        raise ValueError("keys must be contiguous")
+    nbytes = keys.numel() * keys.element_size()
+    if key_bytes == 4:
+        if keys.element_size() != 4:
+            raise TypeError("uint32 keys need a 4-byte dtype (torch.int32 / torch.uint32)")
+    elif keys.dtype != torch.uint8 or nbytes % 13:
+        raise TypeError("13-byte keys need a uint8 tensor of n*13 bytes")
+    return keys.data_ptr(), nbytes // key_bytes
+
+
+def make_config(d: int, w: int, z: int, key_bytes: int = 4, seed_base: int = 1,
+                batch_ops: int = 1 << 20) -> sf_config:
+    return sf_config(d, w, z, key_bytes, seed_base, batch_ops)
+
+
+def sf_footprint(cfg: sf_config) -> int:
+    return int(lib().sf_footprint(ctypes.byref(cfg)))
+
+
+def sf_create(cfg: sf_config, hbm_budget_bytes: int = 0, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().sf_create(ctypes.byref(cfg), hbm_budget_bytes, _stream_handle(stream),
+                           ctypes.byref(h)), "sf_create")
+    return h
+
+
+def sf_destroy(h):
+    _check(lib().sf_destroy(h), "sf_destroy")
+
+
+def sf_reset(h):
+    _check(lib().sf_reset(h), "sf_reset")
+
+
+def sf_set_stream(h, stream):
+    _check(lib().sf_set_stream(h, _stream_handle(stream)), "sf_set_stream")
+
+
+def sf_insert(h, keys, key_bytes: int = 4):
+    p, n = _keys_ptr(keys, key_bytes)
+    _check(lib().sf_insert(h, p, n), "sf_insert")
+
+
+def sf_delete(h, keys, key_bytes: int = 4):
+    p, n = _keys_ptr(keys, key_bytes)
+    _check(lib().sf_delete(h, p, n), "sf_delete")
+
+
+def sf_update(h, keys, ops, key_bytes: int = 4):
+    import torch
+    p, n = _keys_ptr(keys, key_bytes)
+    if not (isinstance(ops, torch.Tensor) and ops.is_cuda and ops.dtype == torch.uint8
+            and ops.is_contiguous() and ops.numel() == n):
+        raise TypeError("ops must be a contiguous GPU uint8 tensor with one entry per key")
+    _check(lib().sf_update(h, p, ops.data_ptr(), n), "sf_update")
+
+
+def sf_query(h, keys, out, key_bytes: int = 4):
+    p, n = _keys_ptr(keys, key_bytes)
+    if out.numel() < n or out.element_size() != 4 or not out.is_cuda:
+        raise ValueError("out must be a GPU 4-byte tensor with one element per key")
+    _check(lib().sf_query(h, p, n, out.data_ptr()), "sf_query")
+
+
+def sf_query_slim(slim, cfg: sf_config, keys, out, stream=None):
+    p, n = _keys_ptr(keys, cfg.key_bytes)
+    if out.numel() < n or out.element_size() != 4 or not out.is_cuda:
+        raise ValueError("out must be a GPU 4-byte tensor with one element per key")
+    _check(lib().sf_query_slim(slim.data_ptr(), ctypes.byref(cfg), p, n, out.data_ptr(),
+                               _stream_handle(stream)), "sf_query_slim")
+
+
+def sf_export_slim(h, out):
+    _check(lib().sf_export_slim(h, out.ctypes.data if hasattr(out, "ctypes") else out.data_ptr(),
+                                out.size if hasattr(out, "ctypes") else out.numel()),
+           "sf_export_slim")
+
+
+def sf_export_fat(h, out):
+    _check(lib().sf_export_fat(h, out.ctypes.data if hasattr(out, "ctypes") else out.data_ptr(),
+                               out.size if hasattr(out, "ctypes") else out.numel()),
+           "sf_export_fat")
+
+
+def sf_sync(h):
+    _check(lib().sf_sync(h), "sf_sync")
+
+
+class Sketch:
+    """One SF-sketch on the current GPU.
+
+    d rows; w Slim counters (= Fat buckets) per row; z Fat counters per bucket;
+    keys are uint32 (key_bytes=4, torch.int32/uint32 tensors) or packed 13-byte
+    strings (key_bytes=13, uint8 tensors); batch_ops is the update schedule's
+    batch size (1 = sequential semantics).
+    """
+
+    def __init__(self, d: int, w: int, z: int, key_bytes: int = 4, seed_base: int = 1,
+                 batch_ops: int = 1 << 20, hbm_budget_bytes: int = 0, stream=None):
+        self.cfg = make_config(d, w, z, key_bytes, seed_base, batch_ops)
+        self.d, self.w, self.z, self.key_bytes = d, w, z, key_bytes
+        self._h = sf_create(self.cfg, hbm_budget_bytes, stream)
+
+    @property
+    def footprint(self) -> int:
+        return sf_footprint(self.cfg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            sf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, keys):
+        sf_insert(self._h, keys, self.key_bytes)
+
+    def delete(self, keys):
+        sf_delete(self._h, keys, self.key_bytes)
+
+    def update(self, keys, ops):
+        sf_update(self._h, keys, ops, self.key_bytes)
+
+    def query(self, keys, out=None):
+        import torch
+        n = keys.numel() * keys.element_size() // self.key_bytes
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=keys.device)
+        sf_query(self._h, keys, out, self.key_bytes)
+        return out
+
+    def export_slim(self, out=None):
+        import numpy as np
+        if out is None:
+            out = np.empty((self.d, self.w), dtype=np.uint16)
+        sf_export_slim(self._h, out)
+        return out
+
+    def export_fat(self, out=None):
+        import numpy as np
+        if out is None:
+            out = np.empty((self.d, self.w, self.z), dtype=np.uint32)
+        sf_export_fat(self._h, out)
+        return out
+
+    def reset(self):
+        sf_reset(self._h)
+
+    def sync(self):
+        sf_sync(self._h)

@@ -1,0 +1,64 @@
+"""The C ABI library loads and exports what include/sf.h declares; host-side
+validation and budget checks run before any device call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1701_04148_amd as sf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sf_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = ctypes.CDLL(sf.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(sf.SIGNATURES)
+
+
+def test_strerror_texts():
+    assert sf.sf_strerror(0) == "ok"
+    for code in (-1, -2, -3, -4, -5):
+        assert sf.sf_strerror(code) and sf.sf_strerror(code) != "unknown status"
+    assert sf.sf_strerror(-99) == "unknown status"
+
+
+@pytest.mark.parametrize("bad", [dict(d=0), dict(d=17), dict(w=0), dict(z=0), dict(key_bytes=8),
+                                 dict(batch_ops=0), dict(w=1 << 31, z=4)])
+def test_invalid_config_rejected_before_device(bad):
+    cfg = dict(d=4, w=1024, z=4, key_bytes=4, seed_base=1, batch_ops=1024)
+    cfg.update(bad)
+    c = sf.make_config(**cfg)
+    assert sf.sf_footprint(c) == 0
+    h = ctypes.c_void_p()
+    rc = sf.lib().sf_create(ctypes.byref(c), 0, None, ctypes.byref(h))
+    assert rc == sf.SF_EINVAL and not h.value
+    assert sf.sf_last_error()
+
+
+def test_footprint_and_budget():
+    c = sf.make_config(4, 1 << 20, 4, 4, 1, 1 << 21)
+    fp = sf.sf_footprint(c)
+    cells = 4 << 20
+    assert fp == cells * 4 * 4 + cells * 4 + cells * 2 + 4 * (1 << 21) * 6
+    h = ctypes.c_void_p()
+    rc = sf.lib().sf_create(ctypes.byref(c), fp - 1, None, ctypes.byref(h))
+    assert rc == sf.SF_ENOMEM and not h.value
+    assert "budget" in sf.sf_last_error()
+
+
+def test_dead_handles_rejected():
+    for fn in ("sf_destroy", "sf_sync", "sf_reset"):
+        assert getattr(sf.lib(), fn)(None) == sf.SF_ESTATE
+    assert sf.lib().sf_insert(None, None, 0) == sf.SF_ESTATE
+    assert sf.lib().sf_query(ctypes.c_void_p(12345), None, 0, None) == sf.SF_ESTATE

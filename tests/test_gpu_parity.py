@@ -1,0 +1,172 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Fat counters and query answers are integers and must match bit-exactly; the
+Slim must match the oracle's deterministic batch schedule bit-exactly at the
+same batch size (and the sequential rule at batch size 1).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1701_04148_amd as sf
+import sfgen
+from tests.gpu_support import assert_same, dev_keys, gpu_run, oracle_run, say
+from tests.oracle_support import exact_counts, random_turnstile
+
+pytestmark = pytest.mark.gpu
+
+
+def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag=""):
+    say(f"[case] {tag} d={d} w={w} z={z} kb={kb} n={keys.shape[0]} q={queries.shape[0]} "
+        f"b={b} calls={calls}")
+    g = gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls)
+    o = oracle_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls)
+    assert_same(g[0], o[0], "fat")
+    assert_same(g[1], o[1], "slim")
+    assert_same(g[2], o[2], "query")
+    return g
+
+
+@pytest.mark.parametrize("d,w,z,kb", [(4, 1024, 4, 4), (1, 64, 4, 4), (3, 1000, 3, 4),
+                                      (8, 512, 4, 13), (5, 333, 2, 13), (16, 128, 1, 4),
+                                      (2, 4096, 8, 4), (4, 256, 4, 13)])
+@pytest.mark.parametrize("b", [1000, 1 << 20])
+def test_mixed_small(d, w, z, kb, b):
+    """Several tiles and a ragged tail: 20011 mixed ops, 30% deletes."""
+    rng = np.random.default_rng(d * 7 + w + kb)
+    keys, ops, uni = random_turnstile(rng, 20011, 2500, 0.3, key_bytes=kb)
+    check(d, w, z, kb, keys, ops, uni, b, tag="mixed_small")
+
+
+@pytest.mark.parametrize("b", [1, 3, 64])
+def test_small_batches_and_sequential(b):
+    """b = 1 is the sequential SF_F rule of Section 3.5 (the oracle's seq mode)."""
+    rng = np.random.default_rng(b)
+    keys, ops, uni = random_turnstile(rng, 700, 60, 0.3)
+    fat, slim, ans = check(4, 32, 4, 4, keys, ops, uni, b, tag="small_b")
+    if b == 1:
+        ref = oracle.Sketch(4, 32, 4)
+        assert ref.seq(keys, ops, checked=True) == 0
+        assert_same(slim, ref.slim(), "slim vs seq")
+        assert_same(fat, ref.fat(), "fat vs seq")
+
+
+def test_several_calls_start_new_batches():
+    """Every update call starts a new schedule batch."""
+    rng = np.random.default_rng(5)
+    keys, ops, uni = random_turnstile(rng, 30000, 3000, 0.2)
+    check(4, 512, 4, 4, keys, ops, uni, 4096, calls=7, tag="calls")
+
+
+def test_insert_and_delete_entry_points():
+    """sf_insert / sf_delete (uniform op) equal sf_update with the same ops."""
+    import torch
+    rng = np.random.default_rng(8)
+    keys, ops, uni = random_turnstile(rng, 5000, 400, 0.0)
+    dels = keys[rng.permutation(keys.size)[:1500]]
+    sk = sf.Sketch(4, 256, 4, batch_ops=2048)
+    sk.insert(dev_keys(keys))
+    sk.delete(dev_keys(dels))
+    q = sk.query(dev_keys(uni)).cpu().numpy().view(np.uint32)
+    sk.sync()
+    ref = oracle.Sketch(4, 256, 4)
+    assert ref.batch(keys, None, 2048, True) == 0
+    assert ref.batch(dels, np.ones(dels.size, np.uint8), 2048, True) == 0
+    assert_same(sk.export_fat(), ref.fat(), "fat")
+    assert_same(sk.export_slim(), ref.slim(), "slim")
+    assert_same(q, ref.query(uni), "query")
+    sk.close()
+
+
+def test_small_config_full_size():
+    """1M Zipf(1.0) inserts over 100K keys, d=4, Fat 4x65536, Slim 4x16384; all 100K queried."""
+    wl = sfgen.config_small()
+    fat, slim, ans = check(wl.d, wl.w, wl.z, 4, wl.keys, None, wl.queries, 65536, tag="c1")
+    f = exact_counts(wl.keys, None, wl.queries)
+    assert (ans.astype(np.int64) >= np.minimum(f, 65535)).all()
+
+
+def test_main_config_scaled():
+    """The 32M-op configuration divided by 8 (4M ops, 10% deletes, w=2^17), s=1.4."""
+    wl = sfgen.config_main(1.4, scale=8)
+    check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, 1 << 18, tag="c2/8")
+
+
+def test_flow_config_scaled():
+    """13-byte flow keys, d=8, divided by 64 (2M packets over 62.5K flows)."""
+    wl = sfgen.config_flows(scale=64)
+    check(wl.d, wl.w, wl.z, 13, wl.keys, None, wl.queries, 1 << 18, tag="c3/64")
+
+
+def test_query_exported_slim_collector():
+    """The collector answers from the exported uint16 Slim alone (sf_query_slim)."""
+    import torch
+    rng = np.random.default_rng(3)
+    for kb in (4, 13):
+        keys, ops, uni = random_turnstile(rng, 8000, 900, 0.2, key_bytes=kb)
+        sk = sf.Sketch(4, 512, 4, key_bytes=kb, batch_ops=4096)
+        sk.update(dev_keys(keys), torch.from_numpy(ops).cuda())
+        direct = sk.query(dev_keys(uni)).cpu().numpy()
+        slim = torch.from_numpy(sk.export_slim().astype(np.uint16).view(np.int16)).cuda()
+        out = torch.empty(uni.shape[0], dtype=torch.int32, device="cuda")
+        sf.sf_query_slim(slim, sk.cfg, dev_keys(uni), out)
+        torch.cuda.synchronize()
+        assert_same(out.cpu().numpy(), direct, "collector query")
+        exp = oracle.query_slim(sk.export_slim(), 4, 512, 4, uni, key_bytes=kb)
+        assert_same(out.cpu().numpy().view(np.uint32), exp, "collector vs oracle")
+        sk.close()
+
+
+def test_empty_and_tiny_inputs():
+    import torch
+    sk = sf.Sketch(4, 64, 4, batch_ops=8)
+    e = torch.empty(0, dtype=torch.int32, device="cuda")
+    sk.insert(e)
+    sk.delete(e)
+    sk.update(e, torch.empty(0, dtype=torch.uint8, device="cuda"))
+    assert sk.query(e).numel() == 0
+    one = torch.tensor([42], dtype=torch.int32, device="cuda")
+    sk.insert(one)
+    assert int(sk.query(one).item()) == 1
+    sk.delete(one)
+    assert int(sk.query(one).item()) == 0
+    assert not sk.export_fat().any() and not sk.export_slim().any()
+    sk.close()
+
+
+def test_saturation_on_gpu():
+    """Slim saturates at 65535 while the Fat keeps the exact count."""
+    import torch
+    k = torch.full((70000,), 7, dtype=torch.int32, device="cuda")
+    sk = sf.Sketch(4, 64, 4, batch_ops=1 << 16)
+    sk.insert(k)
+    assert int(sk.query(k[:1]).item()) == 65535
+    assert sk.export_fat().max() == 70000
+    sk.delete(k[:10000])
+    assert int(sk.query(k[:1]).item()) == 60000
+    sk.close()
+
+
+def test_bad_arguments_rejected_without_launch():
+    import torch
+    sk = sf.Sketch(4, 64, 4, batch_ops=8)
+    buf = torch.zeros(16, dtype=torch.int32, device="cuda")
+    mis = buf.view(torch.uint8)[1:9]
+    assert sf.lib().sf_insert(sk._h, mis.data_ptr(), 2) == sf.SF_EINVAL      # misaligned
+    assert sf.lib().sf_insert(sk._h, buf.data_ptr(), 1 << 26) == sf.SF_EINVAL  # past the buffer
+    import numpy as _np
+    host = _np.zeros(16, _np.int32)
+    assert sf.lib().sf_insert(sk._h, host.ctypes.data, 16) == sf.SF_EINVAL   # pageable host
+    small = _np.zeros(3, _np.uint16)
+    assert sf.lib().sf_export_slim(sk._h, small.ctypes.data, 3) == sf.SF_EINVAL
+    sk.close()
+    assert sf.lib().sf_sync(sk._h or None) == sf.SF_ESTATE
+
+
+def test_hbm_budget_admission():
+    c = sf.make_config(4, 1 << 16, 4, 4, 1, 1 << 16)
+    with pytest.raises(sf.SFError) as e:
+        sf.sf_create(c, sf.sf_footprint(c) - 1)
+    assert e.value.status == sf.SF_ENOMEM
+    h = sf.sf_create(c, sf.sf_footprint(c))
+    sf.sf_destroy(h)
