@@ -127,6 +127,32 @@ int sf_export_fat(sf_sketch *sk, uint32_t *out, uint64_t out_elems);
 /* Wait for all work enqueued on the sketch's stream. */
 int sf_sync(sf_sketch *sk);
 
+/* ---- per-kernel timing (measurement aid; off by default) ----------------
+ * When enabled, every kernel the sketch launches is bracketed by two HIP
+ * events recorded on the sketch's stream.  sf_profile_read waits for them
+ * and returns, per kernel kind, the summed duration, the launch count and
+ * the items (ops, keys or cells) the launches covered; reset != 0 clears
+ * the accumulators. */
+enum sf_kernel_kind {
+    SF_K_SNAPSHOT = 0, /* S1 */
+    SF_K_FAT_ADD = 1,  /* S2 */
+    SF_K_RAISE = 2,    /* S3 */
+    SF_K_FAT_SUB = 3,  /* S4 */
+    SF_K_CLAMP = 4,    /* S5 */
+    SF_K_QUERY = 5,
+    SF_K_EXPORT = 6,
+    SF_K_COUNT = 8
+};
+
+typedef struct sf_kernel_stats {
+    double ms[SF_K_COUNT];
+    uint64_t launches[SF_K_COUNT];
+    uint64_t items[SF_K_COUNT];
+} sf_kernel_stats;
+
+int sf_profile(sf_sketch *sk, int enable);
+int sf_profile_read(sf_sketch *sk, sf_kernel_stats *out, int reset);
+
 /* Static text of a status code. */
 const char *sf_strerror(int status);
 

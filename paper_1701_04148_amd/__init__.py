@@ -34,6 +34,14 @@ class sf_config(ctypes.Structure):
                 ("batch_ops", ctypes.c_uint32)]
 
 
+KERNEL_KINDS = ("snapshot", "fat_add", "raise", "fat_sub", "clamp", "query", "export")
+
+
+class sf_kernel_stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8),
+                ("items", ctypes.c_uint64 * 8)]
+
+
 # (name, restype, argtypes) of every entry point declared in include/sf.h
 _P, _U64, _I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
 _CFG = ctypes.POINTER(sf_config)
@@ -51,6 +59,8 @@ SIGNATURES = {
     "sf_export_slim": (_I, [_P, _P, _U64]),
     "sf_export_fat": (_I, [_P, _P, _U64]),
     "sf_sync": (_I, [_P]),
+    "sf_profile": (_I, [_P, _I]),
+    "sf_profile_read": (_I, [_P, ctypes.POINTER(sf_kernel_stats), _I]),
     "sf_strerror": (ctypes.c_char_p, [_I]),
     "sf_last_error": (ctypes.c_char_p, []),
 }
@@ -185,6 +195,17 @@ def sf_sync(h):
     _check(lib().sf_sync(h), "sf_sync")
 
 
+def sf_profile(h, enable: bool):
+    _check(lib().sf_profile(h, int(bool(enable))), "sf_profile")
+
+
+def sf_profile_read(h, reset: bool = True) -> dict:
+    """{kind: (total ms, launches, items)} of the kernels launched while profiling."""
+    st = sf_kernel_stats()
+    _check(lib().sf_profile_read(h, ctypes.byref(st), int(bool(reset))), "sf_profile_read")
+    return {k: (st.ms[i], int(st.launches[i]), int(st.items[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
 class Sketch:
     """One SF-sketch on the current GPU.
 
@@ -248,6 +269,12 @@ class Sketch:
 
     def reset(self):
         sf_reset(self._h)
+
+    def profile(self, enable: bool = True):
+        sf_profile(self._h, enable)
+
+    def profile_read(self, reset: bool = True) -> dict:
+        return sf_profile_read(self._h, reset)
 
     def sync(self):
         sf_sync(self._h)

@@ -7,6 +7,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SO = os.path.join(PKG, "libsf.so")
+MICRO_SO = os.path.join(PKG, "libsf_micro.so")
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
@@ -16,15 +17,20 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    src = os.path.join(PKG, "csrc", "sf_lib.hip")
-    tmp = SO + ".tmp"
+def _hipcc(src: str, out: str, verbose: bool):
+    tmp = out + ".tmp"
     cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
            "-o", tmp, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, SO)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libsf.so (the sketch) and libsf_micro.so (measurement kernels)."""
+    _hipcc(os.path.join(PKG, "csrc", "sf_lib.hip"), SO, verbose)
+    _hipcc(os.path.join(PKG, "csrc", "sf_micro.hip"), MICRO_SO, verbose)
     return SO
 
 

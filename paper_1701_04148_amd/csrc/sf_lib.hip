@@ -25,6 +25,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_set>
+#include <vector>
 
 #include "sf.h"
 #include "sf_device.hpp"
@@ -227,6 +228,12 @@ __global__ __launch_bounds__(kBlock) void k_pack16(const uint32_t* __restrict__ 
 
 // ====================================================================== host side
 
+struct ProfRec {
+    int kind;
+    uint64_t items;
+    hipEvent_t a, b;
+};
+
 struct sf_sketch {
     sf_config cfg;
     Geom g;
@@ -238,6 +245,10 @@ struct sf_sketch {
     uint32_t* bpre;
     uint16_t* asnap;
     uint32_t stride;  // snapshot capacity in ops (= batch_ops)
+    bool prof;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> spare;
+    sf_kernel_stats acc;
 };
 
 namespace {
@@ -346,23 +357,86 @@ bool host_dest(void* p) {
     return at.type != hipMemoryTypeDevice && !at.isManaged;
 }
 
+hipEvent_t take_event(sf_sketch* s) {
+    hipEvent_t e = nullptr;
+    if (!s->spare.empty()) {
+        e = s->spare.back();
+        s->spare.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Brackets one launch with events on the sketch's stream when profiling.
+struct Timed {
+    sf_sketch* s;
+    ProfRec r;
+    Timed(sf_sketch* sk, hipStream_t st, int kind, uint64_t items) : s(sk), r{kind, items, nullptr, nullptr} {
+        if (!s || !s->prof) return;
+        r.a = take_event(s);
+        r.b = take_event(s);
+        if (r.a) (void)hipEventRecord(r.a, st);
+        st_ = st;
+    }
+    ~Timed() {
+        if (!s || !s->prof || !r.a || !r.b) return;
+        (void)hipEventRecord(r.b, st_);
+        s->recs.push_back(r);
+    }
+    hipStream_t st_ = nullptr;
+};
+
+int drain_profile(sf_sketch* s) {
+    hipError_t err = hipSuccess;
+    for (auto& r : s->recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        s->acc.ms[r.kind] += ms;
+        s->acc.launches[r.kind] += 1;
+        s->acc.items[r.kind] += r.items;
+        s->spare.push_back(r.a);
+        s->spare.push_back(r.b);
+    }
+    s->recs.clear();
+    return err == hipSuccess ? SF_OK : device_fail(err, "profile events");
+}
+
 unsigned grid_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
 // One schedule batch of cnt ops starting at keys/ops.
 template <int KB, int D>
-void launch_batch(const sf_sketch* s, const uint8_t* keys, const uint8_t* ops, uint32_t uniform_del,
+void launch_batch(sf_sketch* s, const uint8_t* keys, const uint8_t* ops, uint32_t uniform_del,
                   uint32_t cnt, bool ins, bool del) {
     const dim3 grid(grid_for(cnt)), block(kBlock);
     if (ins) {
-        k_snapshot<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat,
-                                                          s->slim, s->bpre, s->asnap, s->stride);
-        k_fat_update<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, 0u);
-        k_raise<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, s->slim,
-                                                       s->bpre, s->asnap, s->stride);
+        {
+            Timed tm(s, s->stream, SF_K_SNAPSHOT, cnt);
+            k_snapshot<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat,
+                                                              s->slim, s->bpre, s->asnap, s->stride);
+        }
+        {
+            Timed tm(s, s->stream, SF_K_FAT_ADD, cnt);
+            k_fat_update<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, 0u);
+        }
+        {
+            Timed tm(s, s->stream, SF_K_RAISE, cnt);
+            k_raise<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, s->slim,
+                                                           s->bpre, s->asnap, s->stride);
+        }
     }
     if (del) {
-        k_fat_update<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, 1u);
-        k_clamp<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, s->slim);
+        {
+            Timed tm(s, s->stream, SF_K_FAT_SUB, cnt);
+            k_fat_update<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, 1u);
+        }
+        {
+            Timed tm(s, s->stream, SF_K_CLAMP, cnt);
+            k_clamp<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, s->slim);
+        }
     }
 }
 
@@ -484,6 +558,11 @@ int sf_destroy(sf_sketch* s) {
     }
     hipError_t e = hipStreamSynchronize(s->stream);
     hipError_t e2 = hipFree(s->fat);
+    for (auto& r : s->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto ev : s->spare) (void)hipEventDestroy(ev);
     delete s;
     if (e != hipSuccess) return device_fail(e, "sf_destroy sync");
     if (e2 != hipSuccess) return device_fail(e2, "sf_destroy free");
@@ -513,7 +592,7 @@ int sf_update(sf_sketch* s, const void* keys, const uint8_t* ops, uint64_t n) {
     return run_updates(s, keys, ops, n, kMixed);
 }
 
-static int query_common(const sf_config* c, const Geom& g, const void* slim, bool slim16,
+static int query_common(sf_sketch* s, const sf_config* c, const Geom& g, const void* slim, bool slim16,
                         const void* keys, uint64_t n, uint32_t* out, hipStream_t st) {
     if (n == 0) return SF_OK;
     const uint32_t kb = c->key_bytes;
@@ -526,6 +605,7 @@ static int query_common(const sf_config* c, const Geom& g, const void* slim, boo
     const uint8_t* k8 = static_cast<const uint8_t*>(keys);
     for (uint64_t lo = 0; lo < n; lo += kMaxLaunch) {
         const uint32_t cnt = uint32_t(n - lo < kMaxLaunch ? n - lo : kMaxLaunch);
+        Timed tm(s, st, SF_K_QUERY, cnt);
         if (slim16)
             query_dispatch<uint16_t>(kb, c->d, k8 + lo * kb, cnt, g, static_cast<const uint16_t*>(slim),
                                      out + lo, st);
@@ -539,7 +619,7 @@ static int query_common(const sf_config* c, const Geom& g, const void* slim, boo
 
 int sf_query(sf_sketch* s, const void* keys, uint64_t n, uint32_t* out) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
-    return query_common(&s->cfg, s->g, s->slim, false, keys, n, out, s->stream);
+    return query_common(s, &s->cfg, s->g, s->slim, false, keys, n, out, s->stream);
 }
 
 int sf_query_slim(const uint16_t* slim, const sf_config* cfg, const void* keys, uint64_t n,
@@ -549,7 +629,7 @@ int sf_query_slim(const uint16_t* slim, const sf_config* cfg, const void* keys, 
     int rc = validate(cfg ? &c : nullptr);
     if (rc) return rc;
     if (n && (rc = check_gpu_ptr(slim, uint64_t(c.d) * c.w * 2, "slim"))) return rc;
-    return query_common(&c, geom_of(&c), slim, true, keys, n, out, static_cast<hipStream_t>(hip_stream));
+    return query_common(nullptr, &c, geom_of(&c), slim, true, keys, n, out, static_cast<hipStream_t>(hip_stream));
 }
 
 int sf_export_slim(sf_sketch* s, uint16_t* out, uint64_t out_elems) {
@@ -564,7 +644,10 @@ int sf_export_slim(sf_sketch* s, uint16_t* out, uint64_t out_elems) {
     }
     uint16_t* dst = host ? s->stage : out;
     const unsigned grid = grid_for(cells) < 4096u ? grid_for(cells) : 4096u;
-    k_pack16<<<dim3(grid), dim3(kBlock), 0, s->stream>>>(s->slim, dst, cells);
+    {
+        Timed tm(s, s->stream, SF_K_EXPORT, cells);
+        k_pack16<<<dim3(grid), dim3(kBlock), 0, s->stream>>>(s->slim, dst, cells);
+    }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && host) e = hipMemcpyAsync(out, s->stage, cells * 2, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -589,6 +672,20 @@ int sf_sync(sf_sketch* s) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
     hipError_t e = hipStreamSynchronize(s->stream);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_sync");
+}
+
+int sf_profile(sf_sketch* s, int enable) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    s->prof = enable != 0;
+    return SF_OK;
+}
+
+int sf_profile_read(sf_sketch* s, sf_kernel_stats* out, int reset) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    int rc = drain_profile(s);
+    if (out) *out = s->acc;
+    if (reset) s->acc = sf_kernel_stats{};
+    return rc;
 }
 
 const char* sf_strerror(int status) {
