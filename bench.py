@@ -90,7 +90,65 @@ def stored_traffic(kernel_kind: str, workload: str):
     return k.get("hbm_bytes_per_launch")
 
 
-def micro_ceilings(torch, sizes_mib=(16, 64, 256, 4096), n=1 << 26):
+KIND_OF_KERNEL = {"k_snapshot": "snapshot", "k_raise": "raise", "k_clamp": "clamp",
+                  "k_query": "query", "k_pack16": "export"}
+
+
+def _kernel_base(name: str) -> str:
+    base = name.replace("(anonymous namespace)::", "").replace("void ", "").strip()
+    return base.split("(")[0].split("<")[0].strip()
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int) -> dict:
+    """Per-kernel HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch), scaled so the plain copy kernel reads and writes
+    exactly copy_bytes.  k_fat_update dispatches alternate add / subtract within a
+    batch (add follows the snapshot, subtract follows the raise)."""
+    import csv
+    from collections import defaultdict
+
+    def per_kind(path, counter):
+        rows = []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                rows.append((int(r.get("Dispatch_Id", 0)), _kernel_base(r["Kernel_Name"]),
+                             float(r["Counter_Value"])))
+        rows.sort()
+        vals, prev = defaultdict(list), None
+        for _, base, v in rows:
+            if base == "k_fat_update":
+                kind = "fat_sub" if prev == "k_raise" else "fat_add"
+            else:
+                kind = KIND_OF_KERNEL.get(base, base)
+            vals[kind].append(v)
+            prev = base
+        return {k: sum(v) / len(v) for k, v in vals.items()}
+
+    fetch, write = per_kind(fetch_csv, "FETCH_SIZE"), per_kind(write_csv, "WRITE_SIZE")
+    f_scale = (copy_bytes / 1024.0) / fetch["k_copy"]
+    w_scale = (copy_bytes / 1024.0) / write["k_copy"]
+    kernels = {}
+    for kind in fetch:
+        if kind == "k_copy" or kind not in write:
+            continue
+        rd, wr = fetch[kind] * f_scale * 1024, write[kind] * w_scale * 1024
+        kernels[kind] = {"fetch_kib_raw": round(fetch[kind], 1), "write_kib_raw": round(write[kind], 1),
+                         "hbm_bytes_per_launch": int(rd + wr)}
+    return {"workload": workload, "source_digest": source_digest(),
+            "copy_calibration": {"bytes": copy_bytes, "fetch_scale": round(f_scale, 4),
+                                 "write_scale": round(w_scale, 4)},
+            "kernels": kernels}
+
+
+def workload_tag(args) -> str:
+    """Name of the timed workload (sketch shape, stream, schedule, tile) for stored counters."""
+    return (f"c2_d4_w{2**20 // args.scale}_z4_ops{32_000_000 // args.scale}_zipf{args.skew}_del10"
+            f"_b{args.batch_ops}_tile{args.tile}")
+
+
+def micro_ceilings(torch, sizes_mib=(1, 16, 64, 256, 4096), n=1 << 26):
     """Measured random-access ceilings (G accesses/s) at several footprints."""
     from paper_1701_04148_amd import micro
     out = {}
@@ -101,7 +159,9 @@ def micro_ceilings(torch, sizes_mib=(16, 64, 256, 4096), n=1 << 26):
         res = {}
         for name, fn in (("gather_u32", lambda s: micro.gather_u32(t, n, s, sink)),
                          ("atomic_add_u32", lambda s: micro.atomic_add_u32(t, n, s)),
-                         ("gather_16b", lambda s: micro.gather_16b(t, n, s, sink))):
+                         ("gather_16b", lambda s: micro.gather_16b(t, n, s, sink)),
+                         ("pair_same_line", lambda s: micro.gather_pair(t, n, s, True, sink)),
+                         ("pair_two_lines", lambda s: micro.gather_pair(t, n, s, False, sink))):
             fn(1)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -125,11 +185,22 @@ def main():
     ap.add_argument("--skew", type=float, default=1.0, help="Zipf s (0.6, 1.0, 1.4)")
     ap.add_argument("--batch-ops", type=int, default=1 << 21, help="schedule batch size b")
     ap.add_argument("--scale", type=int, default=1, help="divide every size (quick runs)")
+    ap.add_argument("--tile", type=int, default=2048, help="ops per duplicate-merging tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain copy of this many MiB (known traffic, for byte counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/pmc_traffic.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        rec = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], workload_tag(args),
+                            args.copy_calibration_mib << 20)
+        with open(os.path.join(PROFILE_DIR, "pmc_traffic.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -158,6 +229,7 @@ def main():
     slim16 = torch.empty(cells, dtype=torch.int16, device=dev)
     b = args.batch_ops
     sk = sf.Sketch(wl.d, wl.w, wl.z, batch_ops=b)
+    sk.set_tile(args.tile)
 
     def step():
         sk.reset()
@@ -216,10 +288,9 @@ def main():
     alg_per_launch = algorithmic_bytes(dom, wl.d, n_ins, n_del, wl.n_ops, True, wl.n_queries,
                                        cells) * args.steps / dk["launches"]
     achieved = alg_per_launch / (dk["avg_launch_us"] * 1e-6) / 1e9
-    workload_tag = wl.name + f"_b{b}"
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(dom, workload_tag)}
+                "traffic": stored_traffic(dom, workload_tag(args))}
     log(f"[bench] kernels: {json.dumps(kernels)}")
 
     result = {
@@ -232,7 +303,8 @@ def main():
                                f"with {n_del} deletes; export Slim; {wl.n_queries} queries "
                                "(present + absent); keys resident in HBM",
                    "sketches": 1, "d": wl.d, "w": wl.w, "z": wl.z, "ops": wl.n_ops, "deletes": n_del,
-                   "queries": wl.n_queries, "zipf_s": args.skew, "batch_ops": b, "scale": args.scale},
+                   "queries": wl.n_queries, "zipf_s": args.skew, "batch_ops": b, "tile_ops": args.tile,
+                   "scale": args.scale},
         "roofline": roofline,
         "kernels": kernels,
     }

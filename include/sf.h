@@ -127,6 +127,12 @@ int sf_export_fat(sf_sketch *sk, uint32_t *out, uint64_t out_elems);
 /* Wait for all work enqueued on the sketch's stream. */
 int sf_sync(sf_sketch *sk);
 
+/* Launch shape of the duplicate-merging kernels: each workgroup groups the
+ * keys of a tile of tile_ops consecutive ops (256, 1024 or 2048; default
+ * 2048) and issues one atomic per distinct key.  Results do not depend on
+ * it; throughput on skewed streams does. */
+int sf_set_tile(sf_sketch *sk, uint32_t tile_ops);
+
 /* ---- per-kernel timing (measurement aid; off by default) ----------------
  * When enabled, every kernel the sketch launches is bracketed by two HIP
  * events recorded on the sketch's stream.  sf_profile_read waits for them

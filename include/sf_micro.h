@@ -34,6 +34,22 @@ int micro_gather_u32(const uint32_t *table, uint64_t elems, uint64_t n, uint32_t
 int micro_atomic_add_u32(uint32_t *table, uint64_t elems, uint64_t n, uint32_t seed,
                          void *hip_stream);
 
+/* n random relaxed atomic adds of 1 where each workgroup only touches the
+ * 1/nxcc slice of the table that belongs to the XCD it runs on (read from the
+ * XCC_ID hardware register); wg_scope != 0 uses workgroup-scope atomics.
+ * nxcc and elems are powers of two, elems >= 64 * nxcc. */
+int micro_atomic_add_xcd(uint32_t *table, uint64_t elems, uint64_t n, uint32_t seed, uint32_t nxcc,
+                         uint32_t wg_scope, void *hip_stream);
+
+/* n accesses of two 4-byte loads each: the second one 64 bytes away in the
+ * same aligned 128-byte block (same_line != 0) or at an independent random
+ * index.  Tells whether co-locating two counters in one line saves a fetch. */
+int micro_gather_pair(const uint32_t *table, uint64_t elems, uint64_t n, uint32_t seed,
+                      uint32_t same_line, uint32_t *sink, void *hip_stream);
+
+/* XCDs (XCCs) of the current device, or -3 on error. */
+int micro_num_xcc(void);
+
 /* n random aligned 16-byte loads (one Fat bucket of four uint32) from
  * table[0 .. elems) (elems a power of two, counted in uint32). */
 int micro_gather_16b(const uint32_t *table, uint64_t elems, uint64_t n, uint32_t seed,

@@ -59,6 +59,7 @@ SIGNATURES = {
     "sf_export_slim": (_I, [_P, _P, _U64]),
     "sf_export_fat": (_I, [_P, _P, _U64]),
     "sf_sync": (_I, [_P]),
+    "sf_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_profile": (_I, [_P, _I]),
     "sf_profile_read": (_I, [_P, ctypes.POINTER(sf_kernel_stats), _I]),
     "sf_strerror": (ctypes.c_char_p, [_I]),
@@ -195,6 +196,10 @@ def sf_sync(h):
     _check(lib().sf_sync(h), "sf_sync")
 
 
+def sf_set_tile(h, tile_ops: int):
+    _check(lib().sf_set_tile(h, tile_ops), "sf_set_tile")
+
+
 def sf_profile(h, enable: bool):
     _check(lib().sf_profile(h, int(bool(enable))), "sf_profile")
 
@@ -269,6 +274,9 @@ class Sketch:
 
     def reset(self):
         sf_reset(self._h)
+
+    def set_tile(self, tile_ops: int):
+        sf_set_tile(self._h, tile_ops)
 
     def profile(self, enable: bool = True):
         sf_profile(self._h, enable)

@@ -1,7 +1,7 @@
 // Device-side building blocks of the SF-sketch kernels (gfx950, wave64):
 // key loads, MurmurHash3 row hashing in registers, the Eq. (1) index split,
-// and the wavefront key grouping that merges duplicate keys before they reach
-// a counter.
+// and the LDS tile grouping that merges duplicate keys before they reach a
+// counter.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -66,15 +66,6 @@ __device__ __forceinline__ bool key_eq(const Key<KB>& a, const Key<KB>& b) {
     return e;
 }
 
-template <int KB>
-__device__ __forceinline__ Key<KB> key_from_lane(const Key<KB>& k, int lane) {
-    Key<KB> r;
-#pragma unroll
-    for (int j = 0; j < int(sizeof(k.v) / 4); j++)
-        r.v[j] = uint32_t(__builtin_amdgcn_readlane(int(k.v[j]), lane));
-    return r;
-}
-
 // ---------------------------------------------------------------- hashing
 // MurmurHash3_x86_32 split into its seed-independent block mixing (done once
 // per key) and the per-seed rounds (done once per row).
@@ -128,27 +119,55 @@ __device__ __forceinline__ void split(const Geom& g, uint32_t hash, uint32_t& h,
     }
 }
 
-// ---------------------------------------------------------------- grouping
-// Lanes of a wavefront whose keys are equal form one group; the group's
-// lowest lane acts for all of them (one atomic carrying the group size
-// instead of one per duplicate).  Iterations = distinct keys among the
-// active lanes.  Must be reached by every lane of the wavefront.
-template <int KB>
-__device__ __forceinline__ uint64_t wave_group(const Key<KB>& k, bool active) {
-    uint64_t todo = __ballot(active);
-    uint64_t mine = 0;
-    while (todo) {
-        int leader = __builtin_ctzll(todo);
-        Key<KB> lk = key_from_lane<KB>(k, leader);
-        bool same = active && key_eq<KB>(k, lk);
-        uint64_t grp = __ballot(same);
-        if (same) mine = grp;
-        todo &= ~grp;
-    }
-    return mine;
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+// ---------------------------------------------------------------- tile grouping
+// A workgroup takes a tile of kBlock*J consecutive ops and groups its active
+// ops by key in an LDS hash table (open addressing, 2x the tile, so probing
+// always ends).  Each occupied slot then acts once for all of its ops: one
+// Fat atomic carrying the group size, or one Slim raise / clamp.  The owner
+// op of a slot (the first to claim it) depends on timing, but every op of a
+// key computes the same value, so results do not.
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+template <int KB> __device__ __forceinline__ uint32_t slot_hash(const Key<KB>& k) {
+    uint32_t h = 0x9e3779b9u;
+#pragma unroll
+    for (int j = 0; j < int(sizeof(k.v) / 4); j++) h = mm_round(h, mm_mix(k.v[j]));
+    return mm_final(h, 0u);
 }
 
-__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+template <int KB, int J> struct TileLDS {
+    static constexpr uint32_t kOps = uint32_t(kBlock) * J;
+    static constexpr uint32_t kSlots = 2 * kOps;
+    Key<KB> key[kOps];      // key of each op of the tile (by local index)
+    uint32_t owner[kSlots]; // local index of the op that claimed the slot, or kEmpty
+    uint32_t cnt[kSlots];   // ops of the slot's key in the tile
+};
+
+template <int KB, int J>
+__device__ __forceinline__ void tile_clear(TileLDS<KB, J>& L) {
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
+        L.owner[s] = kEmpty;
+        L.cnt[s] = 0;
+    }
+}
+
+// Insert local op `idx` (key k) into the table; L.key[idx] must already hold k
+// for every inserted op (a barrier separates the key stores from the probing).
+template <int KB, int J>
+__device__ __forceinline__ void tile_insert(TileLDS<KB, J>& L, const Key<KB>& k, uint32_t idx) {
+    constexpr uint32_t mask = TileLDS<KB, J>::kSlots - 1;
+    uint32_t s = slot_hash<KB>(k) & mask;
+    for (uint32_t probe = 0; probe < TileLDS<KB, J>::kSlots; probe++) {
+        const uint32_t prev = atomicCAS(&L.owner[s], kEmpty, idx);
+        if (prev == kEmpty || key_eq<KB>(L.key[prev], k)) {
+            atomicAdd(&L.cnt[s], 1u);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
 
 __device__ __forceinline__ void atomic_add_u32(uint32_t* p, uint32_t v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

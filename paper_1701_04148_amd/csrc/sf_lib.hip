@@ -63,38 +63,63 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const uint8_t* __restrict__
     }
 }
 
+// Loads the tile's active ops (op type == want_del) into the LDS table.
+// Returns after a barrier; the table then holds each distinct key once.
+template <int KB, int J>
+__device__ __forceinline__ void tile_build(TileLDS<KB, J>& L, const uint8_t* __restrict__ keys,
+                                           const uint8_t* __restrict__ ops, uint32_t uniform_del,
+                                           uint32_t cnt, uint32_t base, bool want_del) {
+    tile_clear<KB, J>(L);
+    Key<KB> k[J];
+    bool act[J];
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
+        const uint32_t t = base + idx;
+        act[j] = t < cnt && is_delete(ops, t, uniform_del) == want_del;
+        if (act[j]) {
+            k[j] = load_key<KB>(keys, t);
+            L.key[idx] = k[j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; j++)
+        if (act[j]) tile_insert<KB, J>(L, k[j], uint32_t(j) * kBlock + threadIdx.x);
+    __syncthreads();
+}
+
 // S2 / S4: Fat counters of every insert (want_del = 0) or delete (want_del = 1)
-// op move by one; duplicate keys of a wavefront are merged into one atomic.
-template <int KB, int D>
+// op move by one: one atomic per distinct key of the tile, carrying its count.
+template <int KB, int D, int J>
 __global__ __launch_bounds__(kBlock) void k_fat_update(const uint8_t* __restrict__ keys,
                                                        const uint8_t* __restrict__ ops,
                                                        uint32_t uniform_del, uint32_t cnt, Geom g,
                                                        uint32_t* __restrict__ fat, uint32_t want_del) {
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
-    bool active = false;
-    Key<KB> k = {};
-    if (t < cnt && is_delete(ops, t, uniform_del) == (want_del != 0)) {
-        active = true;
-        k = load_key<KB>(keys, t);
-    }
-    const uint64_t grp = wave_group<KB>(k, active);
-    if (!active || lane_id() != uint32_t(__builtin_ctzll(grp))) return;
-    const uint32_t n = uint32_t(__popcll(grp));
-    const uint32_t v = want_del ? 0u - n : n;
-    const Mixed<KB> mx(k);
+    __shared__ TileLDS<KB, J> L;
+    const uint32_t base = blockIdx.x * TileLDS<KB, J>::kOps;
+    tile_build<KB, J>(L, keys, ops, uniform_del, cnt, base, want_del != 0);
     const uint32_t d = D ? uint32_t(D) : g.d;
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
+        const uint32_t o = L.owner[s];
+        if (o == kEmpty) continue;
+        const uint32_t n = L.cnt[s];
+        const uint32_t v = want_del ? 0u - n : n;
+        const Mixed<KB> mx(L.key[o]);
 #pragma unroll
-    for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
-        if (i < d) {
-            uint32_t h, f;
-            split(g, mx.row(g.seed_base + i), h, f);
-            atomic_add_u32(&fat[(size_t(i) * g.w + h) * g.z + f], v);
+        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+            if (i < d) {
+                uint32_t h, f;
+                split(g, mx.row(g.seed_base + i), h, f);
+                atomic_add_u32(&fat[(size_t(i) * g.w + h) * g.z + f], v);
+            }
         }
     }
 }
 
-// S3: raise the Slim counters of every inserted key to its water level T.
-template <int KB, int D>
+// S3: raise the Slim counters of every inserted key to its water level
+// T = min(m0 + delta, max(m0, Bmin), 65535), once per distinct key of the tile.
+template <int KB, int D, int J>
 __global__ __launch_bounds__(kBlock) void k_raise(const uint8_t* __restrict__ keys,
                                                   const uint8_t* __restrict__ ops,
                                                   uint32_t uniform_del, uint32_t cnt, Geom g,
@@ -103,17 +128,17 @@ __global__ __launch_bounds__(kBlock) void k_raise(const uint8_t* __restrict__ ke
                                                   const uint32_t* __restrict__ bpre,
                                                   const uint16_t* __restrict__ asnap, uint32_t stride) {
     constexpr int R = D ? D : kMaxD;
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    __shared__ TileLDS<KB, J> L;
+    const uint32_t base = blockIdx.x * TileLDS<KB, J>::kOps;
+    tile_build<KB, J>(L, keys, ops, uniform_del, cnt, base, false);
     const uint32_t d = D ? uint32_t(D) : g.d;
-    bool active = false, need = false;
-    Key<KB> k = {};
-    size_t cell[R];
-    uint32_t a[R];
-    uint32_t T = 0;
-    if (t < cnt && !is_delete(ops, t, uniform_del)) {
-        active = true;
-        k = load_key<KB>(keys, t);
-        const Mixed<KB> mx(k);
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
+        const uint32_t o = L.owner[s];
+        if (o == kEmpty) continue;
+        const uint32_t t = base + o;  // any op of the key: all share one snapshot
+        const Mixed<KB> mx(L.key[o]);
+        size_t cell[R];
+        uint32_t a[R];
         uint32_t m0 = ~0u, bmin = ~0u, delta = ~0u;
 #pragma unroll
         for (int i = 0; i < R; i++) {
@@ -133,17 +158,12 @@ __global__ __launch_bounds__(kBlock) void k_raise(const uint8_t* __restrict__ ke
         }
         const uint64_t rise = uint64_t(m0) + delta;
         const uint64_t level = m0 > bmin ? m0 : bmin;
-        uint64_t tt = rise < level ? rise : level;
-        T = uint32_t(tt < kSlimMax ? tt : kSlimMax);
+        const uint64_t tt = rise < level ? rise : level;
+        const uint32_t T = uint32_t(tt < kSlimMax ? tt : kSlimMax);
 #pragma unroll
-        for (int i = 0; i < R; i++) need = need || (uint32_t(i) < d && a[i] < T);
+        for (int i = 0; i < R; i++)
+            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&slim[cell[i]], T);
     }
-    const bool go = active && need;
-    const uint64_t grp = wave_group<KB>(k, go);
-    if (!go || lane_id() != uint32_t(__builtin_ctzll(grp))) return;
-#pragma unroll
-    for (int i = 0; i < R; i++)
-        if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&slim[cell[i]], T);
 }
 
 // Largest counter of a Fat bucket.
@@ -158,44 +178,33 @@ __device__ __forceinline__ uint32_t bucket_max(const uint32_t* __restrict__ fat,
     return m;
 }
 
-// S5: clamp the Slim counters of every deleted key to their bucket's max.
-template <int KB, int D>
+// S5: clamp the Slim counters of every deleted key to their bucket's max,
+// once per distinct key of the tile.
+template <int KB, int D, int J>
 __global__ __launch_bounds__(kBlock) void k_clamp(const uint8_t* __restrict__ keys,
                                                   const uint8_t* __restrict__ ops,
                                                   uint32_t uniform_del, uint32_t cnt, Geom g,
                                                   const uint32_t* __restrict__ fat,
                                                   uint32_t* __restrict__ slim) {
-    constexpr int R = D ? D : kMaxD;
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    __shared__ TileLDS<KB, J> L;
+    const uint32_t base = blockIdx.x * TileLDS<KB, J>::kOps;
+    tile_build<KB, J>(L, keys, ops, uniform_del, cnt, base, true);
     const uint32_t d = D ? uint32_t(D) : g.d;
-    bool active = false, need = false;
-    Key<KB> k = {};
-    size_t cell[R];
-    uint32_t m[R], a[R];
-    if (t < cnt && is_delete(ops, t, uniform_del)) {
-        active = true;
-        k = load_key<KB>(keys, t);
-        const Mixed<KB> mx(k);
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
+        const uint32_t o = L.owner[s];
+        if (o == kEmpty) continue;
+        const Mixed<KB> mx(L.key[o]);
 #pragma unroll
-        for (int i = 0; i < R; i++) {
-            cell[i] = 0;
-            m[i] = a[i] = 0;
-            if (uint32_t(i) < d) {
+        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+            if (i < d) {
                 uint32_t h, f;
                 split(g, mx.row(g.seed_base + i), h, f);
-                cell[i] = size_t(i) * g.w + h;
-                m[i] = bucket_max(fat, cell[i], g);
-                a[i] = slim[cell[i]];
-                need = need || a[i] > m[i];
+                const size_t cell = size_t(i) * g.w + h;
+                const uint32_t m = bucket_max(fat, cell, g);
+                if (slim[cell] > m) atomic_min_u32(&slim[cell], m);
             }
         }
     }
-    const bool go = active && need;
-    const uint64_t grp = wave_group<KB>(k, go);
-    if (!go || lane_id() != uint32_t(__builtin_ctzll(grp))) return;
-#pragma unroll
-    for (int i = 0; i < R; i++)
-        if (uint32_t(i) < d && a[i] > m[i]) atomic_min_u32(&slim[cell[i]], m[i]);
 }
 
 // Point query: minimum of the d Slim counters of each key.
@@ -245,6 +254,7 @@ struct sf_sketch {
     uint32_t* bpre;
     uint16_t* asnap;
     uint32_t stride;  // snapshot capacity in ops (= batch_ops)
+    uint32_t tile_j;  // ops per thread of the grouping kernels (tile = 256 * tile_j ops)
     bool prof;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> spare;
@@ -408,10 +418,11 @@ int drain_profile(sf_sketch* s) {
 unsigned grid_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
 // One schedule batch of cnt ops starting at keys/ops.
-template <int KB, int D>
-void launch_batch(sf_sketch* s, const uint8_t* keys, const uint8_t* ops, uint32_t uniform_del,
-                  uint32_t cnt, bool ins, bool del) {
+template <int KB, int D, int J>
+void launch_batch_j(sf_sketch* s, const uint8_t* keys, const uint8_t* ops, uint32_t uniform_del,
+                    uint32_t cnt, bool ins, bool del) {
     const dim3 grid(grid_for(cnt)), block(kBlock);
+    const dim3 tgrid(unsigned((uint64_t(cnt) + TileLDS<KB, J>::kOps - 1) / TileLDS<KB, J>::kOps));
     if (ins) {
         {
             Timed tm(s, s->stream, SF_K_SNAPSHOT, cnt);
@@ -420,23 +431,33 @@ void launch_batch(sf_sketch* s, const uint8_t* keys, const uint8_t* ops, uint32_
         }
         {
             Timed tm(s, s->stream, SF_K_FAT_ADD, cnt);
-            k_fat_update<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, 0u);
+            k_fat_update<KB, D, J><<<tgrid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, 0u);
         }
         {
             Timed tm(s, s->stream, SF_K_RAISE, cnt);
-            k_raise<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, s->slim,
-                                                           s->bpre, s->asnap, s->stride);
+            k_raise<KB, D, J><<<tgrid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat,
+                                                               s->slim, s->bpre, s->asnap, s->stride);
         }
     }
     if (del) {
         {
             Timed tm(s, s->stream, SF_K_FAT_SUB, cnt);
-            k_fat_update<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, 1u);
+            k_fat_update<KB, D, J><<<tgrid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, 1u);
         }
         {
             Timed tm(s, s->stream, SF_K_CLAMP, cnt);
-            k_clamp<KB, D><<<grid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, s->slim);
+            k_clamp<KB, D, J><<<tgrid, block, 0, s->stream>>>(keys, ops, uniform_del, cnt, s->g, s->fat, s->slim);
         }
+    }
+}
+
+template <int KB, int D>
+void launch_batch(sf_sketch* s, const uint8_t* keys, const uint8_t* ops, uint32_t uniform_del,
+                  uint32_t cnt, bool ins, bool del) {
+    switch (s->tile_j) {
+        case 1: launch_batch_j<KB, D, 1>(s, keys, ops, uniform_del, cnt, ins, del); break;
+        case 4: launch_batch_j<KB, D, 4>(s, keys, ops, uniform_del, cnt, ins, del); break;
+        default: launch_batch_j<KB, D, 8>(s, keys, ops, uniform_del, cnt, ins, del); break;
     }
 }
 
@@ -522,6 +543,7 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     s->g = geom_of(cfg);
     s->stream = static_cast<hipStream_t>(hip_stream);
     s->stride = cfg->batch_ops;
+    s->tile_j = 8;
     hipError_t e = hipGetDevice(&s->device);
     char* base = nullptr;
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&base), sz.total());
@@ -672,6 +694,14 @@ int sf_sync(sf_sketch* s) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
     hipError_t e = hipStreamSynchronize(s->stream);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_sync");
+}
+
+int sf_set_tile(sf_sketch* s, uint32_t tile_ops) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    if (tile_ops != 256 && tile_ops != 1024 && tile_ops != 2048)
+        return fail(SF_EINVAL, "tile_ops must be 256, 1024 or 2048");
+    s->tile_j = tile_ops / kBlock;
+    return SF_OK;
 }
 
 int sf_profile(sf_sketch* s, int enable) {

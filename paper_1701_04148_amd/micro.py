@@ -23,6 +23,12 @@ def lib():
         for n in ("micro_gather_u32", "micro_gather_16b"):
             getattr(L, n).restype = I
             getattr(L, n).argtypes = [P, U64, U64, U32, P, P]
+        L.micro_gather_pair.restype = I
+        L.micro_gather_pair.argtypes = [P, U64, U64, U32, U32, P, P]
+        L.micro_num_xcc.restype = I
+        L.micro_num_xcc.argtypes = []
+        L.micro_atomic_add_xcd.restype = I
+        L.micro_atomic_add_xcd.argtypes = [P, U64, U64, U32, U32, U32, P]
         L.micro_atomic_add_u32.restype = I
         L.micro_atomic_add_u32.argtypes = [P, U64, U64, U32, P]
         _lib = L
@@ -56,3 +62,17 @@ def gather_16b(table, n: int, seed: int, sink):
 def atomic_add_u32(table, n: int, seed: int):
     _ok(lib().micro_atomic_add_u32(table.data_ptr(), table.numel(), n, seed, _stream()),
         "micro_atomic_add_u32")
+
+
+def atomic_add_xcd(table, n: int, seed: int, nxcc: int, wg_scope: bool):
+    _ok(lib().micro_atomic_add_xcd(table.data_ptr(), table.numel(), n, seed, nxcc, int(wg_scope),
+                                   _stream()), "micro_atomic_add_xcd")
+
+
+def num_xcc() -> int:
+    return int(lib().micro_num_xcc())
+
+
+def gather_pair(table, n: int, seed: int, same_line: bool, sink):
+    _ok(lib().micro_gather_pair(table.data_ptr(), table.numel(), n, seed, int(same_line),
+                                sink.data_ptr(), _stream()), "micro_gather_pair")

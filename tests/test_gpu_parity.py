@@ -51,6 +51,26 @@ def test_small_batches_and_sequential(b):
         assert_same(fat, ref.fat(), "fat vs seq")
 
 
+@pytest.mark.parametrize("kb", [4, 13])
+def test_launch_shape_does_not_change_results(kb):
+    """Duplicate merging at tile sizes 256 / 1024 / 2048 ops gives identical state."""
+    import torch
+    wl = sfgen.make("tiles", d=4, w=2048, z=4, n_universe=5000, n_ops=200_000, s=1.3, p_del=0.15,
+                    key_bytes=kb, seed=11)
+    ref = oracle_run(4, 2048, 4, kb, wl.keys, wl.ops, wl.universe, 50_000)
+    for tile in (256, 1024, 2048):
+        say(f"[case] tile={tile} kb={kb}")
+        sk = sf.Sketch(4, 2048, 4, key_bytes=kb, batch_ops=50_000)
+        sk.set_tile(tile)
+        sk.update(dev_keys(wl.keys), torch.from_numpy(wl.ops).cuda())
+        q = sk.query(dev_keys(wl.universe)).cpu().numpy().view(np.uint32)
+        sk.sync()
+        assert_same(sk.export_fat(), ref[0], f"fat tile={tile}")
+        assert_same(sk.export_slim(), ref[1], f"slim tile={tile}")
+        assert_same(q, ref[2], f"query tile={tile}")
+        sk.close()
+
+
 def test_several_calls_start_new_batches():
     """Every update call starts a new schedule batch."""
     rng = np.random.default_rng(5)
