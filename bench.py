@@ -177,6 +177,195 @@ def micro_ceilings(torch, sizes_mib=(1, 16, 64, 256, 4096), n=1 << 26):
     return out
 
 
+def batch_for_width(w: int) -> int:
+    """Schedule batch size per sketch width: b = 16 w (capped at 2^20).  The oracle
+    measurements behind it: ARE drift of the batch schedule vs sequential stays
+    within 1.10x + 1e-3 up to b = 16 w on the 1M-insert workload (b = 64 w does not)."""
+    return int(min(16 * w, 1 << 20))
+
+
+def run_multi(args, torch, np, sf, sfgen):
+    """1024 sketches in one group (graph-captured rounds) vs one sketch per launch."""
+    t_gen = time.time()
+    m = sfgen.config_multi(seed=0, length_scale=1.0 / args.scale,
+                           workers=min(16, os.cpu_count() or 1))
+    n_ops, n_q = int(m.keys.size), int(m.queries.size)
+    log(f"[bench] workload {m.name}: {m.n} sketches, {n_ops} ops ({int(m.ops.sum())} deletes), "
+        f"{n_q} queries, generated in {time.time() - t_gen:.1f}s")
+    dev = torch.device("cuda:0")
+    keys = torch.from_numpy(m.keys.view(np.int32)).to(dev)
+    ops = torch.from_numpy(m.ops).to(dev)
+    qk = torch.from_numpy(m.queries.view(np.int32)).to(dev)
+    out = torch.empty(n_q, dtype=torch.int32, device=dev)
+    cfgs = [sf.make_config(m.d, int(m.w[i]), m.z, 4, 1, batch_for_width(int(m.w[i]))) for i in range(m.n)]
+    G = sf.SketchGroup(cfgs)
+    G.set_tile(args.tile)
+
+    def step():
+        G.reset()
+        G.update(keys, ops, m.seg)
+        G.query(qk, m.qseg, out)
+
+    for _ in range(args.warmup):
+        step()
+    G.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    G.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = el * 1e3 / args.steps
+    value = (n_ops + n_q) * args.steps / el / 1e6
+    sub, tiles = G.rounds()
+    log(f"[bench] group: {ms_step:.2f} ms/step, {value:.1f} M items/s ({sub} launch rounds, {tiles} tiles)")
+    # per-kernel times from one profiled (eager) pass
+    G.profile(True)
+    G.profile_read(reset=True)
+    step()
+    prof = G.profile_read(reset=True)
+    G.profile(False)
+    kernels = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]}
+    rows = []
+    for i in range(0, m.n, max(1, m.n // 8)):       # sanity: Fat row sums = net weight
+        k_i, o_i, _ = m.part(i)
+        net = int((o_i == 0).sum()) - int((o_i == 1).sum())
+        fat = G.export_fat(i)
+        rows.append(bool((fat.reshape(m.d, -1).astype(np.int64).sum(axis=1) == net).all()))
+    if not all(rows):
+        raise SystemExit("group Fat row sums differ from net stream weight")
+    group_answers = out.cpu().numpy().view(np.uint32).copy()
+    G.close()
+    del G
+    torch.cuda.empty_cache()
+
+    # the plain path: one Sketch per stream, its own launches, same kernels
+    lone = [sf.Sketch(c.d, c.w, c.z, batch_ops=c.batch_ops) for c in cfgs]
+    for s_ in lone:
+        s_.set_tile(args.tile)
+    seg, qseg = m.seg.astype(np.int64), m.qseg.astype(np.int64)
+
+    def lone_step():
+        for i, s_ in enumerate(lone):
+            s_.reset()
+            s_.update(keys[seg[i]:seg[i + 1]], ops[seg[i]:seg[i + 1]])
+            s_.query(qk[qseg[i]:qseg[i + 1]], out[qseg[i]:qseg[i + 1]])
+
+    lone_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lone_step()
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t0
+    lone_value = (n_ops + n_q) / el1 / 1e6
+    same = bool(np.array_equal(out.cpu().numpy().view(np.uint32), group_answers))
+    log(f"[bench] one sketch per launch: {el1 * 1e3:.2f} ms/step, {lone_value:.1f} M items/s; "
+        f"answers identical to the group: {same}")
+    for s_ in lone:
+        s_.close()
+    if not same:
+        raise SystemExit("group answers differ from the one-sketch-per-launch path")
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mitems/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{m.n} SF-sketches, d=4, Fat 2^14..2^20 u32 log-uniform (z=4), "
+                               "stream lengths lognormal median 200K in [10K, 4M], Zipf(1.1), 5% deletes; "
+                               "one graph-captured group update, then query every stream's universe",
+                   "sketches": m.n, "ops": n_ops, "queries": n_q, "batch_ops": "16 w per sketch",
+                   "tile_ops": args.tile, "launch_rounds": sub, "scale": args.scale},
+        "one_sketch_per_launch": {"value": round(lone_value, 2), "unit": "Mitems/s",
+                                  "ms_per_step": round(el1 * 1e3, 3)},
+        "group_vs_lone": round(value / lone_value, 2),
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        n_s = 0
+        c0 = time.perf_counter()
+        items = 0
+        while n_s < m.n and time.perf_counter() - c0 < 15.0:
+            k_i, o_i, q_i = m.part(n_s)
+            ref = oracle.Sketch(m.d, int(m.w[n_s]), m.z)
+            ref.batch(k_i, o_i, cfgs[n_s].batch_ops)
+            ans = ref.query(q_i)
+            if not np.array_equal(ans, group_answers[qseg[n_s]:qseg[n_s + 1]]):
+                raise SystemExit(f"sketch {n_s}: GPU answers differ from the oracle")
+            items += k_i.shape[0] + q_i.shape[0]
+            n_s += 1
+        c_el = time.perf_counter() - c0
+        result["cpu_baseline"] = {"value": round(items / c_el / 1e6, 3), "unit": "Mitems/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": f"first {n_s} of {m.n} sketches ({items} ops + queries), "
+                                            f"{c_el:.1f}s on 1 thread; their GPU answers bit-exact"}
+    return result
+
+
+SERVE_SHAPES = {
+    # per-stream sketch "as the 128M-packet flow configuration": d=8, Fat 8 x 2^23, Slim 8 x 2^21
+    "flows": dict(d=8, w=1 << 21, z=4),
+    # the many-sketch configuration's largest sketch: d=4, Fat 4 x 2^20, Slim 4 x 2^18
+    "small": dict(d=4, w=1 << 18, z=4),
+}
+
+
+def run_serve(args, torch, np, sf, sfgen):
+    """4096 streams of insert/delete/query requests through the continuous-batching loop."""
+    from paper_1701_04148_amd.serve import Server
+    t_gen = time.time()
+    w = sfgen.serving(seed=0, n_streams=4096 // args.scale, per_stream=16)
+    total_keys = sum(r.n for r in w.requests)
+    log(f"[bench] serving workload: {len(w.requests)} requests, {w.n_streams} streams, "
+        f"{total_keys} keys, generated in {time.time() - t_gen:.1f}s")
+    shape = SERVE_SHAPES[args.serve_shape]
+    cfg = sf.make_config(shape["d"], shape["w"], shape["z"], 4, 1, batch_for_width(shape["w"]))
+    budget = 64 << 30
+    pool = sf.SketchPool(cfg, hbm_budget_bytes=budget)
+    slots, _ = pool.capacity()
+    dev = torch.device("cuda:0")
+    keys = torch.from_numpy(w.pool.view(np.int32)).to(dev)
+    answers = torch.empty(1 << 20, dtype=torch.int32, device=dev)          # answers are discarded
+    sink = torch.empty(shape["d"] * shape["w"], dtype=torch.int16, device=dev)  # stands for the collector
+    srv = Server(pool, max_launch_keys=args.serve_launch_keys, max_in_flight=3)
+
+    def go(reqs, realtime):
+        return srv.run(reqs, key_of=lambda r: keys[r.off:r.off + r.n], out_of=lambda r: answers[:r.n],
+                       export_to=lambda st: sink, realtime=realtime)
+
+    warm = [r for r in w.requests if r.stream < 8]
+    go(warm, False)
+    pool.sync()
+    sat = go(w.requests, False)
+    pool.sync()
+    log(f"[bench] serving saturation: {sat.keys_per_s / 1e6:.1f} M keys/s, {sat.launches} launches, "
+        f"{sat.mean_requests_per_launch:.1f} requests/launch, peak resident {sat.peak_resident}/{slots}")
+    span = max(r.arrival for r in w.requests)
+    offered = total_keys / span
+    f = offered / (args.serve_load * sat.keys_per_s)
+    import copy
+    paced = [copy.copy(r) for r in w.requests]
+    for r in paced:
+        r.arrival *= f
+    res = go(paced, True)
+    pool.sync()
+    log(f"[bench] serving at {args.serve_load:.2f} x saturation: {res.keys_per_s / 1e6:.1f} M keys/s, "
+        f"latency {res.latency_ms}, queueing {res.queue_ms}")
+    pool.close()
+    return {"workload": f"{w.n_streams} streams x 16 requests (insert/delete/query 0.7/0.1/0.2, "
+                        "log-uniform 1K-1M uint32 keys, Zipf 1.0), per-stream sketch "
+                        f"d={shape['d']} Fat {shape['d']}x{shape['w'] * 4} u32, 64 GiB HBM budget "
+                        f"({slots} resident sketches)",
+            "saturation_mitems_s": round(sat.keys_per_s / 1e6, 2),
+            "offered_load": args.serve_load,
+            "value": round(res.keys_per_s / 1e6, 2), "unit": "Mitems/s",
+            "latency_ms": res.latency_ms, "queueing_ms": res.queue_ms,
+            "launches": res.launches, "requests_per_launch": round(res.mean_requests_per_launch, 2),
+            "peak_resident_sketches": res.peak_resident, "slots": slots}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +379,15 @@ def main():
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain copy of this many MiB (known traffic, for byte counters)")
+    ap.add_argument("--workload", choices=("main", "multi", "serve"), default="main",
+                    help="main: one sketch, 32M ops (plus the multi and serve summaries unless "
+                         "--no-multi / --no-serve); multi: 1024 sketches in one group; serve: the "
+                         "request loop alone")
+    ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-shape", choices=tuple(SERVE_SHAPES), default="flows")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / saturation")
+    ap.add_argument("--serve-launch-keys", type=int, default=1 << 24)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_traffic.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -213,6 +411,13 @@ def main():
 
     import paper_1701_04148_amd as sf
     import sfgen
+
+    if args.workload == "multi":
+        print(json.dumps(run_multi(args, torch, np, sf, sfgen)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args, torch, np, sf, sfgen)), flush=True)
+        return
 
     t_gen = time.time()
     wl = sfgen.config_main(args.skew, scale=args.scale)
@@ -336,6 +541,17 @@ def main():
             raise SystemExit("GPU query answers differ from the oracle at full size")
 
     sk.close()
+    del sk, keys, ops, qk, out
+    torch.cuda.empty_cache()
+    if not args.no_multi:
+        multi = run_multi(args, torch, np, sf, sfgen)
+        result["sketches_1024"] = {k: multi[k] for k in ("value", "unit", "ms_per_step", "config",
+                                                         "one_sketch_per_launch", "group_vs_lone")}
+        if "cpu_baseline" in multi:
+            result["sketches_1024"]["cpu_baseline"] = multi["cpu_baseline"]
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        result["serving"] = run_serve(args, torch, np, sf, sfgen)
     print(json.dumps(result), flush=True)
 
 

@@ -159,6 +159,95 @@ typedef struct sf_kernel_stats {
 int sf_profile(sf_sketch *sk, int enable);
 int sf_profile_read(sf_sketch *sk, sf_kernel_stats *out, int reset);
 
+/* ---- sketch groups -----------------------------------------------------
+ * Many independent sketches (e.g. one per monitoring node, Section 1) kept
+ * in one allocation and updated by the same launches.  cfgs[i] gives sketch
+ * i's shape and schedule (d, w, z, seed_base and batch_ops may differ;
+ * key_bytes must be equal).  Every sketch cuts ITS OWN ops into batches of
+ * its own batch_ops, so its state is exactly what sf_create + sf_update on
+ * the same ops would give.  Round k runs batch k of every sketch;
+ * round_ops (0 = min(sum of batch_ops, 2^26), at least the largest
+ * batch_ops) bounds the ops one launch covers and sizes the snapshot
+ * scratch.  Update calls are recorded into a hipGraph and replayed when the
+ * next call has the same segments, buffers and op kind (sf_group_set_graph
+ * turns this off).  If hip_stream is NULL the group creates its own
+ * (blocking) stream, because graphs cannot be captured on the null stream.
+ *
+ * Keys of an update or query call are the concatenation of every sketch's
+ * keys, sketch 0 first; seg is a HOST array of n+1 offsets (seg[0] = 0,
+ * non-decreasing, seg[n] = total keys): sketch i owns keys [seg[i], seg[i+1]).
+ * Query answers go to out in the same order. */
+typedef struct sf_group sf_group;
+
+uint64_t sf_group_footprint(uint32_t n, const sf_config *cfgs, uint64_t round_ops);
+int sf_group_create(uint32_t n, const sf_config *cfgs, uint64_t round_ops, uint64_t hbm_budget_bytes,
+                    void *hip_stream, sf_group **out);
+int sf_group_destroy(sf_group *g);
+int sf_group_reset(sf_group *g);
+int sf_group_insert(sf_group *g, const void *keys, const uint64_t *seg);
+int sf_group_delete(sf_group *g, const void *keys, const uint64_t *seg);
+int sf_group_update(sf_group *g, const void *keys, const uint8_t *ops, const uint64_t *seg);
+int sf_group_query(sf_group *g, const void *keys, const uint64_t *seg, uint32_t *out);
+int sf_group_export_slim(sf_group *g, uint32_t i, uint16_t *out, uint64_t out_elems);
+int sf_group_export_fat(sf_group *g, uint32_t i, uint32_t *out, uint64_t out_elems);
+int sf_group_sync(sf_group *g);
+int sf_group_set_graph(sf_group *g, int enable);
+int sf_group_set_tile(sf_group *g, uint32_t tile_ops);
+/* Sub-rounds (launch groups) and tiles of the last update call's plan. */
+int sf_group_rounds(sf_group *g, uint64_t *subrounds, uint64_t *tiles);
+int sf_group_profile(sf_group *g, int enable);
+int sf_group_profile_read(sf_group *g, sf_kernel_stats *out, int reset);
+
+
+
+/* ---- sketch pools: the device side of a serving loop -------------------
+ * A pool holds sketches of ONE shape (cfg) in slots of one allocation.  The
+ * number of slots is max_slots, or what hbm_budget_bytes holds after the
+ * shared buffers (snapshot scratch for round_ops ops -- 0 = 2^24, at least
+ * batch_ops -- export staging and an in-flight descriptor ring); both given:
+ * the smaller.  A monitoring node's stream acquires a slot when admitted
+ * (the slot is zeroed: Section 3.1 initialisation) and releases it when it
+ * closes.  sf_pool_launch runs requests of many slots together, AT MOST ONE
+ * PER SLOT: each update request is cut into batch_ops batches exactly like
+ * one sf_insert / sf_delete / sf_update call on a lone sketch (its own batch
+ * boundaries), so a slot ends in the same state alone or in any mix; query
+ * requests see their slot after every earlier launch.  Launches run in order
+ * on the pool's stream (NULL: the pool creates a blocking stream) and return
+ * a ticket; sf_pool_done / sf_pool_wait report completion.  Request buffers
+ * must stay valid until their ticket is done. */
+typedef struct sf_pool sf_pool;
+
+enum sf_request_kind { SF_REQ_INSERT = 0, SF_REQ_DELETE = 1, SF_REQ_UPDATE = 2, SF_REQ_QUERY = 3 };
+
+typedef struct sf_request {
+    const void *keys;   /* device: n keys */
+    const uint8_t *ops; /* device: n op codes, 0 insert / 1 delete (SF_REQ_UPDATE only) */
+    uint32_t *out;      /* device: n answers (SF_REQ_QUERY only) */
+    uint64_t n;
+    uint32_t slot;      /* an acquired slot */
+    uint32_t kind;      /* sf_request_kind */
+} sf_request;
+
+/* Device bytes one slot takes (Fat + Slim working copy + table entry). */
+uint64_t sf_pool_slot_bytes(const sf_config *cfg);
+int sf_pool_create(const sf_config *cfg, uint32_t max_slots, uint64_t round_ops, uint64_t hbm_budget_bytes,
+                   void *hip_stream, sf_pool **out);
+int sf_pool_destroy(sf_pool *p);
+int sf_pool_capacity(sf_pool *p, uint32_t *slots, uint32_t *free_slots);
+/* SF_ENOMEM when every slot is taken (admission control). */
+int sf_pool_acquire(sf_pool *p, uint32_t *slot);
+int sf_pool_release(sf_pool *p, uint32_t slot);
+int sf_pool_launch(sf_pool *p, const sf_request *reqs, uint32_t n, uint64_t *ticket);
+/* 1 when the ticket's launch has completed, 0 while pending, < 0 on error. */
+int sf_pool_done(sf_pool *p, uint64_t ticket);
+int sf_pool_wait(sf_pool *p, uint64_t ticket);
+/* Slim of a slot as uint16 [d][w]; async != 0 (device destination only)
+ * enqueues the copy on the pool stream without waiting. */
+int sf_pool_export_slim(sf_pool *p, uint32_t slot, uint16_t *out, uint64_t out_elems, int async);
+int sf_pool_export_fat(sf_pool *p, uint32_t slot, uint32_t *out, uint64_t out_elems);
+int sf_pool_sync(sf_pool *p);
+int sf_pool_set_tile(sf_pool *p, uint32_t tile_ops);
+
 /* Static text of a status code. */
 const char *sf_strerror(int status);
 

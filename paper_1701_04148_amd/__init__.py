@@ -62,6 +62,35 @@ SIGNATURES = {
     "sf_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_profile": (_I, [_P, _I]),
     "sf_profile_read": (_I, [_P, ctypes.POINTER(sf_kernel_stats), _I]),
+    "sf_group_footprint": (_U64, [ctypes.c_uint32, _CFG, _U64]),
+    "sf_group_create": (_I, [ctypes.c_uint32, _CFG, _U64, _U64, _P, ctypes.POINTER(_P)]),
+    "sf_group_destroy": (_I, [_P]),
+    "sf_group_reset": (_I, [_P]),
+    "sf_group_insert": (_I, [_P, _P, _P]),
+    "sf_group_delete": (_I, [_P, _P, _P]),
+    "sf_group_update": (_I, [_P, _P, _P, _P]),
+    "sf_group_query": (_I, [_P, _P, _P, _P]),
+    "sf_group_export_slim": (_I, [_P, ctypes.c_uint32, _P, _U64]),
+    "sf_group_export_fat": (_I, [_P, ctypes.c_uint32, _P, _U64]),
+    "sf_group_sync": (_I, [_P]),
+    "sf_group_set_graph": (_I, [_P, _I]),
+    "sf_group_set_tile": (_I, [_P, ctypes.c_uint32]),
+    "sf_group_rounds": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "sf_group_profile": (_I, [_P, _I]),
+    "sf_group_profile_read": (_I, [_P, ctypes.POINTER(sf_kernel_stats), _I]),
+    "sf_pool_slot_bytes": (_U64, [_CFG]),
+    "sf_pool_create": (_I, [_CFG, ctypes.c_uint32, _U64, _U64, _P, ctypes.POINTER(_P)]),
+    "sf_pool_destroy": (_I, [_P]),
+    "sf_pool_capacity": (_I, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+    "sf_pool_acquire": (_I, [_P, ctypes.POINTER(ctypes.c_uint32)]),
+    "sf_pool_release": (_I, [_P, ctypes.c_uint32]),
+    "sf_pool_launch": (_I, [_P, _P, ctypes.c_uint32, ctypes.POINTER(_U64)]),
+    "sf_pool_done": (_I, [_P, _U64]),
+    "sf_pool_wait": (_I, [_P, _U64]),
+    "sf_pool_export_slim": (_I, [_P, ctypes.c_uint32, _P, _U64, _I]),
+    "sf_pool_export_fat": (_I, [_P, ctypes.c_uint32, _P, _U64]),
+    "sf_pool_sync": (_I, [_P]),
+    "sf_pool_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_strerror": (ctypes.c_char_p, [_I]),
     "sf_last_error": (ctypes.c_char_p, []),
 }
@@ -286,3 +315,238 @@ class Sketch:
 
     def sync(self):
         sf_sync(self._h)
+
+
+# ---------------------------------------------------------------- sketch groups
+
+def _cfg_array(cfgs):
+    arr = (sf_config * len(cfgs))()
+    for i, c in enumerate(cfgs):
+        arr[i] = c if isinstance(c, sf_config) else make_config(**c)
+    return arr
+
+
+def _seg_array(seg, n):
+    import numpy as np
+    a = np.ascontiguousarray(seg, dtype=np.uint64)
+    if a.shape != (n + 1,):
+        raise ValueError(f"seg must have n+1 = {n + 1} offsets")
+    return a
+
+
+def sf_group_footprint(cfgs, round_ops: int = 0) -> int:
+    arr = _cfg_array(cfgs)
+    return int(lib().sf_group_footprint(len(cfgs), arr, round_ops))
+
+
+class SketchGroup:
+    """Many independent sketches updated and queried by the same launches.
+
+    cfgs: one sf_config (or dict of make_config arguments) per sketch.  Keys of a
+    call are every sketch's keys concatenated; seg (n+1 host offsets) marks
+    where each sketch's keys start.  Each sketch follows its own batch schedule,
+    so its state equals a lone Sketch fed the same ops.
+    """
+
+    def __init__(self, cfgs, round_ops: int = 0, hbm_budget_bytes: int = 0, stream=None):
+        self._arr = _cfg_array(cfgs)
+        self.n = len(cfgs)
+        self.cfgs = [self._arr[i] for i in range(self.n)]
+        self.key_bytes = self.cfgs[0].key_bytes
+        h = ctypes.c_void_p()
+        _check(lib().sf_group_create(self.n, self._arr, round_ops, hbm_budget_bytes,
+                                     _stream_handle(stream), ctypes.byref(h)), "sf_group_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().sf_group_destroy(self._h), "sf_group_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ops_ptr(self, ops, n):
+        import torch
+        if not (isinstance(ops, torch.Tensor) and ops.is_cuda and ops.dtype == torch.uint8
+                and ops.is_contiguous() and ops.numel() == n):
+            raise TypeError("ops must be a contiguous GPU uint8 tensor with one entry per key")
+        return ops.data_ptr()
+
+    def insert(self, keys, seg):
+        p, n = _keys_ptr(keys, self.key_bytes)
+        sg = _seg_array(seg, self.n)
+        _check(lib().sf_group_insert(self._h, p, sg.ctypes.data), "sf_group_insert")
+
+    def delete(self, keys, seg):
+        p, n = _keys_ptr(keys, self.key_bytes)
+        sg = _seg_array(seg, self.n)
+        _check(lib().sf_group_delete(self._h, p, sg.ctypes.data), "sf_group_delete")
+
+    def update(self, keys, ops, seg):
+        p, n = _keys_ptr(keys, self.key_bytes)
+        sg = _seg_array(seg, self.n)
+        _check(lib().sf_group_update(self._h, p, self._ops_ptr(ops, n), sg.ctypes.data),
+               "sf_group_update")
+
+    def query(self, keys, seg, out=None):
+        import torch
+        p, n = _keys_ptr(keys, self.key_bytes)
+        sg = _seg_array(seg, self.n)
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=keys.device)
+        if out.numel() < n or out.element_size() != 4 or not out.is_cuda:
+            raise ValueError("out must be a GPU 4-byte tensor with one element per key")
+        _check(lib().sf_group_query(self._h, p, sg.ctypes.data, out.data_ptr()), "sf_group_query")
+        return out
+
+    def export_slim(self, i: int, out=None):
+        import numpy as np
+        c = self.cfgs[i]
+        if out is None:
+            out = np.empty((c.d, c.w), dtype=np.uint16)
+        ptr, cnt = (out.ctypes.data, out.size) if hasattr(out, "ctypes") else (out.data_ptr(), out.numel())
+        _check(lib().sf_group_export_slim(self._h, i, ptr, cnt), "sf_group_export_slim")
+        return out
+
+    def export_fat(self, i: int, out=None):
+        import numpy as np
+        c = self.cfgs[i]
+        if out is None:
+            out = np.empty((c.d, c.w, c.z), dtype=np.uint32)
+        ptr, cnt = (out.ctypes.data, out.size) if hasattr(out, "ctypes") else (out.data_ptr(), out.numel())
+        _check(lib().sf_group_export_fat(self._h, i, ptr, cnt), "sf_group_export_fat")
+        return out
+
+    def reset(self):
+        _check(lib().sf_group_reset(self._h), "sf_group_reset")
+
+    def sync(self):
+        _check(lib().sf_group_sync(self._h), "sf_group_sync")
+
+    def set_graph(self, enable: bool):
+        _check(lib().sf_group_set_graph(self._h, int(bool(enable))), "sf_group_set_graph")
+
+    def set_tile(self, tile_ops: int):
+        _check(lib().sf_group_set_tile(self._h, tile_ops), "sf_group_set_tile")
+
+    def rounds(self):
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sf_group_rounds(self._h, ctypes.byref(a), ctypes.byref(b)), "sf_group_rounds")
+        return int(a.value), int(b.value)
+
+    def profile(self, enable: bool = True):
+        _check(lib().sf_group_profile(self._h, int(bool(enable))), "sf_group_profile")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        st = sf_kernel_stats()
+        _check(lib().sf_group_profile_read(self._h, ctypes.byref(st), int(bool(reset))),
+               "sf_group_profile_read")
+        return {k: (st.ms[i], int(st.launches[i]), int(st.items[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+# ---------------------------------------------------------------- sketch pools (serving)
+
+SF_REQ_INSERT, SF_REQ_DELETE, SF_REQ_UPDATE, SF_REQ_QUERY = 0, 1, 2, 3
+
+
+class sf_request(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("ops", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("slot", ctypes.c_uint32), ("kind", ctypes.c_uint32)]
+
+
+def sf_pool_slot_bytes(cfg: sf_config) -> int:
+    return int(lib().sf_pool_slot_bytes(ctypes.byref(cfg)))
+
+
+class SketchPool:
+    """Slots of one sketch shape under an HBM budget, launched request by request.
+
+    launch() takes a list of (slot, kind, keys, ops, out) with at most one
+    request per slot; it returns a ticket, and done()/wait() report completion.
+    """
+
+    def __init__(self, cfg: sf_config, max_slots: int = 0, round_ops: int = 0,
+                 hbm_budget_bytes: int = 0, stream=None):
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        _check(lib().sf_pool_create(ctypes.byref(cfg), max_slots, round_ops, hbm_budget_bytes,
+                                    _stream_handle(stream), ctypes.byref(h)), "sf_pool_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().sf_pool_destroy(self._h), "sf_pool_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def capacity(self):
+        a, b = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().sf_pool_capacity(self._h, ctypes.byref(a), ctypes.byref(b)), "sf_pool_capacity")
+        return int(a.value), int(b.value)
+
+    def acquire(self):
+        """A zeroed slot, or None when the budget holds no free slot."""
+        s = ctypes.c_uint32()
+        rc = lib().sf_pool_acquire(self._h, ctypes.byref(s))
+        if rc == SF_ENOMEM:
+            return None
+        _check(rc, "sf_pool_acquire")
+        return int(s.value)
+
+    def release(self, slot: int):
+        _check(lib().sf_pool_release(self._h, slot), "sf_pool_release")
+
+    def launch(self, reqs) -> int:
+        """reqs: iterable of (slot, kind, keys_tensor, ops_tensor_or_None, out_tensor_or_None)."""
+        reqs = list(reqs)
+        arr = (sf_request * max(1, len(reqs)))()
+        kb = self.cfg.key_bytes
+        for i, (slot, kind, keys, ops, out) in enumerate(reqs):
+            p, n = _keys_ptr(keys, kb)
+            arr[i] = sf_request(p, ops.data_ptr() if ops is not None else None,
+                                out.data_ptr() if out is not None else None, n, slot, kind)
+        t = ctypes.c_uint64()
+        _check(lib().sf_pool_launch(self._h, arr, len(reqs), ctypes.byref(t)), "sf_pool_launch")
+        return int(t.value)
+
+    def done(self, ticket: int) -> bool:
+        rc = lib().sf_pool_done(self._h, ticket)
+        if rc < 0:
+            _check(rc, "sf_pool_done")
+        return rc == 1
+
+    def wait(self, ticket: int):
+        _check(lib().sf_pool_wait(self._h, ticket), "sf_pool_wait")
+
+    def export_slim(self, slot: int, out=None, asynchronous: bool = False):
+        import numpy as np
+        c = self.cfg
+        if out is None:
+            out = np.empty((c.d, c.w), dtype=np.uint16)
+        ptr, cnt = (out.ctypes.data, out.size) if hasattr(out, "ctypes") else (out.data_ptr(), out.numel())
+        _check(lib().sf_pool_export_slim(self._h, slot, ptr, cnt, int(asynchronous)), "sf_pool_export_slim")
+        return out
+
+    def export_fat(self, slot: int, out=None):
+        import numpy as np
+        c = self.cfg
+        if out is None:
+            out = np.empty((c.d, c.w, c.z), dtype=np.uint32)
+        ptr, cnt = (out.ctypes.data, out.size) if hasattr(out, "ctypes") else (out.data_ptr(), out.numel())
+        _check(lib().sf_pool_export_fat(self._h, slot, ptr, cnt), "sf_pool_export_fat")
+        return out
+
+    def sync(self):
+        _check(lib().sf_pool_sync(self._h), "sf_pool_sync")
+
+    def set_tile(self, tile_ops: int):
+        _check(lib().sf_pool_set_tile(self._h, tile_ops), "sf_pool_set_tile")

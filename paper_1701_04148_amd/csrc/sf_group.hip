@@ -1,0 +1,521 @@
+// libsf.so: sketch groups -- many independent SF-sketches (one per monitoring
+// node, each with its own stream of ops) updated and queried together.
+//
+// Every sketch keeps its own schedule: its ops are cut into batches of its
+// own batch_ops, exactly as a single sketch would cut them, so a group gives
+// each sketch the same state it would reach alone.  Round k runs batch k of
+// every sketch that has one.  Sketches are independent, so a round may be
+// split into sub-rounds (each sketch's batch whole inside one) to bound the
+// snapshot scratch; sub-round order does not matter.  Each sub-round is one
+// launch of each schedule step over a device table of tiles (ListPlan); a
+// whole update call can be captured into one hipGraph and replayed.
+//
+// Device memory (one allocation): all Fat arrays, all Slim working copies,
+// the sketch table, export staging (largest sketch), the snapshot scratch
+// ([d_max][round_ops] uint32 + uint16), and a growable tile table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "sf.h"
+#include "sf_host.hpp"
+
+using namespace sfk;
+using namespace sfh;
+
+struct sf_group {
+    uint32_t n;
+    uint32_t key_bytes;
+    uint32_t d_max;
+    uint32_t d_uniform;  // common d, or 0 when the sketches differ
+    std::vector<sf_config> cfg;
+    std::vector<SketchDesc> desc;  // host copy of the sketch table
+    hipStream_t stream;
+    bool own_stream;               // created here: graphs cannot capture the null stream
+    char* base;                    // the one allocation
+    uint64_t state_bytes;          // Fat + Slim region (zeroed by reset)
+    SketchDesc* d_desc;
+    uint16_t* stage;
+    uint32_t* bpre;
+    uint16_t* asnap;
+    uint64_t round_ops;            // snapshot capacity in ops
+    uint32_t tile_j;
+    bool use_graph;
+    // tile table (device, growable) and its pinned host staging
+    TileDesc* d_tiles = nullptr;
+    size_t tiles_cap = 0;
+    TileDesc* h_tiles = nullptr;
+    size_t h_cap = 0;
+    // the last update call's plan and its captured graph
+    std::vector<TileDesc> plan;
+    std::vector<std::pair<uint32_t, uint32_t>> subrounds;  // (first tile, tiles)
+    uint32_t plan_kind = 0;
+    bool plan_on_device = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // query tiles (device, growable)
+    TileDesc* d_qtiles = nullptr;
+    size_t qtiles_cap = 0;
+    Profiler prof;
+};
+
+namespace {
+
+std::mutex g_mu;
+std::unordered_set<const sf_group*> g_live;
+
+bool live(const sf_group* g) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g && g_live.count(g);
+}
+
+struct Layout {
+    std::vector<uint64_t> fat_off, slim_off;
+    uint64_t state, desc, stage, bpre, asnap, total;
+    uint64_t round_ops;
+    uint32_t d_max;
+};
+
+int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) {
+    if (n == 0 || !cfgs) return fail(SF_EINVAL, "a group needs at least one sketch config");
+    uint64_t off = 0, max_b = 0, max_cells = 0;
+    L.d_max = 0;
+    L.fat_off.resize(n);
+    L.slim_off.resize(n);
+    for (uint32_t i = 0; i < n; i++) {
+        int rc = validate(&cfgs[i]);
+        if (rc) return fail(rc, "sketch " + std::to_string(i) + ": " + last_error());
+        if (cfgs[i].key_bytes != cfgs[0].key_bytes) return fail(SF_EINVAL, "key_bytes must match across a group");
+        const uint64_t cells = uint64_t(cfgs[i].d) * cfgs[i].w;
+        L.fat_off[i] = off;
+        off += round256(cells * cfgs[i].z * 4);
+        max_b = std::max<uint64_t>(max_b, cfgs[i].batch_ops);
+        max_cells = std::max(max_cells, cells);
+        L.d_max = std::max(L.d_max, cfgs[i].d);
+    }
+    for (uint32_t i = 0; i < n; i++) {
+        L.slim_off[i] = off;
+        off += round256(uint64_t(cfgs[i].d) * cfgs[i].w * 4);
+    }
+    L.state = off;
+    if (round_ops == 0) {
+        uint64_t sum_b = 0;
+        for (uint32_t i = 0; i < n; i++) sum_b += cfgs[i].batch_ops;
+        round_ops = std::min<uint64_t>(sum_b, 1ull << 26);
+    }
+    L.round_ops = std::max(round_ops, max_b);
+    if (L.round_ops > (1ull << 31)) return fail(SF_EINVAL, "round_ops must be <= 2^31");
+    L.desc = off;
+    off += round256(uint64_t(n) * sizeof(SketchDesc));
+    L.stage = off;
+    off += round256(max_cells * 2);
+    L.bpre = off;
+    off += round256(uint64_t(L.d_max) * L.round_ops * 4);
+    L.asnap = off;
+    off += round256(uint64_t(L.d_max) * L.round_ops * 2);
+    L.total = off;
+    return SF_OK;
+}
+
+int ensure_device_tiles(TileDesc*& buf, size_t& cap, size_t need) {
+    if (need <= cap) return SF_OK;
+    size_t ncap = std::max<size_t>(need, cap * 2 + 1024);
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&buf), ncap * sizeof(TileDesc));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        buf = nullptr;
+        return e == hipErrorOutOfMemory ? fail(SF_ENOMEM, "tile table") : device_fail(e, "tile table");
+    }
+    cap = ncap;
+    return SF_OK;
+}
+
+int upload_tiles(sf_group* g, TileDesc* dst, const std::vector<TileDesc>& src) {
+    if (src.empty()) return SF_OK;
+    if (g->h_cap < src.size()) {
+        if (g->h_tiles) (void)hipHostFree(g->h_tiles);
+        g->h_tiles = nullptr;
+        g->h_cap = 0;
+        hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&g->h_tiles), src.size() * sizeof(TileDesc),
+                                     hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return device_fail(e, "pinned tile staging");
+        }
+        g->h_cap = src.size();
+    }
+    std::memcpy(g->h_tiles, src.data(), src.size() * sizeof(TileDesc));
+    hipError_t e = hipMemcpyAsync(dst, g->h_tiles, src.size() * sizeof(TileDesc), hipMemcpyHostToDevice,
+                                  g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);  // staging reused by the next call
+    return e == hipSuccess ? SF_OK : device_fail(e, "tile upload");
+}
+
+int check_segments(const sf_group* g, const uint64_t* seg) {
+    if (!seg) return fail(SF_EINVAL, "seg is null");
+    if (seg[0] != 0) return fail(SF_EINVAL, "seg[0] must be 0");
+    for (uint32_t i = 0; i < g->n; i++)
+        if (seg[i + 1] < seg[i]) return fail(SF_EINVAL, "seg must be non-decreasing");
+    return SF_OK;
+}
+
+// Cut every sketch's ops into its own batches; round k = batch k of every
+// sketch; rounds split into sub-rounds of at most round_ops ops.
+void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uint8_t* ops, uint32_t mode) {
+    g->plan.clear();
+    g->subrounds.clear();
+    const uint32_t tile_ops = uint32_t(kBlock) * g->tile_j;
+    uint64_t rounds = 0;
+    for (uint32_t s = 0; s < g->n; s++) {
+        const uint64_t len = seg[s + 1] - seg[s], b = g->cfg[s].batch_ops;
+        rounds = std::max(rounds, (len + b - 1) / b);
+    }
+    for (uint64_t k = 0; k < rounds; k++) {
+        uint64_t used = 0;
+        uint32_t first = uint32_t(g->plan.size());
+        for (uint32_t s = 0; s < g->n; s++) {
+            const uint64_t b = g->cfg[s].batch_ops;
+            const uint64_t lo = seg[s] + k * b;
+            if (lo >= seg[s + 1]) continue;
+            const uint64_t cnt = std::min(b, seg[s + 1] - lo);
+            if (used + cnt > g->round_ops) {  // close the sub-round
+                g->subrounds.emplace_back(first, uint32_t(g->plan.size()) - first);
+                first = uint32_t(g->plan.size());
+                used = 0;
+            }
+            for (uint64_t off = 0; off < cnt; off += tile_ops) {
+                TileDesc t{};
+                t.keys = keys + (lo + off) * g->key_bytes;
+                t.ops = mode == kOpsArray ? ops + lo + off : nullptr;
+                t.count = uint32_t(std::min<uint64_t>(tile_ops, cnt - off));
+                t.sketch = s;
+                t.scr = uint32_t(used + off);
+                t.mode = mode;
+                g->plan.push_back(t);
+            }
+            used += cnt;
+        }
+        if (uint32_t(g->plan.size()) > first) g->subrounds.emplace_back(first, uint32_t(g->plan.size()) - first);
+    }
+}
+
+template <int KB>
+void launch_plan(sf_group* g, bool ins, bool del, Profiler* prof) {
+    for (auto& sr : g->subrounds) {
+        const ListPlan<KB> plan{g->d_tiles + sr.first, g->d_desc};
+        uint64_t items = 0;
+        if (prof)
+            for (uint32_t t = 0; t < sr.second; t++) items += g->plan[sr.first + t].count;
+        Steps<ListPlan>::by_rows<KB>(g->d_uniform, g->tile_j, plan, sr.second, ins, del, g->bpre, g->asnap,
+                                    uint32_t(g->round_ops), g->stream, prof, items);
+    }
+}
+
+void drop_graph(sf_group* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->exec = nullptr;
+    g->graph = nullptr;
+}
+
+enum Kind : uint32_t { kInsert = 1, kDelete = 2, kMixed = 3 };
+
+int group_updates(sf_group* g, const void* keys, const uint8_t* ops, const uint64_t* seg, Kind kind) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    int rc = check_segments(g, seg);
+    if (rc) return rc;
+    const uint64_t n = seg[g->n];
+    if (n == 0) return SF_OK;
+    const uint32_t kb = g->key_bytes;
+    if (kb == 4 && (reinterpret_cast<uintptr_t>(keys) & 3u))
+        return fail(SF_EINVAL, "uint32 keys must be 4-byte aligned");
+    if ((rc = check_gpu_ptr(keys, n * kb, "keys"))) return rc;
+    if (kind == kMixed && (rc = check_gpu_ptr(ops, n, "ops"))) return rc;
+
+    // Same plan as the previous call (same segments, buffers and op kind)?
+    const uint32_t mode = kind == kMixed ? kOpsArray : kind == kDelete ? kAllDelete : kAllInsert;
+    std::vector<TileDesc> old;
+    old.swap(g->plan);
+    build_plan(g, seg, static_cast<const uint8_t*>(keys), ops, mode);
+    const bool same = g->plan_on_device && old.size() == g->plan.size() && g->plan_kind == kind &&
+                      std::memcmp(old.data(), g->plan.data(), old.size() * sizeof(TileDesc)) == 0;
+    const bool profiling = g->prof.on;
+    if (!same) {
+        drop_graph(g);
+        hipError_t e = hipStreamSynchronize(g->stream);  // the old table may still be in use
+        if (e != hipSuccess) return device_fail(e, "group sync");
+        if ((rc = ensure_device_tiles(g->d_tiles, g->tiles_cap, g->plan.size()))) return rc;
+        if ((rc = upload_tiles(g, g->d_tiles, g->plan))) return rc;
+        g->plan_kind = kind;
+        g->plan_on_device = true;
+    }
+    const bool ins = kind != kDelete, del = kind != kInsert;
+    auto launch_all = [&](Profiler* prof) {
+        if (kb == 4) launch_plan<4>(g, ins, del, prof);
+        else launch_plan<13>(g, ins, del, prof);
+    };
+    if (!g->use_graph || profiling) {
+        launch_all(profiling ? &g->prof : nullptr);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? SF_OK : device_fail(e, "group update launch");
+    }
+    if (!g->exec) {
+        hipError_t e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return device_fail(e, "graph capture begin");
+        launch_all(nullptr);
+        e = hipStreamEndCapture(g->stream, &g->graph);
+        if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            drop_graph(g);
+            return device_fail(e, "graph capture");
+        }
+    }
+    hipError_t e = hipGraphLaunch(g->exec, g->stream);
+    return e == hipSuccess ? SF_OK : device_fail(e, "graph launch");
+}
+
+template <int KB, typename S>
+void launch_group_query(sf_group* g, unsigned tiles) {
+    const ListPlan<KB> plan{g->d_qtiles, g->d_desc};
+    launch_query_rows<KB, ListPlan<KB>, S>(g->d_uniform, plan, tiles, g->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t sf_group_footprint(uint32_t n, const sf_config* cfgs, uint64_t round_ops) {
+    Layout L;
+    if (layout_of(n, cfgs, round_ops, L)) return 0;
+    return L.total;
+}
+
+int sf_group_create(uint32_t n, const sf_config* cfgs, uint64_t round_ops, uint64_t hbm_budget_bytes,
+                    void* hip_stream, sf_group** out) {
+    if (!out) return fail(SF_EINVAL, "null output handle");
+    Layout L;
+    int rc = layout_of(n, cfgs, round_ops, L);
+    if (rc) return rc;
+    if (hbm_budget_bytes && L.total > hbm_budget_bytes)
+        return fail(SF_ENOMEM, "group needs " + std::to_string(L.total) + " bytes, budget is " +
+                                   std::to_string(hbm_budget_bytes));
+    sf_group* g = new sf_group{};
+    g->n = n;
+    g->key_bytes = cfgs[0].key_bytes;
+    g->d_max = L.d_max;
+    g->d_uniform = cfgs[0].d;
+    for (uint32_t i = 1; i < n; i++)
+        if (cfgs[i].d != cfgs[0].d) g->d_uniform = 0;
+    g->cfg.assign(cfgs, cfgs + n);
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    if (!g->stream) {
+        hipError_t se = hipStreamCreate(&g->stream);  // default priority, blocking w.r.t. the null stream
+        if (se != hipSuccess) {
+            (void)hipGetLastError();
+            delete g;
+            return device_fail(se, "sf_group_create stream");
+        }
+        g->own_stream = true;
+    }
+    g->round_ops = L.round_ops;
+    g->tile_j = 8;
+    g->use_graph = true;
+    g->state_bytes = L.state;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->base), L.total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (g->own_stream) (void)hipStreamDestroy(g->stream);
+        delete g;
+        return e == hipErrorOutOfMemory ? fail(SF_ENOMEM, "hipMalloc: out of device memory")
+                                        : device_fail(e, "sf_group_create");
+    }
+    g->desc.resize(n);
+    for (uint32_t i = 0; i < n; i++) {
+        g->desc[i].g = geom_of(&cfgs[i]);
+        g->desc[i].fat = reinterpret_cast<uint32_t*>(g->base + L.fat_off[i]);
+        g->desc[i].slim = reinterpret_cast<uint32_t*>(g->base + L.slim_off[i]);
+    }
+    g->d_desc = reinterpret_cast<SketchDesc*>(g->base + L.desc);
+    g->stage = reinterpret_cast<uint16_t*>(g->base + L.stage);
+    g->bpre = reinterpret_cast<uint32_t*>(g->base + L.bpre);
+    g->asnap = reinterpret_cast<uint16_t*>(g->base + L.asnap);
+    e = hipMemcpy(g->d_desc, g->desc.data(), n * sizeof(SketchDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemsetAsync(g->base, 0, L.state, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(g->base);
+        if (g->own_stream) (void)hipStreamDestroy(g->stream);
+        delete g;
+        return device_fail(e, "sf_group_create init");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(g);
+    }
+    *out = g;
+    return SF_OK;
+}
+
+int sf_group_destroy(sf_group* g) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g || !g_live.erase(g)) return fail(SF_ESTATE, "group handle is not live");
+    }
+    hipError_t e = hipStreamSynchronize(g->stream);
+    drop_graph(g);
+    if (g->d_tiles) (void)hipFree(g->d_tiles);
+    if (g->d_qtiles) (void)hipFree(g->d_qtiles);
+    if (g->h_tiles) (void)hipHostFree(g->h_tiles);
+    hipError_t e2 = hipFree(g->base);
+    if (g->own_stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+    if (e != hipSuccess) return device_fail(e, "sf_group_destroy sync");
+    if (e2 != hipSuccess) return device_fail(e2, "sf_group_destroy free");
+    return SF_OK;
+}
+
+int sf_group_reset(sf_group* g) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    hipError_t e = hipMemsetAsync(g->base, 0, g->state_bytes, g->stream);
+    return e == hipSuccess ? SF_OK : device_fail(e, "sf_group_reset");
+}
+
+int sf_group_insert(sf_group* g, const void* keys, const uint64_t* seg) {
+    return group_updates(g, keys, nullptr, seg, kInsert);
+}
+
+int sf_group_delete(sf_group* g, const void* keys, const uint64_t* seg) {
+    return group_updates(g, keys, nullptr, seg, kDelete);
+}
+
+int sf_group_update(sf_group* g, const void* keys, const uint8_t* ops, const uint64_t* seg) {
+    return group_updates(g, keys, ops, seg, kMixed);
+}
+
+int sf_group_query(sf_group* g, const void* keys, const uint64_t* seg, uint32_t* out) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    int rc = check_segments(g, seg);
+    if (rc) return rc;
+    const uint64_t n = seg[g->n];
+    if (n == 0) return SF_OK;
+    const uint32_t kb = g->key_bytes;
+    if (kb == 4 && (reinterpret_cast<uintptr_t>(keys) & 3u))
+        return fail(SF_EINVAL, "uint32 keys must be 4-byte aligned");
+    if (reinterpret_cast<uintptr_t>(out) & 3u) return fail(SF_EINVAL, "out must be 4-byte aligned");
+    if ((rc = check_gpu_ptr(keys, n * kb, "keys"))) return rc;
+    if ((rc = check_gpu_ptr(out, n * 4, "out"))) return rc;
+    std::vector<TileDesc> tiles;
+    const uint8_t* k8 = static_cast<const uint8_t*>(keys);
+    for (uint32_t s = 0; s < g->n; s++)
+        for (uint64_t lo = seg[s]; lo < seg[s + 1]; lo += kBlock) {
+            TileDesc t{};
+            t.keys = k8 + lo * kb;
+            t.out = out + lo;
+            t.count = uint32_t(std::min<uint64_t>(kBlock, seg[s + 1] - lo));
+            t.sketch = s;
+            t.mode = kAllInsert;
+            tiles.push_back(t);
+        }
+    hipError_t e = hipStreamSynchronize(g->stream);  // previous query table may be in use
+    if (e != hipSuccess) return device_fail(e, "group sync");
+    if ((rc = ensure_device_tiles(g->d_qtiles, g->qtiles_cap, tiles.size()))) return rc;
+    if ((rc = upload_tiles(g, g->d_qtiles, tiles))) return rc;
+    {
+        Timed tm(&g->prof, g->stream, SF_K_QUERY, n);
+        if (kb == 4) launch_group_query<4, uint32_t>(g, unsigned(tiles.size()));
+        else launch_group_query<13, uint32_t>(g, unsigned(tiles.size()));
+    }
+    e = hipGetLastError();
+    return e == hipSuccess ? SF_OK : device_fail(e, "group query launch");
+}
+
+int sf_group_export_slim(sf_group* g, uint32_t i, uint16_t* out, uint64_t out_elems) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    if (i >= g->n) return fail(SF_EINVAL, "sketch index out of range");
+    const uint64_t cells = uint64_t(g->cfg[i].d) * g->cfg[i].w;
+    if (!out) return fail(SF_EINVAL, "out is null");
+    if (out_elems < cells) return fail(SF_EINVAL, "out_elems < d*w");
+    const bool host = host_dest(out);
+    if (!host) {
+        int rc = check_gpu_ptr(out, cells * 2, "out");
+        if (rc) return rc;
+    }
+    uint16_t* dst = host ? g->stage : out;
+    const unsigned grid = blocks_for(cells, kBlock) < 4096u ? blocks_for(cells, kBlock) : 4096u;
+    k_pack16<uint32_t><<<dim3(grid), dim3(kBlock), 0, g->stream>>>(g->desc[i].slim, dst, cells);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && host) e = hipMemcpyAsync(out, g->stage, cells * 2, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    return e == hipSuccess ? SF_OK : device_fail(e, "sf_group_export_slim");
+}
+
+int sf_group_export_fat(sf_group* g, uint32_t i, uint32_t* out, uint64_t out_elems) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    if (i >= g->n) return fail(SF_EINVAL, "sketch index out of range");
+    const uint64_t n = uint64_t(g->cfg[i].d) * g->cfg[i].w * g->cfg[i].z;
+    if (!out) return fail(SF_EINVAL, "out is null");
+    if (out_elems < n) return fail(SF_EINVAL, "out_elems < d*w*z");
+    if (!host_dest(out)) {
+        int rc = check_gpu_ptr(out, n * 4, "out");
+        if (rc) return rc;
+    }
+    hipError_t e = hipMemcpyAsync(out, g->desc[i].fat, n * 4, hipMemcpyDefault, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    return e == hipSuccess ? SF_OK : device_fail(e, "sf_group_export_fat");
+}
+
+int sf_group_sync(sf_group* g) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    hipError_t e = hipStreamSynchronize(g->stream);
+    return e == hipSuccess ? SF_OK : device_fail(e, "sf_group_sync");
+}
+
+int sf_group_set_graph(sf_group* g, int enable) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    g->use_graph = enable != 0;
+    return SF_OK;
+}
+
+int sf_group_set_tile(sf_group* g, uint32_t tile_ops) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    if (tile_ops != 256 && tile_ops != 1024 && tile_ops != 2048)
+        return fail(SF_EINVAL, "tile_ops must be 256, 1024 or 2048");
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return device_fail(e, "group sync");
+    g->tile_j = tile_ops / kBlock;
+    drop_graph(g);
+    g->plan_on_device = false;
+    return SF_OK;
+}
+
+int sf_group_rounds(sf_group* g, uint64_t* subrounds, uint64_t* tiles) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    if (subrounds) *subrounds = g->subrounds.size();
+    if (tiles) *tiles = g->plan.size();
+    return SF_OK;
+}
+
+int sf_group_profile(sf_group* g, int enable) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    g->prof.on = enable != 0;
+    return SF_OK;
+}
+
+int sf_group_profile_read(sf_group* g, sf_kernel_stats* out, int reset) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    int rc = g->prof.drain();
+    if (out) *out = g->prof.acc;
+    if (reset) g->prof.acc = sf_kernel_stats{};
+    return rc;
+}
+
+}  // extern "C"

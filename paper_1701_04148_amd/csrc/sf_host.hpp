@@ -1,0 +1,232 @@
+// Host-side helpers shared by the single-sketch and sketch-group entry
+// points: error reporting, config validation, pointer checks, geometry,
+// launch dispatch and per-kernel event timing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "sf.h"
+#include "sf_kernels.hpp"
+
+namespace sfh {
+
+using namespace sfk;
+
+std::string& last_error();  // thread-local detail string (defined in sf_lib.hip)
+
+inline int fail(int code, const std::string& msg) {
+    last_error() = msg;
+    return code;
+}
+
+inline int device_fail(hipError_t e, const char* what) {
+    return fail(SF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr uint64_t kMaxBatch = 1ull << 30;
+constexpr uint32_t kMaxLaunch = 1u << 30;  // ops per kernel launch (uint32 indexing)
+
+inline bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+inline int validate(const sf_config* c) {
+    if (!c) return fail(SF_EINVAL, "null config");
+    if (c->d < 1 || c->d > uint32_t(kMaxD)) return fail(SF_EINVAL, "d must be in 1..16");
+    if (c->w < 1 || c->z < 1) return fail(SF_EINVAL, "w and z must be >= 1");
+    if (uint64_t(c->w) * c->z > (1ull << 32)) return fail(SF_EINVAL, "w*z must be <= 2^32");
+    if (c->key_bytes != 4 && c->key_bytes != 13) return fail(SF_EINVAL, "key_bytes must be 4 or 13");
+    if (c->batch_ops < 1 || c->batch_ops > kMaxBatch) return fail(SF_EINVAL, "batch_ops must be in 1..2^30");
+    return SF_OK;
+}
+
+inline uint64_t round256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+inline Geom geom_of(const sf_config* c) {
+    Geom g{};
+    g.d = c->d;
+    g.w = c->w;
+    g.z = c->z;
+    g.seed_base = c->seed_base;
+    const uint64_t wz = uint64_t(c->w) * c->z;
+    g.wz32 = uint32_t(wz);  // 2^32 wraps to 0
+    g.pow2 = is_pow2(c->w) && is_pow2(c->z);
+    if (g.pow2) {
+        g.w_mask = c->w - 1;
+        g.wz_mask = uint32_t(wz - 1);
+        g.w_shift = uint32_t(__builtin_ctzll(c->w));
+    }
+    return g;
+}
+
+// A pointer the GPU may read or write: device memory (checked to hold
+// `bytes` from p on) or pinned host memory.  Rejects pageable host memory,
+// which a kernel cannot touch.
+inline int check_gpu_ptr(const void* p, uint64_t bytes, const char* what) {
+    if (!p) return fail(SF_EINVAL, std::string(what) + " is null");
+    hipPointerAttribute_t at{};
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SF_EINVAL, std::string(what) + " is not GPU-accessible memory");
+    }
+    if (at.type == hipMemoryTypeDevice) {
+        void* base = nullptr;
+        size_t size = 0;
+        if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && base) {
+            const uint64_t off = uint64_t(static_cast<const char*>(p) - static_cast<const char*>(base));
+            if (off + bytes > size)
+                return fail(SF_EINVAL, std::string(what) + " buffer is smaller than the requested size");
+        } else {
+            (void)hipGetLastError();
+        }
+        return SF_OK;
+    }
+    if (at.type == hipMemoryTypeHost || at.isManaged) return SF_OK;
+    return fail(SF_EINVAL, std::string(what) + " is not GPU-accessible memory");
+}
+
+inline bool host_dest(void* p) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return at.type != hipMemoryTypeDevice && !at.isManaged;
+}
+
+inline unsigned blocks_for(uint64_t n, uint32_t per_block) { return unsigned((n + per_block - 1) / per_block); }
+
+// ---------------------------------------------------------------- timing
+// Brackets launches with HIP events on the launching stream when enabled.
+struct Profiler {
+    struct Rec {
+        int kind;
+        uint64_t items;
+        hipEvent_t a, b;
+    };
+    bool on = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare;
+    sf_kernel_stats acc{};
+
+    hipEvent_t take() {
+        hipEvent_t e = nullptr;
+        if (!spare.empty()) {
+            e = spare.back();
+            spare.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
+
+    int drain() {
+        hipError_t err = hipSuccess;
+        for (auto& r : recs) {
+            float ms = 0.f;
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+            if (e != hipSuccess && err == hipSuccess) err = e;
+            acc.ms[r.kind] += ms;
+            acc.launches[r.kind] += 1;
+            acc.items[r.kind] += r.items;
+            spare.push_back(r.a);
+            spare.push_back(r.b);
+        }
+        recs.clear();
+        return err == hipSuccess ? SF_OK : device_fail(err, "profile events");
+    }
+
+    ~Profiler() {
+        for (auto& r : recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : spare) (void)hipEventDestroy(e);
+    }
+};
+
+struct Timed {
+    Profiler* p;
+    hipStream_t st;
+    Profiler::Rec r;
+    Timed(Profiler* prof, hipStream_t stream, int kind, uint64_t items)
+        : p(prof && prof->on ? prof : nullptr), st(stream), r{kind, items, nullptr, nullptr} {
+        if (!p) return;
+        r.a = p->take();
+        r.b = p->take();
+        if (r.a) (void)hipEventRecord(r.a, st);
+    }
+    ~Timed() {
+        if (!p || !r.a || !r.b) return;
+        (void)hipEventRecord(r.b, st);
+        p->recs.push_back(r);
+    }
+};
+
+// ---------------------------------------------------------------- launches
+// The five steps of one schedule batch (or round of a group) over plan P.
+template <int KB, int D, int J, class P>
+void launch_steps(const P& plan, unsigned tiles, bool ins, bool del, uint32_t* bpre, uint16_t* asnap,
+                  uint32_t stride, hipStream_t st, Profiler* prof, uint64_t items) {
+    const dim3 grid(tiles), block(kBlock);
+    if (ins) {
+        {
+            Timed tm(prof, st, SF_K_SNAPSHOT, items);
+            k_snapshot<KB, D, J, P><<<grid, block, 0, st>>>(plan, bpre, asnap, stride);
+        }
+        {
+            Timed tm(prof, st, SF_K_FAT_ADD, items);
+            k_fat_update<KB, D, J, P><<<grid, block, 0, st>>>(plan, 0u);
+        }
+        {
+            Timed tm(prof, st, SF_K_RAISE, items);
+            k_raise<KB, D, J, P><<<grid, block, 0, st>>>(plan, bpre, asnap, stride);
+        }
+    }
+    if (del) {
+        {
+            Timed tm(prof, st, SF_K_FAT_SUB, items);
+            k_fat_update<KB, D, J, P><<<grid, block, 0, st>>>(plan, 1u);
+        }
+        {
+            Timed tm(prof, st, SF_K_CLAMP, items);
+            k_clamp<KB, D, J, P><<<grid, block, 0, st>>>(plan);
+        }
+    }
+}
+
+// Dispatch of (key width, rows, tile) to kernel instantiations.
+template <template <int> class PT>
+struct Steps {
+    template <int KB, int D>
+    static void by_tile(uint32_t j, const PT<KB>& plan, unsigned tiles, bool ins, bool del, uint32_t* bpre,
+                        uint16_t* asnap, uint32_t stride, hipStream_t st, Profiler* prof, uint64_t items) {
+        switch (j) {
+            case 1: launch_steps<KB, D, 1>(plan, tiles, ins, del, bpre, asnap, stride, st, prof, items); break;
+            case 4: launch_steps<KB, D, 4>(plan, tiles, ins, del, bpre, asnap, stride, st, prof, items); break;
+            default: launch_steps<KB, D, 8>(plan, tiles, ins, del, bpre, asnap, stride, st, prof, items); break;
+        }
+    }
+    template <int KB>
+    static void by_rows(uint32_t d, uint32_t j, const PT<KB>& plan, unsigned tiles, bool ins, bool del,
+                        uint32_t* bpre, uint16_t* asnap, uint32_t stride, hipStream_t st, Profiler* prof,
+                        uint64_t items) {
+        if (d == 4) by_tile<KB, 4>(j, plan, tiles, ins, del, bpre, asnap, stride, st, prof, items);
+        else if (d == 8) by_tile<KB, 8>(j, plan, tiles, ins, del, bpre, asnap, stride, st, prof, items);
+        else by_tile<KB, 0>(j, plan, tiles, ins, del, bpre, asnap, stride, st, prof, items);
+    }
+};
+
+template <int KB, class P, typename S>
+void launch_query_rows(uint32_t d, const P& plan, unsigned tiles, hipStream_t st) {
+    const dim3 grid(tiles), block(kBlock);
+    if (d == 4) k_query<KB, 4, S, P><<<grid, block, 0, st>>>(plan);
+    else if (d == 8) k_query<KB, 8, S, P><<<grid, block, 0, st>>>(plan);
+    else k_query<KB, 0, S, P><<<grid, block, 0, st>>>(plan);
+}
+
+}  // namespace sfh

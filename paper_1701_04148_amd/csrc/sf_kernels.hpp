@@ -1,0 +1,272 @@
+// SF-sketch kernels (gfx950).  Every kernel takes a work plan that tells each
+// workgroup which tile of ops (or query keys) it owns and in which sketch:
+//   UniformPlan  one sketch, one schedule batch, tile = blockIdx (no table)
+//   ListPlan     a device table of tiles over many sketches (sketch groups)
+// The step each kernel implements is the same in both cases.
+//
+// One schedule batch (the sf.h update schedule):
+//   k_snapshot   S1  insert ops: Slim and Fat counters before the batch
+//   k_fat_update S2  insert ops: Fat += count, one atomic per distinct key of the tile
+//   k_raise      S3  insert ops: T = min(m0 + delta, max(m0, Bmin), 65535),
+//                    atomic max into the Slim where T exceeds the snapshot
+//   k_fat_update S4  delete ops: Fat -= count
+//   k_clamp      S5  delete ops: atomic min of the Slim with the bucket max
+// Kernel boundaries are the schedule's grid-wide barriers.
+#pragma once
+
+#include "sf_device.hpp"
+
+namespace sfk {
+
+// How the ops of a tile are typed.
+enum OpMode : uint32_t { kOpsArray = 0, kAllInsert = 1, kAllDelete = 2 };
+
+// What one workgroup processes.
+struct Work {
+    const uint8_t* keys;  // first key of the tile
+    const uint8_t* ops;   // first op code of the tile (kOpsArray only)
+    uint32_t* out;        // first query answer of the tile (queries only)
+    uint32_t count;       // ops (or query keys) in the tile
+    uint32_t scr;         // snapshot index of the tile's first op
+    uint32_t mode;        // OpMode
+    Geom g;
+    uint32_t* fat;
+    void* slim;           // uint32 working copy (updates) or uint16 export (collector queries)
+};
+
+template <int KB> struct UniformPlan {
+    const uint8_t* keys;
+    const uint8_t* ops;
+    uint32_t* out;
+    uint32_t cnt;
+    uint32_t mode;
+    Geom g;
+    uint32_t* fat;
+    void* slim;
+    __device__ __forceinline__ Work at(uint32_t blk, uint32_t tile_ops) const {
+        const uint32_t first = blk * tile_ops;
+        const uint32_t rest = cnt - first;
+        return Work{keys + size_t(first) * KB, ops ? ops + first : nullptr, out ? out + first : nullptr,
+                    rest < tile_ops ? rest : tile_ops, first, mode, g, fat, slim};
+    }
+};
+
+struct TileDesc {         // one tile of a ListPlan
+    const uint8_t* keys;  // its first key
+    const uint8_t* ops;   // its first op code (kOpsArray), else null
+    uint32_t* out;        // its first answer (queries), else null
+    uint32_t count;       // ops or keys in the tile
+    uint32_t sketch;      // index into the sketch table
+    uint32_t scr;         // snapshot index of its first op (within the launch round)
+    uint32_t mode;        // OpMode
+};
+
+struct SketchDesc {       // one sketch of a group or pool
+    Geom g;
+    uint32_t* fat;
+    uint32_t* slim;
+};
+
+template <int KB> struct ListPlan {
+    const TileDesc* tiles;
+    const SketchDesc* sketches;
+    __device__ __forceinline__ Work at(uint32_t blk, uint32_t) const {
+        const TileDesc t = tiles[blk];
+        const SketchDesc s = sketches[t.sketch];
+        return Work{t.keys, t.ops, t.out, t.count, t.scr, t.mode, s.g, s.fat, s.slim};
+    }
+};
+
+__device__ __forceinline__ bool is_delete(const uint8_t* ops, uint32_t t, uint32_t mode) {
+    return mode == kOpsArray ? ops[t] != 0 : mode == kAllDelete;
+}
+
+#define SF_ROWS(D, g) (D ? uint32_t(D) : (g).d)
+
+// S1: snapshot of each insert op's Slim and Fat counters (state before the batch).
+template <int KB, int D, int J, class P>
+__global__ __launch_bounds__(kBlock) void k_snapshot(P plan, uint32_t* __restrict__ bpre,
+                                                     uint16_t* __restrict__ asnap, uint32_t stride) {
+    const Work w = plan.at(blockIdx.x, kBlock * J);
+    const uint32_t* slim = static_cast<const uint32_t*>(w.slim);
+    const uint32_t d = SF_ROWS(D, w.g);
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const uint32_t t = uint32_t(j) * kBlock + threadIdx.x;
+        if (t >= w.count || is_delete(w.ops, t, w.mode)) continue;
+        const Mixed<KB> mx(load_key<KB>(w.keys, t));
+        const size_t s = size_t(w.scr) + t;
+#pragma unroll
+        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+            if (i < d) {
+                uint32_t h, f;
+                split(w.g, mx.row(w.g.seed_base + i), h, f);
+                const size_t cell = size_t(i) * w.g.w + h;
+                asnap[size_t(i) * stride + s] = uint16_t(slim[cell]);
+                bpre[size_t(i) * stride + s] = w.fat[cell * w.g.z + f];
+            }
+        }
+    }
+}
+
+// Loads the tile's active ops (op type == want_del) into the LDS table.
+// Returns after a barrier; the table then holds each distinct key once.
+template <int KB, int J>
+__device__ __forceinline__ void tile_build(TileLDS<KB, J>& L, const Work& w, bool want_del) {
+    tile_clear<KB, J>(L);
+    Key<KB> k[J];
+    bool act[J];
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
+        act[j] = idx < w.count && is_delete(w.ops, idx, w.mode) == want_del;
+        if (act[j]) {
+            k[j] = load_key<KB>(w.keys, idx);
+            L.key[idx] = k[j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; j++)
+        if (act[j]) tile_insert<KB, J>(L, k[j], uint32_t(j) * kBlock + threadIdx.x);
+    __syncthreads();
+}
+
+// S2 / S4: Fat counters of every insert (want_del = 0) or delete (want_del = 1)
+// op move by one: one atomic per distinct key of the tile, carrying its count.
+template <int KB, int D, int J, class P>
+__global__ __launch_bounds__(kBlock) void k_fat_update(P plan, uint32_t want_del) {
+    __shared__ TileLDS<KB, J> L;
+    const Work w = plan.at(blockIdx.x, kBlock * J);
+    tile_build<KB, J>(L, w, want_del != 0);
+    const uint32_t d = SF_ROWS(D, w.g);
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
+        const uint32_t o = L.owner[s];
+        if (o == kEmpty) continue;
+        const uint32_t n = L.cnt[s];
+        const uint32_t v = want_del ? 0u - n : n;
+        const Mixed<KB> mx(L.key[o]);
+#pragma unroll
+        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+            if (i < d) {
+                uint32_t h, f;
+                split(w.g, mx.row(w.g.seed_base + i), h, f);
+                atomic_add_u32(&w.fat[(size_t(i) * w.g.w + h) * w.g.z + f], v);
+            }
+        }
+    }
+}
+
+// S3: raise the Slim counters of every inserted key to its water level
+// T = min(m0 + delta, max(m0, Bmin), 65535), once per distinct key of the tile.
+template <int KB, int D, int J, class P>
+__global__ __launch_bounds__(kBlock) void k_raise(P plan, const uint32_t* __restrict__ bpre,
+                                                  const uint16_t* __restrict__ asnap, uint32_t stride) {
+    constexpr int R = D ? D : kMaxD;
+    __shared__ TileLDS<KB, J> L;
+    const Work w = plan.at(blockIdx.x, kBlock * J);
+    tile_build<KB, J>(L, w, false);
+    uint32_t* slim = static_cast<uint32_t*>(w.slim);
+    const uint32_t d = SF_ROWS(D, w.g);
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
+        const uint32_t o = L.owner[s];
+        if (o == kEmpty) continue;
+        const size_t t = size_t(w.scr) + o;  // any op of the key: all share one snapshot
+        const Mixed<KB> mx(L.key[o]);
+        size_t cell[R];
+        uint32_t a[R];
+        uint32_t m0 = ~0u, bmin = ~0u, delta = ~0u;
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            cell[i] = 0;
+            a[i] = kSlimMax;
+            if (uint32_t(i) < d) {
+                uint32_t h, f;
+                split(w.g, mx.row(w.g.seed_base + i), h, f);
+                cell[i] = size_t(i) * w.g.w + h;
+                a[i] = asnap[size_t(i) * stride + t];
+                const uint32_t post = w.fat[cell[i] * w.g.z + f];
+                const uint32_t grew = post - bpre[size_t(i) * stride + t];
+                m0 = min(m0, a[i]);
+                bmin = min(bmin, post);
+                delta = min(delta, grew);
+            }
+        }
+        const uint64_t rise = uint64_t(m0) + delta;
+        const uint64_t level = m0 > bmin ? m0 : bmin;
+        const uint64_t tt = rise < level ? rise : level;
+        const uint32_t T = uint32_t(tt < kSlimMax ? tt : kSlimMax);
+#pragma unroll
+        for (int i = 0; i < R; i++)
+            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&slim[cell[i]], T);
+    }
+}
+
+// Largest counter of a Fat bucket.
+__device__ __forceinline__ uint32_t bucket_max(const uint32_t* __restrict__ fat, size_t cell,
+                                               const Geom& g) {
+    if (g.z == 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(fat + cell * 4);
+        return max(max(v.x, v.y), max(v.z, v.w));
+    }
+    uint32_t m = 0;
+    for (uint32_t j = 0; j < g.z; j++) m = max(m, fat[cell * g.z + j]);
+    return m;
+}
+
+// S5: clamp the Slim counters of every deleted key to their bucket's max,
+// once per distinct key of the tile.
+template <int KB, int D, int J, class P>
+__global__ __launch_bounds__(kBlock) void k_clamp(P plan) {
+    __shared__ TileLDS<KB, J> L;
+    const Work w = plan.at(blockIdx.x, kBlock * J);
+    tile_build<KB, J>(L, w, true);
+    uint32_t* slim = static_cast<uint32_t*>(w.slim);
+    const uint32_t d = SF_ROWS(D, w.g);
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
+        const uint32_t o = L.owner[s];
+        if (o == kEmpty) continue;
+        const Mixed<KB> mx(L.key[o]);
+#pragma unroll
+        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+            if (i < d) {
+                uint32_t h, f;
+                split(w.g, mx.row(w.g.seed_base + i), h, f);
+                const size_t cell = size_t(i) * w.g.w + h;
+                const uint32_t m = bucket_max(w.fat, cell, w.g);
+                if (slim[cell] > m) atomic_min_u32(&slim[cell], m);
+            }
+        }
+    }
+}
+
+// Point query: minimum of the d Slim counters of each key (one key per lane).
+template <int KB, int D, typename S, class P>
+__global__ __launch_bounds__(kBlock) void k_query(P plan) {
+    const Work w = plan.at(blockIdx.x, kBlock);
+    const uint32_t t = threadIdx.x;
+    if (t >= w.count) return;
+    const S* slim = static_cast<const S*>(w.slim);
+    const Mixed<KB> mx(load_key<KB>(w.keys, t));
+    const uint32_t d = SF_ROWS(D, w.g);
+    uint32_t q = ~0u;
+#pragma unroll
+    for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+        if (i < d) {
+            uint32_t h, f;
+            split(w.g, mx.row(w.g.seed_base + i), h, f);
+            q = min(q, uint32_t(slim[size_t(i) * w.g.w + h]));
+        }
+    }
+    w.out[t] = q;
+}
+
+// Narrowing copy of a 32-bit Slim working copy into the uint16 export form.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pack16(const T* __restrict__ in, uint16_t* __restrict__ out,
+                                                   size_t n) {
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock)
+        out[i] = uint16_t(in[i]);
+}
+
+}  // namespace sfk

@@ -65,16 +65,22 @@ def rngs(seed: int, k: int = 4):
     return [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(k)]
 
 
-def zipf_ranks(rng: np.random.Generator, n: int, s: float, size: int) -> np.ndarray:
-    """0-based ranks with P(r) proportional to (r+1)^-s, by inverse CDF."""
+def zipf_ranks(rng: np.random.Generator, n: int, s: float, size: int,
+               threaded: bool = True) -> np.ndarray:
+    """0-based ranks with P(r) proportional to (r+1)^-s, by inverse CDF.
+    threaded: use torch's multi-threaded CPU searchsorted (same indices)."""
     w = np.arange(1, n + 1, dtype=np.float64) ** (-float(s))
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
     u = rng.random(size)
-    try:  # torch's CPU searchsorted is multi-threaded and gives the same indices
-        import torch
-        r = torch.searchsorted(torch.from_numpy(cdf), torch.from_numpy(u), right=True).numpy()
-    except Exception:  # pragma: no cover
+    r = None
+    if threaded:
+        try:
+            import torch
+            r = torch.searchsorted(torch.from_numpy(cdf), torch.from_numpy(u), right=True).numpy()
+        except Exception:  # pragma: no cover
+            r = None
+    if r is None:
         r = np.searchsorted(cdf, u, side="right")
     return np.minimum(r, n - 1).astype(np.int64)
 
@@ -222,3 +228,150 @@ def config_flows(seed: int = 0, scale: int = 1) -> Workload:
                 d=8, w=2**21 // scale, z=4, n_universe=4_000_000 // scale,
                 n_ops=128_000_000 // scale, s=1.2, key_bytes=13, seed=seed,
                 n_absent=12_000_000 // scale)
+
+
+@dataclass
+class MultiWorkload:
+    """Many sketches' inputs, concatenated sketch by sketch.
+
+    keys / ops / queries hold every sketch's arrays back to back; seg and qseg
+    (n+1 offsets) mark where sketch i's ops and queries start.  w[i] is sketch
+    i's Slim width (Fat width = 4 w[i])."""
+    name: str
+    d: int
+    z: int
+    w: np.ndarray
+    keys: np.ndarray
+    ops: np.ndarray
+    seg: np.ndarray
+    queries: np.ndarray
+    qseg: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.w.shape[0])
+
+    def part(self, i: int):
+        lo, hi = int(self.seg[i]), int(self.seg[i + 1])
+        qlo, qhi = int(self.qseg[i]), int(self.qseg[i + 1])
+        return self.keys[lo:hi], self.ops[lo:hi], self.queries[qlo:qhi]
+
+
+def _multi_sketch(args):
+    """One sketch's (keys, ops, queries) of the many-sketch recipe."""
+    child, L, s, p_del = args
+    g_uni, g_rank, g_del, _ = [np.random.default_rng(c) for c in child.spawn(4)]
+    n_uni = max(1, -(-L // 10))
+    uni = universe_u32(g_uni, n_uni)
+    k, o = turnstile(uni[zipf_ranks(g_rank, n_uni, s, L, threaded=False)], g_del, p_del)
+    return k, o, uni
+
+
+def config_multi(seed: int = 0, n_sketches: int = 1024, length_scale: float = 1.0,
+                 d: int = 4, fat_log2=(14, 20), median: float = 200_000.0, sigma: float = 1.0,
+                 len_range=(10_000, 4_000_000), s: float = 1.1, p_del: float = 0.05,
+                 workers: int = 1) -> MultiWorkload:
+    """1024 independent sketches (one per monitoring node): Fat width 2^14..2^20
+    uint32 log-uniform per sketch (Slim width a quarter of it, z = 4); stream
+    length lognormal (median 200K, sigma 1.0) clipped to [10K, 4M]; universe of
+    ceil(length / 10) distinct uint32 keys per stream; Zipf(1.1); 5% deletions
+    of live occurrences; queries = each stream's universe.  length_scale
+    shrinks every stream (tests).  workers > 1 draws sketches in that many
+    freshly started worker processes (same result)."""
+    top = np.random.SeedSequence(seed)
+    g_shape = np.random.default_rng(top.spawn(1)[0])
+    e_fat = g_shape.integers(fat_log2[0], fat_log2[1] + 1, size=n_sketches)
+    lens = np.exp(np.log(median) + sigma * g_shape.standard_normal(n_sketches))
+    lens = np.clip(np.round(lens), len_range[0], len_range[1])
+    lens = np.maximum(1, np.round(lens * length_scale)).astype(np.int64)
+    w = (2 ** (e_fat - 2)).astype(np.int64)
+    children = np.random.SeedSequence(seed + 1).spawn(n_sketches)
+    jobs = [(children[i], int(lens[i]), s, p_del) for i in range(n_sketches)]
+    if workers > 1:
+        import multiprocessing as mp
+        _native()  # build / load the helper once, before forking
+        with mp.get_context("spawn").Pool(workers) as pool:
+            parts = pool.map(_multi_sketch, jobs, chunksize=max(1, n_sketches // (4 * workers)))
+    else:
+        parts = [_multi_sketch(j) for j in jobs]
+    seg = np.zeros(n_sketches + 1, dtype=np.uint64)
+    qseg = np.zeros(n_sketches + 1, dtype=np.uint64)
+    seg[1:] = np.cumsum([p[0].shape[0] for p in parts])
+    qseg[1:] = np.cumsum([p[2].shape[0] for p in parts])
+    return MultiWorkload(f"multi{n_sketches}_d{d}_fat2^{fat_log2[0]}-2^{fat_log2[1]}_lognormal",
+                         d, 4, w, np.concatenate([p[0] for p in parts]),
+                         np.concatenate([p[1] for p in parts]), seg,
+                         np.concatenate([p[2] for p in parts]), qseg,
+                         dict(seed=seed, s=s, p_del=p_del, median=median, sigma=sigma,
+                              length_scale=length_scale))
+
+
+@dataclass
+class ServeRequest:
+    """One request of the serving workload: keys are pool[off : off + n]."""
+    stream: int
+    seq: int          # position in the stream's request order
+    kind: int         # 0 insert, 1 delete, 3 query (the sf_request kinds)
+    off: int
+    n: int
+    arrival: float    # seconds after the start
+    last: bool        # the stream closes after this request
+
+
+@dataclass
+class ServeWorkload:
+    pool: np.ndarray                # uint32 key pool every request slices
+    requests: list                  # ServeRequest, sorted by arrival
+    n_streams: int
+    meta: dict = field(default_factory=dict)
+
+
+def serving(seed: int = 0, n_streams: int = 4096, per_stream: int = 16, mix=(0.7, 0.1, 0.2),
+            size_range=(1_000, 1_000_000), pool_keys: int = 1 << 26, universe: int = 1_000_000,
+            s: float = 1.0, open_window: float = 1.0, stream_rate: float = 16.0) -> ServeWorkload:
+    """Request stream of the serving loop.
+
+    Every stream opens at a uniform time in [0, open_window) seconds and then
+    issues per_stream requests with exponential gaps (Poisson, stream_rate
+    requests/s); its last request closes it.  Kinds insert / delete / query
+    with probabilities mix (a delete with nothing live becomes an insert);
+    sizes log-uniform in size_range.  Keys come from one pool of pool_keys
+    Zipf(s) draws over a universe of distinct uint32: an insert or query takes
+    a random slice of the pool; a delete takes a suffix of the stream's most
+    recent insert that still has undeleted keys, so deletions never exceed
+    insertions (strict turnstile).  Scale offered load with open_window and
+    stream_rate."""
+    g_uni, g_rank, g_req, g_arr = rngs(seed)
+    uni = universe_u32(g_uni, universe)
+    pool = uni[zipf_ranks(g_rank, universe, s, pool_keys)]
+    lo, hi = np.log(size_range[0]), np.log(size_range[1])
+    reqs = []
+    for st in range(n_streams):
+        t = float(g_arr.random() * open_window)
+        live = []  # [off, remaining] of this stream's inserts
+        for q in range(per_stream):
+            t += float(g_arr.exponential(1.0 / stream_rate))
+            n = int(round(np.exp(lo + (hi - lo) * g_req.random())))
+            u = g_req.random()
+            kind = 0 if u < mix[0] else (1 if u < mix[0] + mix[1] else 3)
+            if kind == 1:
+                while live and live[-1][1] == 0:
+                    live.pop()
+                if not live:
+                    kind = 0
+            if kind == 1:
+                ins = live[-1]
+                n = min(n, ins[1])
+                ins[1] -= n
+                off = ins[0] + ins[1]            # suffix of the insert's slice
+            else:
+                off = int(g_req.integers(0, pool_keys - n + 1))
+                if kind == 0:
+                    live.append([off, n])
+            reqs.append(ServeRequest(st, q, kind, off, n, t, q == per_stream - 1))
+    reqs.sort(key=lambda r: (r.arrival, r.stream, r.seq))
+    return ServeWorkload(pool, reqs, n_streams,
+                         dict(seed=seed, per_stream=per_stream, mix=mix, size_range=size_range,
+                              pool_keys=pool_keys, universe=universe, s=s, open_window=open_window,
+                              stream_rate=stream_rate))

@@ -1,0 +1,145 @@
+"""Sketch groups on the GPU: every sketch of a group must end in exactly the
+state the oracle (and a lone sketch) reaches on its own ops with its own
+batch size, whatever the round packing, graph capture or tile size."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1701_04148_amd as sf
+import sfgen
+from tests.gpu_support import assert_same, dev_keys, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfgs(w, d, batch, kb=4, seeds=None):
+    return [sf.make_config(int(d[i]), int(w[i]), 4, kb, int(seeds[i]) if seeds is not None else 1,
+                           int(batch[i])) for i in range(len(w))]
+
+
+def _oracle_parts(m, cfgs, kb=4):
+    out = []
+    for i, c in enumerate(cfgs):
+        k, o, q = m.part(i)
+        ref = oracle.Sketch(c.d, c.w, c.z, kb, c.seed_base)
+        assert ref.batch(k, o, c.batch_ops, checked=True) == 0
+        out.append((ref.fat(), ref.slim(), ref.query(q)))
+    return out
+
+
+def _check_group(G, m, refs):
+    import torch
+    out = G.query(dev_keys(m.queries), m.qseg)
+    G.sync()
+    ans = out.cpu().numpy().view(np.uint32)
+    for i in range(m.n):
+        assert_same(G.export_fat(i), refs[i][0], f"fat of sketch {i}")
+        assert_same(G.export_slim(i), refs[i][1], f"slim of sketch {i}")
+        assert_same(ans[int(m.qseg[i]):int(m.qseg[i + 1])], refs[i][2], f"queries of sketch {i}")
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("round_ops", [0, 20_000])
+def test_group_matches_oracle_per_sketch(graph, round_ops):
+    """48 sketches of different widths, stream lengths and batch sizes, mixed ops."""
+    import torch
+    m = sfgen.config_multi(seed=3, n_sketches=48, length_scale=0.03, fat_log2=(8, 13))
+    rng = np.random.default_rng(1)
+    batch = rng.choice([700, 2048, 5000, 1 << 20], size=m.n)
+    cfgs = _cfgs(m.w, np.full(m.n, 4), batch)
+    say(f"[case] group n={m.n} ops={m.keys.size} graph={graph} round_ops={round_ops}")
+    G = sf.SketchGroup(cfgs, round_ops=round_ops)
+    G.set_graph(graph)
+    G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
+    sub, tiles = G.rounds()
+    say(f"  sub-rounds {sub}, tiles {tiles}")
+    _check_group(G, m, _oracle_parts(m, cfgs))
+    G.close()
+
+
+def test_group_replay_and_replan():
+    """A repeated call replays the captured graph; new buffers rebuild the plan."""
+    import torch
+    m = sfgen.config_multi(seed=5, n_sketches=16, length_scale=0.02, fat_log2=(8, 12))
+    cfgs = _cfgs(m.w, np.full(m.n, 4), np.full(m.n, 3000))
+    refs = _oracle_parts(m, cfgs)
+    G = sf.SketchGroup(cfgs)
+    keys, ops = dev_keys(m.keys), torch.from_numpy(m.ops).cuda()
+    for rep in range(3):
+        G.reset()
+        G.update(keys, ops, m.seg)
+        _check_group(G, m, refs)
+    keys2 = keys.clone()                 # same contents, new buffer: plan is rebuilt
+    G.reset()
+    G.update(keys2, ops, m.seg)
+    _check_group(G, m, refs)
+    G.close()
+
+
+def test_group_mixed_rows_and_flow_keys():
+    """Different d per sketch (generic row loop) and 13-byte keys."""
+    import torch
+    rng = np.random.default_rng(9)
+    n = 12
+    parts, seg, qs, qseg = [], [0], [], [0]
+    ops_all = []
+    for i in range(n):
+        L = int(rng.integers(500, 6000))
+        uni = rng.integers(0, 256, size=(max(1, L // 8), 13), dtype=np.uint8)
+        ranks = rng.zipf(1.3, L) % uni.shape[0]
+        k, o = sfgen.turnstile(uni[ranks], np.random.default_rng(i), 0.1)
+        parts.append(k)
+        ops_all.append(o)
+        seg.append(seg[-1] + L)
+        qs.append(uni)
+        qseg.append(qseg[-1] + uni.shape[0])
+    m = sfgen.MultiWorkload("flows", 0, 4, rng.choice([64, 256, 1000], n), np.concatenate(parts),
+                            np.concatenate(ops_all), np.array(seg, np.uint64), np.concatenate(qs),
+                            np.array(qseg, np.uint64))
+    d = rng.integers(1, 9, n)
+    cfgs = _cfgs(m.w, d, rng.choice([333, 4096], n), kb=13, seeds=rng.integers(1, 100, n))
+    G = sf.SketchGroup(cfgs)
+    G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
+    _check_group(G, m, _oracle_parts(m, cfgs, kb=13))
+    G.close()
+
+
+def test_group_equals_lone_sketches_and_tiles():
+    """Group state == one Sketch per stream; tile size does not change it."""
+    import torch
+    m = sfgen.config_multi(seed=7, n_sketches=10, length_scale=0.05, fat_log2=(10, 12))
+    cfgs = _cfgs(m.w, np.full(m.n, 4), np.full(m.n, 4096))
+    lone = []
+    for i, c in enumerate(cfgs):
+        k, o, q = m.part(i)
+        s = sf.Sketch(c.d, c.w, c.z, batch_ops=c.batch_ops)
+        s.update(dev_keys(k), torch.from_numpy(np.ascontiguousarray(o)).cuda())
+        s.sync()
+        lone.append((s.export_fat(), s.export_slim(), s.query(dev_keys(q)).cpu().numpy().view(np.uint32)))
+        s.close()
+    for tile in (256, 2048):
+        G = sf.SketchGroup(cfgs)
+        G.set_tile(tile)
+        G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
+        _check_group(G, m, lone)
+        G.close()
+
+
+def test_group_insert_delete_and_errors():
+    import torch
+    cfgs = _cfgs([64, 128], [4, 4], [100, 100])
+    G = sf.SketchGroup(cfgs)
+    keys = torch.arange(0, 300, dtype=torch.int32, device="cuda")
+    seg = np.array([0, 100, 300], np.uint64)
+    G.insert(keys, seg)
+    G.delete(keys, seg)
+    G.sync()
+    assert not G.export_fat(0).any() and not G.export_fat(1).any()
+    assert not G.export_slim(1).any()
+    with pytest.raises(sf.SFError):
+        G.insert(keys, np.array([0, 200, 100], np.uint64))       # decreasing offsets
+    with pytest.raises(sf.SFError):
+        G.insert(keys, np.array([0, 100, 1 << 30], np.uint64))   # past the key buffer
+    G.close()
+    with pytest.raises(sf.SFError):
+        sf.SketchGroup([sf.make_config(4, 64, 4, 4), sf.make_config(4, 64, 4, 13)])

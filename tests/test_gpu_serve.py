@@ -1,0 +1,130 @@
+"""Serving loop on the GPU: every stream's result is the same alone and in the
+mix (bit-exact), matches the oracle, and admission respects the HBM budget."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1701_04148_amd as sf
+import sfgen
+from paper_1701_04148_amd.serve import Server
+from tests.gpu_support import assert_same, say
+
+pytestmark = pytest.mark.gpu
+
+CFG = dict(d=4, w=2048, z=4, key_bytes=4, seed_base=1, batch_ops=3000)
+
+
+def _workload(seed=1, n_streams=40, per_stream=6):
+    return sfgen.serving(seed=seed, n_streams=n_streams, per_stream=per_stream, size_range=(50, 9000),
+                         pool_keys=1 << 18, universe=20_000, open_window=0.02, stream_rate=400.0)
+
+
+def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15):
+    import torch
+    pool_t = torch.from_numpy(w.pool.view(np.int32)).cuda()
+    outs = {i: torch.full((r.n,), -1, dtype=torch.int32, device="cuda")
+            for i, r in enumerate(w.requests) if r.kind == sf.SF_REQ_QUERY}
+    index = {id(r): i for i, r in enumerate(w.requests)}
+    slims = {s: torch.zeros(CFG["d"] * CFG["w"], dtype=torch.int16, device="cuda")
+             for s in range(w.n_streams)}
+    pool = sf.SketchPool(sf.make_config(**CFG), max_slots=max_slots)
+    srv = Server(pool, max_launch_keys=max_launch_keys, max_in_flight=3)
+    st = srv.run(w.requests, key_of=lambda r: pool_t[r.off:r.off + r.n],
+                 out_of=lambda r: outs[index[id(r)]], export_to=lambda s: slims[s], realtime=realtime)
+    pool.sync()
+    torch.cuda.synchronize()
+    res = {s: slims[s].cpu().numpy().view(np.uint16).reshape(CFG["d"], CFG["w"]) for s in slims}
+    ans = {i: o.cpu().numpy().view(np.uint32) for i, o in outs.items()}
+    pool.close()
+    return st, res, ans
+
+
+def _run_alone(w, stream):
+    import torch
+    pool_t = torch.from_numpy(w.pool.view(np.int32)).cuda()
+    pool = sf.SketchPool(sf.make_config(**CFG), max_slots=1)
+    slot = pool.acquire()
+    ans = {}
+    for i, r in enumerate(w.requests):
+        if r.stream != stream:
+            continue
+        out = torch.full((r.n,), -1, dtype=torch.int32, device="cuda") if r.kind == sf.SF_REQ_QUERY else None
+        t = pool.launch([(slot, r.kind, pool_t[r.off:r.off + r.n], None, out)])
+        pool.wait(t)
+        if out is not None:
+            ans[i] = out.cpu().numpy().view(np.uint32)
+    slim = pool.export_slim(slot)
+    fat = pool.export_fat(slot)
+    pool.close()
+    return slim, fat, ans
+
+
+def _oracle_stream(w, stream):
+    ref = oracle.Sketch(CFG["d"], CFG["w"], CFG["z"])
+    ans = {}
+    for i, r in enumerate(w.requests):
+        if r.stream != stream:
+            continue
+        keys = w.pool[r.off:r.off + r.n]
+        if r.kind == sf.SF_REQ_QUERY:
+            ans[i] = ref.query(keys)
+        else:
+            ops = np.full(r.n, 1 if r.kind == sf.SF_REQ_DELETE else 0, np.uint8)
+            assert ref.batch(keys, ops, CFG["batch_ops"], checked=True) == 0
+    return ref.slim(), ref.fat(), ans
+
+
+@pytest.mark.parametrize("realtime", [False, True])
+def test_alone_equals_mixed_and_oracle(realtime):
+    w = _workload()
+    say(f"[case] serving mix realtime={realtime}: {len(w.requests)} requests, {w.n_streams} streams")
+    st, res, ans = _run_mixed(w, max_slots=8, realtime=realtime)
+    say(f"  launches {st.launches}, mean {st.mean_requests_per_launch:.1f} req/launch, "
+        f"latency {st.latency_ms}, peak resident {st.peak_resident}")
+    assert st.peak_resident <= 8 and st.launches > 1 and st.mean_requests_per_launch > 1
+    assert all(o.done >= o.issued >= 0 for o in st.outcomes)
+    for stream in (0, 1, 7, 23, 39):
+        slim_a, fat_a, ans_a = _run_alone(w, stream)
+        assert_same(res[stream], slim_a, f"slim of stream {stream}: mixed vs alone")
+        for i, a in ans_a.items():
+            assert_same(ans[i], a, f"query {i} of stream {stream}: mixed vs alone")
+        slim_o, fat_o, ans_o = _oracle_stream(w, stream)
+        assert_same(slim_a, slim_o, f"slim of stream {stream} vs oracle")
+        assert_same(fat_a, fat_o, f"fat of stream {stream} vs oracle")
+        for i, a in ans_o.items():
+            assert_same(ans_a[i], a, f"query {i} of stream {stream} vs oracle")
+
+
+def test_admission_by_budget():
+    cfg = sf.make_config(**CFG)
+    slot = sf.sf_pool_slot_bytes(cfg)
+    probe = sf.SketchPool(cfg, max_slots=1)
+    probe.close()
+    pool = sf.SketchPool(cfg, hbm_budget_bytes=(1 << 31))  # shared buffers + as many slots as fit
+    total, free = pool.capacity()
+    assert total >= 1 and free == total
+    got = [pool.acquire() for _ in range(total)]
+    assert None not in got and pool.acquire() is None       # budget exhausted
+    pool.release(got[0])
+    assert pool.acquire() == got[0]
+    pool.close()
+    with pytest.raises(sf.SFError):
+        sf.SketchPool(cfg, hbm_budget_bytes=slot)           # no room for the shared buffers
+    w = _workload(seed=2, n_streams=20, per_stream=4)
+    st, _, _ = _run_mixed(w, max_slots=3, realtime=False)
+    assert st.peak_resident <= 3 and st.requests == len(w.requests)
+
+
+def test_pool_rejects_bad_requests():
+    import torch
+    pool = sf.SketchPool(sf.make_config(**CFG), max_slots=2)
+    a = pool.acquire()
+    keys = torch.arange(100, dtype=torch.int32, device="cuda")
+    with pytest.raises(sf.SFError):
+        pool.launch([(a, sf.SF_REQ_INSERT, keys, None, None), (a, sf.SF_REQ_INSERT, keys, None, None)])
+    with pytest.raises(sf.SFError):
+        pool.launch([(1 - a, sf.SF_REQ_INSERT, keys, None, None)])   # slot not acquired
+    t = pool.launch([(a, sf.SF_REQ_INSERT, keys, None, None)])
+    pool.wait(t)
+    assert pool.done(t)
+    pool.close()
