@@ -65,13 +65,16 @@ def algorithmic_bytes(kind: str, d: int, n_ins: int, n_del: int, n_ops: int, mix
         return n_q * (4 + d * 4 + 4)
     if kind == "export":     # uint32 working cell in, uint16 out
         return cells * 6
+    if kind == "merge":      # key read twice + partitioned copy written and read; S1 as snapshot
+        return n_ins * (4 * 4 + d * (4 + 4 + 4 + 2)) + n_del * 16 + 2 * op_byte
     return 0
 
 
 # random accesses per unit of each kernel (reads + atomics, merged duplicates not subtracted)
 def random_accesses(kind: str, d: int, n_ins: int, n_del: int, n_q: int) -> int:
     return {"snapshot": 2 * d * n_ins, "fat_add": d * n_ins, "raise": d * n_ins,
-            "fat_sub": d * n_del, "clamp": 2 * d * n_del, "query": d * n_q}.get(kind, 0)
+            "fat_sub": d * n_del, "clamp": 2 * d * n_del, "query": d * n_q,
+            "merge": 2 * d * n_ins}.get(kind, 0)
 
 
 def stored_traffic(kernel_kind: str, workload: str):
@@ -145,7 +148,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
 def workload_tag(args) -> str:
     """Name of the timed workload (sketch shape, stream, schedule, tile) for stored counters."""
     return (f"c2_d4_w{2**20 // args.scale}_z4_ops{32_000_000 // args.scale}_zipf{args.skew}_del10"
-            f"_b{args.batch_ops}_tile{args.tile}")
+            f"_b{args.batch_ops}_tile{args.tile}_merge{args.merge}")
 
 
 def micro_ceilings(torch, sizes_mib=(1, 16, 64, 256, 4096), n=1 << 26):
@@ -375,6 +378,8 @@ def main():
     ap.add_argument("--batch-ops", type=int, default=1 << 21, help="schedule batch size b")
     ap.add_argument("--scale", type=int, default=1, help="divide every size (quick runs)")
     ap.add_argument("--tile", type=int, default=2048, help="ops per duplicate-merging tile")
+    ap.add_argument("--merge", choices=("tile", "batch"), default="batch",
+                    help="merge duplicate keys per tile or across the whole schedule batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -435,6 +440,7 @@ def main():
     b = args.batch_ops
     sk = sf.Sketch(wl.d, wl.w, wl.z, batch_ops=b)
     sk.set_tile(args.tile)
+    sk.set_merge(args.merge == "batch")
 
     def step():
         sk.reset()
@@ -508,7 +514,7 @@ def main():
                                f"with {n_del} deletes; export Slim; {wl.n_queries} queries "
                                "(present + absent); keys resident in HBM",
                    "sketches": 1, "d": wl.d, "w": wl.w, "z": wl.z, "ops": wl.n_ops, "deletes": n_del,
-                   "queries": wl.n_queries, "zipf_s": args.skew, "batch_ops": b, "tile_ops": args.tile,
+                   "queries": wl.n_queries, "zipf_s": args.skew, "batch_ops": b, "tile_ops": args.tile, "merge": args.merge,
                    "scale": args.scale},
         "roofline": roofline,
         "kernels": kernels,

@@ -34,7 +34,7 @@ class sf_config(ctypes.Structure):
                 ("batch_ops", ctypes.c_uint32)]
 
 
-KERNEL_KINDS = ("snapshot", "fat_add", "raise", "fat_sub", "clamp", "query", "export")
+KERNEL_KINDS = ("snapshot", "fat_add", "raise", "fat_sub", "clamp", "query", "export", "merge")
 
 
 class sf_kernel_stats(ctypes.Structure):
@@ -60,6 +60,7 @@ SIGNATURES = {
     "sf_export_fat": (_I, [_P, _P, _U64]),
     "sf_sync": (_I, [_P]),
     "sf_set_tile": (_I, [_P, ctypes.c_uint32]),
+    "sf_set_merge": (_I, [_P, _I]),
     "sf_profile": (_I, [_P, _I]),
     "sf_profile_read": (_I, [_P, ctypes.POINTER(sf_kernel_stats), _I]),
     "sf_group_footprint": (_U64, [ctypes.c_uint32, _CFG, _U64]),
@@ -306,6 +307,10 @@ class Sketch:
 
     def set_tile(self, tile_ops: int):
         sf_set_tile(self._h, tile_ops)
+
+    def set_merge(self, batch_wide: bool):
+        """Merge duplicate keys across the whole batch (True, the default) or per tile (False)."""
+        _check(lib().sf_set_merge(self._h, int(bool(batch_wide))), "sf_set_merge")
 
     def profile(self, enable: bool = True):
         sf_profile(self._h, enable)

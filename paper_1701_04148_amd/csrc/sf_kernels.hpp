@@ -270,3 +270,262 @@ __global__ __launch_bounds__(kBlock) void k_pack16(const T* __restrict__ in, uin
 }
 
 }  // namespace sfk
+
+// =====================================================================
+// Batch-wide duplicate merging ("batch merge").  The tile kernels above
+// merge duplicates inside each tile only; on skewed streams most of a
+// batch's ops repeat keys seen in other tiles.  Here the batch's keys are
+// first partitioned into kBuckets hash buckets per op type, then one
+// workgroup per chunk of a bucket merges them in the LDS table, emitting one
+// entry (key, count) per distinct key of the chunk.  Insert entries grow up
+// from index 0, delete entries down from the last index, so both fit the
+// snapshot scratch of one batch.  S1 is taken while the entries are emitted;
+// S2..S5 then run once per entry.
+// =====================================================================
+namespace sfk {
+
+constexpr uint32_t kBuckets = 256;             // per op type
+constexpr uint32_t kPartOps = 8192;            // ops per partitioning workgroup
+template <int KB> struct MergeShape {          // LDS table of the merging kernel
+    static constexpr int J = KB == 4 ? 16 : 8; // 4096 (or 2048) keys per chunk
+    static constexpr uint32_t kChunk = uint32_t(kBlock) * J;
+};
+
+struct MergeMeta {                 // device-side bookkeeping of one batch
+    uint32_t total[2 * kBuckets];  // keys per bucket (zeroed again by k_part_start)
+    uint32_t start[2 * kBuckets];  // first position of each bucket in part_keys
+    uint32_t size[2 * kBuckets];
+    uint32_t cursor[2 * kBuckets]; // scatter cursors
+    uint32_t chunk0[2 * kBuckets + 1];  // first chunk of each bucket (prefix)
+    uint32_t n_ins, n_del;         // entries emitted
+};
+
+template <int KB> __device__ __forceinline__ uint32_t bucket_of(const Key<KB>& k, bool del) {
+    return (slot_hash<KB>(k) >> 24) + (del ? kBuckets : 0u);   // top 8 bits; the table uses low bits
+}
+
+// Counts the ops of every bucket.
+template <int KB, class P>
+__global__ __launch_bounds__(kBlock) void k_part_count(P plan, MergeMeta* __restrict__ meta) {
+    __shared__ uint32_t hist[2 * kBuckets];
+    const Work w = plan.at(blockIdx.x, kPartOps);
+    for (uint32_t b = threadIdx.x; b < 2 * kBuckets; b += kBlock) hist[b] = 0;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock)
+        atomicAdd(&hist[bucket_of<KB>(load_key<KB>(w.keys, t), is_delete(w.ops, t, w.mode))], 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < 2 * kBuckets; b += kBlock)
+        if (hist[b]) atomicAdd(&meta->total[b], hist[b]);
+}
+
+// One workgroup of 2*kBuckets threads: bucket starts, cursors and chunk
+// prefix; clears the totals and entry counters for the next batch.
+template <int KB>
+__global__ __launch_bounds__(2 * kBuckets) void k_part_start(MergeMeta* __restrict__ meta) {
+    __shared__ uint32_t a[2 * kBuckets], c[2 * kBuckets];
+    const uint32_t b = threadIdx.x;
+    const uint32_t sz = meta->total[b];
+    a[b] = sz;
+    c[b] = (sz + MergeShape<KB>::kChunk - 1) / MergeShape<KB>::kChunk;
+    __syncthreads();
+    for (uint32_t off = 1; off < 2 * kBuckets; off <<= 1) {  // inclusive scans
+        const uint32_t va = b >= off ? a[b - off] : 0u, vc = b >= off ? c[b - off] : 0u;
+        __syncthreads();
+        a[b] += va;
+        c[b] += vc;
+        __syncthreads();
+    }
+    meta->size[b] = sz;
+    meta->start[b] = a[b] - sz;
+    meta->cursor[b] = a[b] - sz;
+    meta->chunk0[b + 1] = c[b];
+    if (b == 0) {
+        meta->chunk0[0] = 0;
+        meta->n_ins = 0;
+        meta->n_del = 0;
+    }
+    meta->total[b] = 0;
+}
+
+// Scatters the keys into their buckets (order inside a bucket is free).
+template <int KB, class P>
+__global__ __launch_bounds__(kBlock) void k_part_scatter(P plan, MergeMeta* __restrict__ meta,
+                                                         Key<KB>* __restrict__ part) {
+    __shared__ uint32_t hist[2 * kBuckets];
+    const Work w = plan.at(blockIdx.x, kPartOps);
+    for (uint32_t b = threadIdx.x; b < 2 * kBuckets; b += kBlock) hist[b] = 0;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock)
+        atomicAdd(&hist[bucket_of<KB>(load_key<KB>(w.keys, t), is_delete(w.ops, t, w.mode))], 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < 2 * kBuckets; b += kBlock)
+        if (hist[b]) hist[b] = atomicAdd(&meta->cursor[b], hist[b]);  // this group's first position
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock) {
+        const Key<KB> k = load_key<KB>(w.keys, t);
+        part[atomicAdd(&hist[bucket_of<KB>(k, is_delete(w.ops, t, w.mode))], 1u)] = k;
+    }
+}
+
+// Merges one chunk of one bucket; emits entries; takes S1 for insert entries.
+// cap = entry capacity (insert entries at [0, n_ins), delete entries at
+// [cap - n_del, cap)).
+template <int KB, int D>
+__global__ __launch_bounds__(kBlock) void k_merge(const Key<KB>* __restrict__ part, MergeMeta* __restrict__ meta,
+                                                  Key<KB>* __restrict__ ent_key, uint32_t* __restrict__ ent_cnt,
+                                                  uint32_t cap, Geom g, const uint32_t* __restrict__ fat,
+                                                  const uint32_t* __restrict__ slim, uint32_t* __restrict__ bpre,
+                                                  uint16_t* __restrict__ asnap, uint32_t stride) {
+    constexpr int J = MergeShape<KB>::J;
+    constexpr uint32_t kChunk = MergeShape<KB>::kChunk;
+    __shared__ TileLDS<KB, J> L;
+    __shared__ uint32_t nloc, base;
+    const uint32_t c = blockIdx.x;
+    if (c >= meta->chunk0[2 * kBuckets]) return;
+    uint32_t lo = 0, hi = 2 * kBuckets;           // bucket b with chunk0[b] <= c < chunk0[b+1]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (meta->chunk0[mid] <= c) lo = mid; else hi = mid;
+    }
+    const uint32_t b = lo;
+    const bool del = b >= kBuckets;
+    const uint32_t first = meta->start[b] + (c - meta->chunk0[b]) * kChunk;
+    const uint32_t end = meta->start[b] + meta->size[b];
+    const uint32_t n = end - first < kChunk ? end - first : kChunk;
+    tile_clear<KB, J>(L);
+    if (threadIdx.x == 0) nloc = 0;
+    Key<KB> k[J];
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
+        if (idx < n) {
+            k[j] = part[first + idx];
+            L.key[idx] = k[j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
+        if (idx < n) tile_insert<KB, J>(L, k[j], idx);
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock)  // compact: occupied slots
+        if (L.owner[s] != kEmpty) L.cnt[s] |= atomicAdd(&nloc, 1u) << 16;      // rank in the high half
+    __syncthreads();
+    if (threadIdx.x == 0) base = atomicAdd(del ? &meta->n_del : &meta->n_ins, nloc);
+    __syncthreads();
+    const uint32_t d = SF_ROWS(D, g);
+    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
+        const uint32_t o = L.owner[s];
+        if (o == kEmpty) continue;
+        const uint32_t v = L.cnt[s];
+        const uint32_t rank = base + (v >> 16);
+        const uint32_t id = del ? cap - 1 - rank : rank;
+        const Key<KB> key = L.key[o];
+        ent_key[id] = key;
+        ent_cnt[id] = v & 0xffffu;
+        if (del) continue;
+        const Mixed<KB> mx(key);
+#pragma unroll
+        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+            if (i < d) {
+                uint32_t h, f;
+                split(g, mx.row(g.seed_base + i), h, f);
+                const size_t cell = size_t(i) * g.w + h;
+                asnap[size_t(i) * stride + id] = uint16_t(slim[cell]);
+                bpre[size_t(i) * stride + id] = fat[cell * g.z + f];
+            }
+        }
+    }
+}
+
+// S2 / S4 over merged entries: one atomic per entry and row carrying its count.
+template <int KB, int D>
+__global__ __launch_bounds__(kBlock) void k_entries_fat(const MergeMeta* __restrict__ meta,
+                                                        const Key<KB>* __restrict__ ent_key,
+                                                        const uint32_t* __restrict__ ent_cnt, uint32_t cap,
+                                                        Geom g, uint32_t* __restrict__ fat, uint32_t del) {
+    const uint32_t n = del ? meta->n_del : meta->n_ins;
+    const uint32_t d = SF_ROWS(D, g);
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
+        const uint32_t id = del ? cap - 1 - e : e;
+        const uint32_t v = del ? 0u - ent_cnt[id] : ent_cnt[id];
+        const Mixed<KB> mx(ent_key[id]);
+#pragma unroll
+        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+            if (i < d) {
+                uint32_t h, f;
+                split(g, mx.row(g.seed_base + i), h, f);
+                atomic_add_u32(&fat[(size_t(i) * g.w + h) * g.z + f], v);
+            }
+        }
+    }
+}
+
+// S3 over merged insert entries.
+template <int KB, int D>
+__global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __restrict__ meta,
+                                                          const Key<KB>* __restrict__ ent_key, Geom g,
+                                                          const uint32_t* __restrict__ fat,
+                                                          uint32_t* __restrict__ slim,
+                                                          const uint32_t* __restrict__ bpre,
+                                                          const uint16_t* __restrict__ asnap, uint32_t stride) {
+    constexpr int R = D ? D : kMaxD;
+    const uint32_t n = meta->n_ins;
+    const uint32_t d = SF_ROWS(D, g);
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
+        const Mixed<KB> mx(ent_key[e]);
+        size_t cell[R];
+        uint32_t a[R];
+        uint32_t m0 = ~0u, bmin = ~0u, delta = ~0u;
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            cell[i] = 0;
+            a[i] = kSlimMax;
+            if (uint32_t(i) < d) {
+                uint32_t h, f;
+                split(g, mx.row(g.seed_base + i), h, f);
+                cell[i] = size_t(i) * g.w + h;
+                a[i] = asnap[size_t(i) * stride + e];
+                const uint32_t post = fat[cell[i] * g.z + f];
+                const uint32_t grew = post - bpre[size_t(i) * stride + e];
+                m0 = min(m0, a[i]);
+                bmin = min(bmin, post);
+                delta = min(delta, grew);
+            }
+        }
+        const uint64_t rise = uint64_t(m0) + delta;
+        const uint64_t level = m0 > bmin ? m0 : bmin;
+        const uint64_t tt = rise < level ? rise : level;
+        const uint32_t T = uint32_t(tt < kSlimMax ? tt : kSlimMax);
+#pragma unroll
+        for (int i = 0; i < R; i++)
+            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&slim[cell[i]], T);
+    }
+}
+
+// S5 over merged delete entries.
+template <int KB, int D>
+__global__ __launch_bounds__(kBlock) void k_entries_clamp(const MergeMeta* __restrict__ meta,
+                                                          const Key<KB>* __restrict__ ent_key, uint32_t cap,
+                                                          Geom g, const uint32_t* __restrict__ fat,
+                                                          uint32_t* __restrict__ slim) {
+    const uint32_t n = meta->n_del;
+    const uint32_t d = SF_ROWS(D, g);
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
+        const Mixed<KB> mx(ent_key[cap - 1 - e]);
+#pragma unroll
+        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
+            if (i < d) {
+                uint32_t h, f;
+                split(g, mx.row(g.seed_base + i), h, f);
+                const size_t cell = size_t(i) * g.w + h;
+                const uint32_t m = bucket_max(fat, cell, g);
+                if (slim[cell] > m) atomic_min_u32(&slim[cell], m);
+            }
+        }
+    }
+}
+
+}  // namespace sfk

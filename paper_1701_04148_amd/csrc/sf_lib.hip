@@ -44,6 +44,11 @@ struct sf_sketch {
     uint16_t* asnap;
     uint32_t stride;  // snapshot capacity in ops (= batch_ops)
     uint32_t tile_j;  // ops per thread of a tile (tile = 256 * tile_j ops)
+    bool merge_batch; // merge duplicates across the whole batch (else per tile)
+    void* part;       // batch merge: keys partitioned by bucket      [b] keys
+    void* ent_key;    // batch merge: one key per merged entry        [b] keys
+    uint32_t* ent_cnt;//              its op count                    [b]
+    MergeMeta* meta;
     Profiler prof;
 };
 
@@ -58,25 +63,75 @@ bool live(const sf_sketch* s) {
 }
 
 struct Sizes {
-    uint64_t fat, slim, stage, bpre, asnap;
-    uint64_t total() const { return fat + slim + stage + bpre + asnap; }
+    uint64_t fat, slim, stage, bpre, asnap, part, ent_key, ent_cnt, meta;
+    uint64_t total() const { return fat + slim + stage + bpre + asnap + part + ent_key + ent_cnt + meta; }
 };
 
 Sizes sizes_of(const sf_config* c) {
     Sizes s;
     const uint64_t cells = uint64_t(c->d) * c->w;
+    const uint64_t key = c->key_bytes == 4 ? sizeof(Key<4>) : sizeof(Key<13>);
     s.fat = round256(cells * c->z * 4);
     s.slim = round256(cells * 4);
     s.stage = round256(cells * 2);
     s.bpre = round256(uint64_t(c->d) * c->batch_ops * 4);
     s.asnap = round256(uint64_t(c->d) * c->batch_ops * 2);
+    s.part = round256(uint64_t(c->batch_ops) * key);
+    s.ent_key = round256(uint64_t(c->batch_ops) * key);
+    s.ent_cnt = round256(uint64_t(c->batch_ops) * 4);
+    s.meta = round256(sizeof(MergeMeta));
     return s;
+}
+
+// Batch-wide merge: partition, merge (+ S1), then S2..S5 over the entries.
+template <int KB, int D>
+void launch_merged(sf_sketch* s, const UniformPlan<KB>& plan, uint32_t cnt, bool ins, bool del) {
+    hipStream_t st = s->stream;
+    Key<KB>* part = static_cast<Key<KB>*>(s->part);
+    Key<KB>* ek = static_cast<Key<KB>*>(s->ent_key);
+    const unsigned pt = blocks_for(cnt, kPartOps);
+    const unsigned eg = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
+    {
+        Timed tm(&s->prof, st, SF_K_MERGE, cnt);
+        k_part_count<KB, UniformPlan<KB>><<<pt, kBlock, 0, st>>>(plan, s->meta);
+        k_part_start<KB><<<1, 2 * kBuckets, 0, st>>>(s->meta);
+        k_part_scatter<KB, UniformPlan<KB>><<<pt, kBlock, 0, st>>>(plan, s->meta, part);
+        k_merge<KB, D><<<blocks_for(cnt, MergeShape<KB>::kChunk) + 2 * kBuckets, kBlock, 0, st>>>(
+            part, s->meta, ek, s->ent_cnt, s->stride, s->g, s->fat, s->slim, s->bpre, s->asnap, s->stride);
+    }
+    if (ins) {
+        {
+            Timed tm(&s->prof, st, SF_K_FAT_ADD, cnt);
+            k_entries_fat<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->ent_cnt, s->stride, s->g, s->fat, 0u);
+        }
+        {
+            Timed tm(&s->prof, st, SF_K_RAISE, cnt);
+            k_entries_raise<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->g, s->fat, s->slim, s->bpre, s->asnap,
+                                                          s->stride);
+        }
+    }
+    if (del) {
+        {
+            Timed tm(&s->prof, st, SF_K_FAT_SUB, cnt);
+            k_entries_fat<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->ent_cnt, s->stride, s->g, s->fat, 1u);
+        }
+        {
+            Timed tm(&s->prof, st, SF_K_CLAMP, cnt);
+            k_entries_clamp<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->stride, s->g, s->fat, s->slim);
+        }
+    }
 }
 
 template <int KB>
 void launch_batch(sf_sketch* s, const uint8_t* keys, const uint8_t* ops, uint32_t mode, uint32_t cnt, bool ins,
                   bool del) {
     const UniformPlan<KB> plan{keys, ops, nullptr, cnt, mode, s->g, s->fat, s->slim};
+    if (s->merge_batch) {
+        if (s->cfg.d == 4) launch_merged<KB, 4>(s, plan, cnt, ins, del);
+        else if (s->cfg.d == 8) launch_merged<KB, 8>(s, plan, cnt, ins, del);
+        else launch_merged<KB, 0>(s, plan, cnt, ins, del);
+        return;
+    }
     const unsigned tiles = blocks_for(cnt, uint32_t(kBlock) * s->tile_j);
     Steps<UniformPlan>::by_rows<KB>(s->cfg.d, s->tile_j, plan, tiles, ins, del, s->bpre, s->asnap, s->stride,
                                    s->stream, &s->prof, cnt);
@@ -165,6 +220,7 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     s->stream = static_cast<hipStream_t>(hip_stream);
     s->stride = cfg->batch_ops;
     s->tile_j = 8;
+    s->merge_batch = true;
     hipError_t e = hipGetDevice(&s->device);
     char* base = nullptr;
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&base), sz.total());
@@ -179,7 +235,13 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     s->stage = reinterpret_cast<uint16_t*>(base + sz.fat + sz.slim);
     s->bpre = reinterpret_cast<uint32_t*>(base + sz.fat + sz.slim + sz.stage);
     s->asnap = reinterpret_cast<uint16_t*>(base + sz.fat + sz.slim + sz.stage + sz.bpre);
-    e = hipMemsetAsync(base, 0, sz.fat + sz.slim, s->stream);
+    char* mq = base + sz.fat + sz.slim + sz.stage + sz.bpre + sz.asnap;
+    s->part = mq;
+    s->ent_key = mq + sz.part;
+    s->ent_cnt = reinterpret_cast<uint32_t*>(mq + sz.part + sz.ent_key);
+    s->meta = reinterpret_cast<MergeMeta*>(mq + sz.part + sz.ent_key + sz.ent_cnt);
+    e = hipMemsetAsync(s->meta, 0, sizeof(MergeMeta), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(base, 0, sz.fat + sz.slim, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         (void)hipFree(base);
@@ -293,6 +355,12 @@ int sf_set_tile(sf_sketch* s, uint32_t tile_ops) {
     if (tile_ops != 256 && tile_ops != 1024 && tile_ops != 2048)
         return fail(SF_EINVAL, "tile_ops must be 256, 1024 or 2048");
     s->tile_j = tile_ops / kBlock;
+    return SF_OK;
+}
+
+int sf_set_merge(sf_sketch* s, int batch_wide) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    s->merge_batch = batch_wide != 0;
     return SF_OK;
 }
 

@@ -190,6 +190,8 @@ def make(name: str, *, d: int, w: int, z: int, n_universe: int, n_ops: int, s: f
     ranks = zipf_ranks(g_rank, n_universe, s, n_ops)
     ins = uni[ranks]
     keys, ops = turnstile(ins, g_del, p_del)
+    # exact occurrence count of every universe key (insert-only streams)
+    counts = np.bincount(ranks, minlength=n_universe) if p_del <= 0 else None
     parts = [uni] if query_universe else []
     if n_absent:
         parts.append(absent_u32(g_abs, uni, n_absent) if key_bytes == 4
@@ -198,7 +200,7 @@ def make(name: str, *, d: int, w: int, z: int, n_universe: int, n_ops: int, s: f
     return Workload(name, d, w, z, key_bytes, seed_base, np.ascontiguousarray(keys),
                     ops if p_del > 0 else None, np.ascontiguousarray(queries), uni,
                     dict(n_universe=n_universe, n_ops=n_ops, s=s, p_del=p_del, seed=seed,
-                         n_absent=n_absent))
+                         n_absent=n_absent, universe_counts=counts))
 
 
 # ---- the benchmark configurations -----------------------------------------

@@ -22,11 +22,13 @@ def dev_keys(keys: np.ndarray):
     return torch.from_numpy(np.ascontiguousarray(keys).reshape(-1)).cuda()
 
 
-def gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base=1, calls=1):
+def gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base=1, calls=1, merge=False, tile=2048):
     """Updates (split into `calls` consecutive calls) then queries, on the GPU.
     Returns (fat, slim, answers)."""
     import torch
     sk = sf.Sketch(d, w, z, key_bytes=kb, seed_base=seed_base, batch_ops=b)
+    sk.set_merge(merge)
+    sk.set_tile(tile)
     n = keys.shape[0]
     cuts = np.linspace(0, n, calls + 1).astype(np.int64)
     for lo, hi in zip(cuts[:-1], cuts[1:]):

@@ -16,10 +16,10 @@ from tests.oracle_support import exact_counts, random_turnstile
 pytestmark = pytest.mark.gpu
 
 
-def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag=""):
+def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag="", merge=False):
     say(f"[case] {tag} d={d} w={w} z={z} kb={kb} n={keys.shape[0]} q={queries.shape[0]} "
-        f"b={b} calls={calls}")
-    g = gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls)
+        f"b={b} calls={calls} merge={'batch' if merge else 'tile'}")
+    g = gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls, merge=merge)
     o = oracle_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls)
     assert_same(g[0], o[0], "fat")
     assert_same(g[1], o[1], "slim")
@@ -31,19 +31,21 @@ def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag=""):
                                       (8, 512, 4, 13), (5, 333, 2, 13), (16, 128, 1, 4),
                                       (2, 4096, 8, 4), (4, 256, 4, 13)])
 @pytest.mark.parametrize("b", [1000, 1 << 20])
-def test_mixed_small(d, w, z, kb, b):
+@pytest.mark.parametrize("merge", [False, True])
+def test_mixed_small(d, w, z, kb, b, merge):
     """Several tiles and a ragged tail: 20011 mixed ops, 30% deletes."""
     rng = np.random.default_rng(d * 7 + w + kb)
     keys, ops, uni = random_turnstile(rng, 20011, 2500, 0.3, key_bytes=kb)
-    check(d, w, z, kb, keys, ops, uni, b, tag="mixed_small")
+    check(d, w, z, kb, keys, ops, uni, b, tag="mixed_small", merge=merge)
 
 
 @pytest.mark.parametrize("b", [1, 3, 64])
-def test_small_batches_and_sequential(b):
+@pytest.mark.parametrize("merge", [False, True])
+def test_small_batches_and_sequential(b, merge):
     """b = 1 is the sequential SF_F rule of Section 3.5 (the oracle's seq mode)."""
     rng = np.random.default_rng(b)
     keys, ops, uni = random_turnstile(rng, 700, 60, 0.3)
-    fat, slim, ans = check(4, 32, 4, 4, keys, ops, uni, b, tag="small_b")
+    fat, slim, ans = check(4, 32, 4, 4, keys, ops, uni, b, tag="small_b", merge=merge)
     if b == 1:
         ref = oracle.Sketch(4, 32, 4)
         assert ref.seq(keys, ops, checked=True) == 0
@@ -98,24 +100,38 @@ def test_insert_and_delete_entry_points():
     sk.close()
 
 
-def test_small_config_full_size():
+@pytest.mark.parametrize("merge", [False, True])
+def test_small_config_full_size(merge):
     """1M Zipf(1.0) inserts over 100K keys, d=4, Fat 4x65536, Slim 4x16384; all 100K queried."""
     wl = sfgen.config_small()
-    fat, slim, ans = check(wl.d, wl.w, wl.z, 4, wl.keys, None, wl.queries, 65536, tag="c1")
+    fat, slim, ans = check(wl.d, wl.w, wl.z, 4, wl.keys, None, wl.queries, 65536, tag="c1", merge=merge)
     f = exact_counts(wl.keys, None, wl.queries)
     assert (ans.astype(np.int64) >= np.minimum(f, 65535)).all()
 
 
-def test_main_config_scaled():
-    """The 32M-op configuration divided by 8 (4M ops, 10% deletes, w=2^17), s=1.4."""
-    wl = sfgen.config_main(1.4, scale=8)
-    check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, 1 << 18, tag="c2/8")
+@pytest.mark.parametrize("skew,merge", [(1.4, False), (1.4, True), (0.6, True), (1.0, True)])
+def test_main_config_scaled(skew, merge):
+    """The 32M-op configuration divided by 8 (4M ops, 10% deletes, w=2^17)."""
+    wl = sfgen.config_main(skew, scale=8)
+    check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, 1 << 18, tag="c2/8", merge=merge)
 
 
-def test_flow_config_scaled():
+@pytest.mark.parametrize("merge", [False, True])
+def test_flow_config_scaled(merge):
     """13-byte flow keys, d=8, divided by 64 (2M packets over 62.5K flows)."""
     wl = sfgen.config_flows(scale=64)
-    check(wl.d, wl.w, wl.z, 13, wl.keys, None, wl.queries, 1 << 18, tag="c3/64")
+    check(wl.d, wl.w, wl.z, 13, wl.keys, None, wl.queries, 1 << 18, tag="c3/64", merge=merge)
+
+
+def test_batch_merge_with_one_hot_key():
+    """One key is 60% of a 2^20-op batch (one bucket far larger than a merge chunk)."""
+    rng = np.random.default_rng(4)
+    n = 1 << 20
+    keys = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    keys[rng.random(n) < 0.6] = 12345
+    ops = np.zeros(n, np.uint8)
+    q = np.unique(keys)[:50_000]
+    check(4, 1 << 14, 4, 4, keys, ops, q, n, tag="hot", merge=True)
 
 
 def test_query_exported_slim_collector():
@@ -190,3 +206,33 @@ def test_hbm_budget_admission():
     assert e.value.status == sf.SF_ENOMEM
     h = sf.sf_create(c, sf.sf_footprint(c))
     sf.sf_destroy(h)
+
+
+def test_flow_config_full_size_properties():
+    """128M 13-byte packets, d=8, Fat 8x2^23, Slim 8x2^21, in the launch shape bench uses
+    (b = 2^20, tile 2048).  At this size the oracle checks: the Fat equals the oracle's
+    histogram of the stream; every Slim cell is at most min(65535, its bucket max)
+    (Appendix I); every flow's answer is at least min(f, 65535) (Appendix II) and at
+    most min_i max_k B_i[h_i][k]; absent keys answer below that bound too."""
+    import torch
+    wl = sfgen.config_flows()
+    counts = wl.meta["universe_counts"]
+    say(f"[case] flows full size: {wl.n_ops} packets, {wl.n_queries} queries")
+    sk = sf.Sketch(wl.d, wl.w, wl.z, key_bytes=13, batch_ops=1 << 20)
+    sk.insert(dev_keys(wl.keys))
+    ans = sk.query(dev_keys(wl.queries)).cpu().numpy().view(np.uint32)
+    sk.sync()
+    fat, slim = sk.export_fat(), sk.export_slim()
+    sk.close()
+    ref = oracle.Sketch(wl.d, wl.w, wl.z, 13)
+    assert_same(fat, ref.fat_histogram(wl.keys), "fat vs oracle histogram")
+    bmax = fat.max(axis=2)
+    assert (slim.astype(np.int64) <= np.minimum(bmax, 65535)).all()
+    h, _ = ref.indices(wl.queries)
+    U = np.min(np.stack([bmax[i][h[:, i]] for i in range(wl.d)]), axis=0).astype(np.int64)
+    f = np.zeros(wl.n_queries, np.int64)
+    f[:counts.size] = counts                       # queries = the flows, then absent keys
+    assert (ans.astype(np.int64) >= np.minimum(f, 65535)).all()
+    assert (ans.astype(np.int64) <= np.minimum(U, 65535)).all()
+    q_or = oracle.query_slim(slim, wl.d, wl.w, wl.z, wl.queries[:200_000], key_bytes=13)
+    assert_same(ans[:200_000], q_or, "answers vs oracle query on the exported Slim")
