@@ -65,8 +65,10 @@ def algorithmic_bytes(kind: str, d: int, n_ins: int, n_del: int, n_ops: int, mix
         return n_q * (4 + d * 4 + 4)
     if kind == "export":     # uint32 working cell in, uint16 out
         return cells * 6
-    if kind == "merge":      # key read twice + partitioned copy written and read; S1 as snapshot
-        return n_ins * (4 * 4 + d * (4 + 4 + 4 + 2)) + n_del * 16 + 2 * op_byte
+    if kind == "partition":  # keys read twice (count, scatter), partitioned copy written
+        return (n_ins + n_del) * 12 + 2 * op_byte
+    if kind == "merge":      # partitioned key read, entry (key, count) written
+        return (n_ins + n_del) * 12
     return 0
 
 
@@ -74,7 +76,7 @@ def algorithmic_bytes(kind: str, d: int, n_ins: int, n_del: int, n_ops: int, mix
 def random_accesses(kind: str, d: int, n_ins: int, n_del: int, n_q: int) -> int:
     return {"snapshot": 2 * d * n_ins, "fat_add": d * n_ins, "raise": d * n_ins,
             "fat_sub": d * n_del, "clamp": 2 * d * n_del, "query": d * n_q,
-            "merge": 2 * d * n_ins}.get(kind, 0)
+            }.get(kind, 0)
 
 
 def stored_traffic(kernel_kind: str, workload: str):
@@ -94,7 +96,11 @@ def stored_traffic(kernel_kind: str, workload: str):
 
 
 KIND_OF_KERNEL = {"k_snapshot": "snapshot", "k_raise": "raise", "k_clamp": "clamp",
-                  "k_query": "query", "k_pack16": "export"}
+                  "k_query": "query", "k_pack16": "export", "k_merge": "merge",
+                  "k_entries_snapshot": "snapshot",
+                  "k_entries_raise": "raise", "k_entries_clamp": "clamp",
+                  "k_part_count": "part_count", "k_part_start": "part_start",
+                  "k_part_scatter": "part_scatter"}
 
 
 def _kernel_base(name: str) -> str:
@@ -121,8 +127,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
         rows.sort()
         vals, prev = defaultdict(list), None
         for _, base, v in rows:
-            if base == "k_fat_update":
-                kind = "fat_sub" if prev == "k_raise" else "fat_add"
+            if base in ("k_fat_update", "k_entries_fat"):
+                kind = "fat_sub" if prev in ("k_raise", "k_entries_raise") else "fat_add"
             else:
                 kind = KIND_OF_KERNEL.get(base, base)
             vals[kind].append(v)

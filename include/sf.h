@@ -155,8 +155,9 @@ enum sf_kernel_kind {
     SF_K_CLAMP = 4,    /* S5 */
     SF_K_QUERY = 5,
     SF_K_EXPORT = 6,
-    SF_K_MERGE = 7,    /* batch-wide merge: partition + merge (+ S1) */
-    SF_K_COUNT = 8
+    SF_K_MERGE = 7,    /* batch-wide merge: merge per bucket chunk (+ S1) */
+    SF_K_PARTITION = 8,/* batch-wide merge: bucket counts, starts, scatter */
+    SF_K_COUNT = 10
 };
 
 typedef struct sf_kernel_stats {

@@ -34,12 +34,14 @@ class sf_config(ctypes.Structure):
                 ("batch_ops", ctypes.c_uint32)]
 
 
-KERNEL_KINDS = ("snapshot", "fat_add", "raise", "fat_sub", "clamp", "query", "export", "merge")
+KERNEL_KINDS = ("snapshot", "fat_add", "raise", "fat_sub", "clamp", "query", "export", "merge",
+                "partition")
+SF_K_COUNT = 10
 
 
 class sf_kernel_stats(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8),
-                ("items", ctypes.c_uint64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * SF_K_COUNT), ("launches", ctypes.c_uint64 * SF_K_COUNT),
+                ("items", ctypes.c_uint64 * SF_K_COUNT)]
 
 
 # (name, restype, argtypes) of every entry point declared in include/sf.h

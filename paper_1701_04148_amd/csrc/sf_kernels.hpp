@@ -289,7 +289,31 @@ constexpr uint32_t kPartOps = 8192;            // ops per partitioning workgroup
 template <int KB> struct MergeShape {          // LDS table of the merging kernel
     static constexpr int J = KB == 4 ? 16 : 8; // 4096 (or 2048) keys per chunk
     static constexpr uint32_t kChunk = uint32_t(kBlock) * J;
+    static constexpr uint32_t kSlots = 2 * kChunk;
 };
+
+// The merge table packs a slot's owner (local key index) and count into one
+// word -- owner in the high half, count in the low half -- so a 4096-key chunk
+// needs 48 KB of LDS (3 workgroups per CU).
+template <int KB> struct MergeLDS {
+    Key<KB> key[MergeShape<KB>::kChunk];
+    uint32_t slot[MergeShape<KB>::kSlots];
+};
+
+template <int KB>
+__device__ __forceinline__ void merge_insert(MergeLDS<KB>& L, const Key<KB>& k, uint32_t idx) {
+    constexpr uint32_t mask = MergeShape<KB>::kSlots - 1;
+    uint32_t s = slot_hash<KB>(k) & mask;
+    for (uint32_t probe = 0; probe < MergeShape<KB>::kSlots; probe++) {
+        const uint32_t prev = atomicCAS(&L.slot[s], kEmpty, (idx << 16) | 1u);
+        if (prev == kEmpty) return;
+        if (key_eq<KB>(L.key[prev >> 16], k)) {
+            atomicAdd(&L.slot[s], 1u);  // count < 2^16: never carries into the owner
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
 
 struct MergeMeta {                 // device-side bookkeeping of one batch
     uint32_t total[2 * kBuckets];  // keys per bucket (zeroed again by k_part_start)
@@ -367,33 +391,34 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(P plan, MergeMeta* __re
     }
 }
 
-// Merges one chunk of one bucket; emits entries; takes S1 for insert entries.
+// Merges one chunk of one bucket and emits its entries (key, count).
 // cap = entry capacity (insert entries at [0, n_ins), delete entries at
 // [cap - n_del, cap)).
-template <int KB, int D>
+template <int KB>
 __global__ __launch_bounds__(kBlock) void k_merge(const Key<KB>* __restrict__ part, MergeMeta* __restrict__ meta,
                                                   Key<KB>* __restrict__ ent_key, uint32_t* __restrict__ ent_cnt,
-                                                  uint32_t cap, Geom g, const uint32_t* __restrict__ fat,
-                                                  const uint32_t* __restrict__ slim, uint32_t* __restrict__ bpre,
-                                                  uint16_t* __restrict__ asnap, uint32_t stride) {
+                                                  uint32_t cap) {
     constexpr int J = MergeShape<KB>::J;
-    constexpr uint32_t kChunk = MergeShape<KB>::kChunk;
-    __shared__ TileLDS<KB, J> L;
+    constexpr uint32_t kChunk = MergeShape<KB>::kChunk, kSlots = MergeShape<KB>::kSlots;
+    __shared__ MergeLDS<KB> L;
+    __shared__ uint32_t chunk0[2 * kBuckets + 1];
     __shared__ uint32_t nloc, base;
     const uint32_t c = blockIdx.x;
     if (c >= meta->chunk0[2 * kBuckets]) return;
+    for (uint32_t i = threadIdx.x; i <= 2 * kBuckets; i += kBlock) chunk0[i] = meta->chunk0[i];
+    for (uint32_t i = threadIdx.x; i < kSlots; i += kBlock) L.slot[i] = kEmpty;
+    if (threadIdx.x == 0) nloc = 0;
+    __syncthreads();
     uint32_t lo = 0, hi = 2 * kBuckets;           // bucket b with chunk0[b] <= c < chunk0[b+1]
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
-        if (meta->chunk0[mid] <= c) lo = mid; else hi = mid;
+        if (chunk0[mid] <= c) lo = mid; else hi = mid;
     }
     const uint32_t b = lo;
     const bool del = b >= kBuckets;
-    const uint32_t first = meta->start[b] + (c - meta->chunk0[b]) * kChunk;
+    const uint32_t first = meta->start[b] + (c - chunk0[b]) * kChunk;
     const uint32_t end = meta->start[b] + meta->size[b];
     const uint32_t n = end - first < kChunk ? end - first : kChunk;
-    tile_clear<KB, J>(L);
-    if (threadIdx.x == 0) nloc = 0;
     Key<KB> k[J];
 #pragma unroll
     for (int j = 0; j < J; j++) {
@@ -407,34 +432,55 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Key<KB>* __restrict__ pa
 #pragma unroll
     for (int j = 0; j < J; j++) {
         const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
-        if (idx < n) tile_insert<KB, J>(L, k[j], idx);
+        if (idx < n) merge_insert<KB>(L, k[j], idx);
     }
     __syncthreads();
-    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock)  // compact: occupied slots
-        if (L.owner[s] != kEmpty) L.cnt[s] |= atomicAdd(&nloc, 1u) << 16;      // rank in the high half
+    uint32_t mine = 0;                            // entries this thread will emit
+    for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) mine += L.slot[s] != kEmpty;
+    uint32_t rank = atomicAdd(&nloc, mine);
     __syncthreads();
     if (threadIdx.x == 0) base = atomicAdd(del ? &meta->n_del : &meta->n_ins, nloc);
     __syncthreads();
-    const uint32_t d = SF_ROWS(D, g);
-    for (uint32_t s = threadIdx.x; s < TileLDS<KB, J>::kSlots; s += kBlock) {
-        const uint32_t o = L.owner[s];
-        if (o == kEmpty) continue;
-        const uint32_t v = L.cnt[s];
-        const uint32_t rank = base + (v >> 16);
+    rank += base;
+    for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
+        const uint32_t v = L.slot[s];
+        if (v == kEmpty) continue;
         const uint32_t id = del ? cap - 1 - rank : rank;
-        const Key<KB> key = L.key[o];
-        ent_key[id] = key;
+        rank++;
+        ent_key[id] = L.key[v >> 16];
         ent_cnt[id] = v & 0xffffu;
-        if (del) continue;
-        const Mixed<KB> mx(key);
+    }
+}
+
+// S1 over merged insert entries: Slim and Fat counters before the batch.
+template <int KB, int D>
+__global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __restrict__ meta,
+                                                             const Key<KB>* __restrict__ ent_key, Geom g,
+                                                             const uint32_t* __restrict__ fat,
+                                                             const uint32_t* __restrict__ slim,
+                                                             uint32_t* __restrict__ bpre,
+                                                             uint16_t* __restrict__ asnap, uint32_t stride) {
+    constexpr int R = D ? D : kMaxD;
+    const uint32_t n = meta->n_ins;
+    const uint32_t d = SF_ROWS(D, g);
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
+        const Mixed<KB> mx(ent_key[e]);
+        uint32_t av[R], bv[R];
 #pragma unroll
-        for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
-            if (i < d) {
+        for (int i = 0; i < R; i++) {
+            if (uint32_t(i) < d) {
                 uint32_t h, f;
                 split(g, mx.row(g.seed_base + i), h, f);
                 const size_t cell = size_t(i) * g.w + h;
-                asnap[size_t(i) * stride + id] = uint16_t(slim[cell]);
-                bpre[size_t(i) * stride + id] = fat[cell * g.z + f];
+                av[i] = slim[cell];
+                bv[i] = fat[cell * g.z + f];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            if (uint32_t(i) < d) {
+                asnap[size_t(i) * stride + e] = uint16_t(av[i]);
+                bpre[size_t(i) * stride + e] = bv[i];
             }
         }
     }

@@ -92,14 +92,22 @@ void launch_merged(sf_sketch* s, const UniformPlan<KB>& plan, uint32_t cnt, bool
     const unsigned pt = blocks_for(cnt, kPartOps);
     const unsigned eg = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
     {
-        Timed tm(&s->prof, st, SF_K_MERGE, cnt);
+        Timed tm(&s->prof, st, SF_K_PARTITION, cnt);
         k_part_count<KB, UniformPlan<KB>><<<pt, kBlock, 0, st>>>(plan, s->meta);
         k_part_start<KB><<<1, 2 * kBuckets, 0, st>>>(s->meta);
         k_part_scatter<KB, UniformPlan<KB>><<<pt, kBlock, 0, st>>>(plan, s->meta, part);
-        k_merge<KB, D><<<blocks_for(cnt, MergeShape<KB>::kChunk) + 2 * kBuckets, kBlock, 0, st>>>(
-            part, s->meta, ek, s->ent_cnt, s->stride, s->g, s->fat, s->slim, s->bpre, s->asnap, s->stride);
+    }
+    {
+        Timed tm(&s->prof, st, SF_K_MERGE, cnt);
+        k_merge<KB><<<blocks_for(cnt, MergeShape<KB>::kChunk) + 2 * kBuckets, kBlock, 0, st>>>(
+            part, s->meta, ek, s->ent_cnt, s->stride);
     }
     if (ins) {
+        {
+            Timed tm(&s->prof, st, SF_K_SNAPSHOT, cnt);
+            k_entries_snapshot<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->g, s->fat, s->slim, s->bpre,
+                                                             s->asnap, s->stride);
+        }
         {
             Timed tm(&s->prof, st, SF_K_FAT_ADD, cnt);
             k_entries_fat<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->ent_cnt, s->stride, s->g, s->fat, 0u);
