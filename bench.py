@@ -45,38 +45,36 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kind: str, d: int, n_ins: int, n_del: int, n_ops: int, mixed: bool,
-                      n_q: int, cells: int) -> int:
-    """Bytes a kernel's step must move, each access counted at its element size
-    (uint32 key, uint32 Slim working cell, uint32 Fat counter, 16 B Fat bucket,
-    the snapshot the batch schedule defines, 1 B op code when ops are mixed)."""
-    op_byte = n_ops if mixed else 0
-    if kind == "snapshot":   # key, Slim cell, Fat counter; snapshot write 4 + 2 B per row
-        return n_ins * (4 + d * (4 + 4 + 4 + 2)) + op_byte
-    if kind == "fat_add":    # key, Fat read-modify-write
-        return n_ins * (4 + d * 8) + op_byte
-    if kind == "raise":      # key, Fat counter, snapshot read 4 + 2 B per row
-        return n_ins * (4 + d * (4 + 4 + 2)) + op_byte
-    if kind == "fat_sub":
-        return n_del * (4 + d * 8) + op_byte
-    if kind == "clamp":      # key, 16-B bucket, Slim cell
-        return n_del * (4 + d * (16 + 4)) + op_byte
-    if kind == "query":      # key, d Slim cells, answer
-        return n_q * (4 + d * 4 + 4)
-    if kind == "export":     # uint32 working cell in, uint16 out
-        return cells * 6
-    if kind == "partition":  # keys read twice (count, scatter), partitioned copy written
-        return (n_ins + n_del) * 12 + 2 * op_byte
-    if kind == "merge":      # partitioned key read, entry (key, count) written
-        return (n_ins + n_del) * 12
-    return 0
+def algorithmic_bytes(kind: str, d: int, u: dict) -> int:
+    """Bytes one kernel kind's step must move over the timed steps, each access counted
+    at its element size.  u holds the units: ins / dels / ops (op counts), q (queries),
+    ie / de (merged insert / delete entries; equal to ins / dels when merging per tile),
+    cells, mixed (1 B op code per op)."""
+    ob = u["ops"] if u["mixed"] else 0
+    return {
+        "partition": (u["ins"] + u["dels"]) * 12 + 2 * ob,   # keys read twice, partitioned copy written
+        "merge": (u["ins"] + u["dels"]) * 4 + (u["ie"] + u["de"]) * 8,  # partitioned keys in, entries out
+        "snapshot": u["ie"] * (4 + d * (4 + 4 + 4 + 2)),     # key, Slim cell, Fat counter, snapshot out
+        "fat_add": u["ie"] * (8 + d * 8),                    # key + count, Fat read-modify-write
+        "raise": u["ie"] * (4 + d * (4 + 4 + 2)),            # key, Fat counter, snapshot in
+        "fat_sub": u["de"] * (8 + d * 8),
+        "clamp": u["de"] * (4 + d * (16 + 4)),               # key, 16-B bucket, Slim cell
+        "query": u["q"] * (4 + d * 4 + 4),                   # key, d Slim cells, answer
+        "export": u["cells"] * 6,                            # 4-B working cell in, 2-B cell out
+    }.get(kind, 0)
 
 
-# random accesses per unit of each kernel (reads + atomics, merged duplicates not subtracted)
-def random_accesses(kind: str, d: int, n_ins: int, n_del: int, n_q: int) -> int:
-    return {"snapshot": 2 * d * n_ins, "fat_add": d * n_ins, "raise": d * n_ins,
-            "fat_sub": d * n_del, "clamp": 2 * d * n_del, "query": d * n_q,
-            }.get(kind, 0)
+def random_accesses(kind: str, d: int, u: dict) -> int:
+    """Random (uncoalesced) accesses of a kernel kind over the timed steps."""
+    return {"snapshot": 2 * d * u["ie"], "fat_add": d * u["ie"], "raise": d * u["ie"],
+            "fat_sub": d * u["de"], "clamp": 2 * d * u["de"], "query": d * u["q"]}.get(kind, 0)
+
+
+def step_algorithmic_bytes(d: int, n_ins: int, n_del: int, n_q: int) -> int:
+    """The method's own bytes per op, whatever the implementation: an insert touches the
+    key, d Fat counters (read-modify-write) and d Slim cells; a delete the key, d Fat
+    buckets and d Slim cells; a query the key and d Slim cells (uint16)."""
+    return n_ins * (4 + d * 8 + d * 2) + n_del * (4 + d * (8 + 12) + d * 2) + n_q * (4 + 2 * d)
 
 
 def stored_traffic(kernel_kind: str, workload: str):
@@ -209,6 +207,7 @@ def run_multi(args, torch, np, sf, sfgen):
     cfgs = [sf.make_config(m.d, int(m.w[i]), m.z, 4, 1, batch_for_width(int(m.w[i]))) for i in range(m.n)]
     G = sf.SketchGroup(cfgs)
     G.set_tile(args.tile)
+    G.set_merge(args.merge == "batch")
 
     def step():
         G.reset()
@@ -219,16 +218,20 @@ def run_multi(args, torch, np, sf, sfgen):
         step()
     G.sync()
     torch.cuda.synchronize()
+    ie0, de0 = G.merge_stats()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     G.sync()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    ie1, de1 = G.merge_stats()
     ms_step = el * 1e3 / args.steps
     value = (n_ops + n_q) * args.steps / el / 1e6
     sub, tiles = G.rounds()
-    log(f"[bench] group: {ms_step:.2f} ms/step, {value:.1f} M items/s ({sub} launch rounds, {tiles} tiles)")
+    entries = ((ie1 - ie0) // args.steps, (de1 - de0) // args.steps)
+    log(f"[bench] group: {ms_step:.2f} ms/step, {value:.1f} M items/s ({sub} launch rounds, {tiles} tiles, "
+        f"merged entries per step: {entries[0]} inserts, {entries[1]} deletes)")
     # per-kernel times from one profiled (eager) pass
     G.profile(True)
     G.profile_read(reset=True)
@@ -253,6 +256,7 @@ def run_multi(args, torch, np, sf, sfgen):
     lone = [sf.Sketch(c.d, c.w, c.z, batch_ops=c.batch_ops) for c in cfgs]
     for s_ in lone:
         s_.set_tile(args.tile)
+        s_.set_merge(args.merge == "batch")
     seg, qseg = m.seg.astype(np.int64), m.qseg.astype(np.int64)
 
     def lone_step():
@@ -284,8 +288,9 @@ def run_multi(args, torch, np, sf, sfgen):
         "config": {"workload": f"{m.n} SF-sketches, d=4, Fat 2^14..2^20 u32 log-uniform (z=4), "
                                "stream lengths lognormal median 200K in [10K, 4M], Zipf(1.1), 5% deletes; "
                                "one graph-captured group update, then query every stream's universe",
-                   "sketches": m.n, "ops": n_ops, "queries": n_q, "batch_ops": "16 w per sketch",
-                   "tile_ops": args.tile, "launch_rounds": sub, "scale": args.scale},
+                   "sketches": m.n, "ops": n_ops, "queries": n_q, "batch_ops": "min(16 w, 2^20) per sketch",
+                   "tile_ops": args.tile, "merge": args.merge, "launch_rounds": sub, "scale": args.scale},
+        "merged_entries_per_step": {"insert": entries[0], "delete": entries[1]},
         "one_sketch_per_launch": {"value": round(lone_value, 2), "unit": "Mitems/s",
                                   "ms_per_step": round(el1 * 1e3, 3)},
         "group_vs_lone": round(value / lone_value, 2),
@@ -333,6 +338,7 @@ def run_serve(args, torch, np, sf, sfgen):
     cfg = sf.make_config(shape["d"], shape["w"], shape["z"], 4, 1, batch_for_width(shape["w"]))
     budget = 64 << 30
     pool = sf.SketchPool(cfg, hbm_budget_bytes=budget)
+    pool.set_merge(args.merge == "batch")
     slots, _ = pool.capacity()
     dev = torch.device("cuda:0")
     keys = torch.from_numpy(w.pool.view(np.int32)).to(dev)
@@ -469,6 +475,7 @@ def main():
     log(f"[bench] warmup {args.warmup} done")
     sk.profile(True)
     sk.profile_read(reset=True)
+    ie0, de0 = sk.merge_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -491,25 +498,30 @@ def main():
 
     # per-kernel accounting from the events on the sketch's stream
     kernels = {}
+    ie1, de1 = sk.merge_stats()
+    units = dict(ins=n_ins * args.steps, dels=n_del * args.steps, ops=wl.n_ops * args.steps,
+                 q=wl.n_queries * args.steps, cells=cells * args.steps, mixed=True,
+                 ie=(ie1 - ie0) if args.merge == "batch" else n_ins * args.steps,
+                 de=(de1 - de0) if args.merge == "batch" else n_del * args.steps)
     for kind, (ms, launches, _) in prof.items():
         if not launches:
             continue
-        byt = algorithmic_bytes(kind, wl.d, n_ins, n_del, wl.n_ops, True, wl.n_queries, cells) * args.steps
-        acc = random_accesses(kind, wl.d, n_ins, n_del, wl.n_queries) * args.steps
+        byt = algorithmic_bytes(kind, wl.d, units)
+        acc = random_accesses(kind, wl.d, units)
         kernels[kind] = dict(ms_total=round(ms, 3), launches=launches,
                              avg_launch_us=round(ms * 1e3 / launches, 2),
                              alg_gbs=round(byt / (ms * 1e-3) / 1e9, 1),
                              g_accesses_s=round(acc / (ms * 1e-3) / 1e9, 2) if acc else None)
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     dk = kernels[dom]
-    alg_per_launch = algorithmic_bytes(dom, wl.d, n_ins, n_del, wl.n_ops, True, wl.n_queries,
-                                       cells) * args.steps / dk["launches"]
+    alg_per_launch = algorithmic_bytes(dom, wl.d, units) / dk["launches"]
     achieved = alg_per_launch / (dk["avg_launch_us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": stored_traffic(dom, workload_tag(args))}
     log(f"[bench] kernels: {json.dumps(kernels)}")
 
+    step_bytes = step_algorithmic_bytes(wl.d, n_ins, n_del, wl.n_queries)
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mitems/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -523,6 +535,11 @@ def main():
                    "queries": wl.n_queries, "zipf_s": args.skew, "batch_ops": b, "tile_ops": args.tile, "merge": args.merge,
                    "scale": args.scale},
         "roofline": roofline,
+        "step_roofline": {"achieved": round(step_bytes / (ms_step * 1e-3) / 1e9, 1), "unit": "GB/s",
+                          "peak": HBM_PEAK_GBS,
+                          "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "bytes_per_step": step_bytes,
+                          "merged_entries_per_step": [units["ie"] // args.steps, units["de"] // args.steps]},
         "kernels": kernels,
     }
 

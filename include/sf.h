@@ -141,6 +141,10 @@ int sf_set_tile(sf_sketch *sk, uint32_t tile_ops);
  * on Zipf 0.6 .. 1.4 streams). */
 int sf_set_merge(sf_sketch *sk, int batch_wide);
 
+/* Merged entries (distinct keys per bucket chunk) the batch-wide merge has
+ * emitted since sf_create, for inserts and deletes; waits for the stream. */
+int sf_merge_stats(sf_sketch *sk, uint64_t *insert_entries, uint64_t *delete_entries);
+
 /* ---- per-kernel timing (measurement aid; off by default) ----------------
  * When enabled, every kernel the sketch launches is bracketed by two HIP
  * events recorded on the sketch's stream.  sf_profile_read waits for them
@@ -203,6 +207,13 @@ int sf_group_export_fat(sf_group *g, uint32_t i, uint32_t *out, uint64_t out_ele
 int sf_group_sync(sf_group *g);
 int sf_group_set_graph(sf_group *g, int enable);
 int sf_group_set_tile(sf_group *g, uint32_t tile_ops);
+/* As sf_set_merge, per group (default 1).  Batch-wide merging treats each
+ * (key, sketch) pair as one key; merged sub-rounds hold at most 2^22 ops
+ * (or the largest batch_ops), tiles of the per-tile path at most round_ops.
+ * Waits for the stream; the next update call re-plans. */
+int sf_group_set_merge(sf_group *g, int batch_wide);
+/* As sf_merge_stats, summed over the group's sketches. */
+int sf_group_merge_stats(sf_group *g, uint64_t *insert_entries, uint64_t *delete_entries);
 /* Sub-rounds (launch groups) and tiles of the last update call's plan. */
 int sf_group_rounds(sf_group *g, uint64_t *subrounds, uint64_t *tiles);
 int sf_group_profile(sf_group *g, int enable);
@@ -257,6 +268,11 @@ int sf_pool_export_slim(sf_pool *p, uint32_t slot, uint16_t *out, uint64_t out_e
 int sf_pool_export_fat(sf_pool *p, uint32_t slot, uint32_t *out, uint64_t out_elems);
 int sf_pool_sync(sf_pool *p);
 int sf_pool_set_tile(sf_pool *p, uint32_t tile_ops);
+/* As sf_set_merge for the pool's later launches (default 1); (key, slot)
+ * pairs are merged across a sub-round of at most 2^22 ops (or batch_ops). */
+int sf_pool_set_merge(sf_pool *p, int batch_wide);
+/* As sf_merge_stats, summed over all launches of the pool; waits for it. */
+int sf_pool_merge_stats(sf_pool *p, uint64_t *insert_entries, uint64_t *delete_entries);
 
 /* Static text of a status code. */
 const char *sf_strerror(int status);

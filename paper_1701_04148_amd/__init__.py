@@ -63,6 +63,7 @@ SIGNATURES = {
     "sf_sync": (_I, [_P]),
     "sf_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_set_merge": (_I, [_P, _I]),
+    "sf_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_profile": (_I, [_P, _I]),
     "sf_profile_read": (_I, [_P, ctypes.POINTER(sf_kernel_stats), _I]),
     "sf_group_footprint": (_U64, [ctypes.c_uint32, _CFG, _U64]),
@@ -78,6 +79,8 @@ SIGNATURES = {
     "sf_group_sync": (_I, [_P]),
     "sf_group_set_graph": (_I, [_P, _I]),
     "sf_group_set_tile": (_I, [_P, ctypes.c_uint32]),
+    "sf_group_set_merge": (_I, [_P, _I]),
+    "sf_group_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_group_rounds": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_group_profile": (_I, [_P, _I]),
     "sf_group_profile_read": (_I, [_P, ctypes.POINTER(sf_kernel_stats), _I]),
@@ -94,6 +97,8 @@ SIGNATURES = {
     "sf_pool_export_fat": (_I, [_P, ctypes.c_uint32, _P, _U64]),
     "sf_pool_sync": (_I, [_P]),
     "sf_pool_set_tile": (_I, [_P, ctypes.c_uint32]),
+    "sf_pool_set_merge": (_I, [_P, _I]),
+    "sf_pool_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_strerror": (ctypes.c_char_p, [_I]),
     "sf_last_error": (ctypes.c_char_p, []),
 }
@@ -310,6 +315,12 @@ class Sketch:
     def set_tile(self, tile_ops: int):
         sf_set_tile(self._h, tile_ops)
 
+    def merge_stats(self):
+        """(insert entries, delete entries) emitted by the batch-wide merge so far."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sf_merge_stats(self._h, ctypes.byref(a), ctypes.byref(b)), "sf_merge_stats")
+        return int(a.value), int(b.value)
+
     def set_merge(self, batch_wide: bool):
         """Merge duplicate keys across the whole batch (True, the default) or per tile (False)."""
         _check(lib().sf_set_merge(self._h, int(bool(batch_wide))), "sf_set_merge")
@@ -440,6 +451,16 @@ class SketchGroup:
     def set_tile(self, tile_ops: int):
         _check(lib().sf_group_set_tile(self._h, tile_ops), "sf_group_set_tile")
 
+    def set_merge(self, batch_wide: bool):
+        """Merge duplicate (key, sketch) pairs across each sub-round (True, the default) or per tile."""
+        _check(lib().sf_group_set_merge(self._h, int(bool(batch_wide))), "sf_group_set_merge")
+
+    def merge_stats(self):
+        """(insert entries, delete entries) emitted by the batch-wide merge so far, all sketches."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sf_group_merge_stats(self._h, ctypes.byref(a), ctypes.byref(b)), "sf_group_merge_stats")
+        return int(a.value), int(b.value)
+
     def rounds(self):
         a, b = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().sf_group_rounds(self._h, ctypes.byref(a), ctypes.byref(b)), "sf_group_rounds")
@@ -557,3 +578,13 @@ class SketchPool:
 
     def set_tile(self, tile_ops: int):
         _check(lib().sf_pool_set_tile(self._h, tile_ops), "sf_pool_set_tile")
+
+    def set_merge(self, batch_wide: bool):
+        """Merge duplicate (key, slot) pairs across each sub-round (True, the default) or per tile."""
+        _check(lib().sf_pool_set_merge(self._h, int(bool(batch_wide))), "sf_pool_set_merge")
+
+    def merge_stats(self):
+        """(insert entries, delete entries) emitted by the batch-wide merge so far, all launches."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sf_pool_merge_stats(self._h, ctypes.byref(a), ctypes.byref(b)), "sf_pool_merge_stats")
+        return int(a.value), int(b.value)

@@ -10,9 +10,16 @@
 // launch of each schedule step over a device table of tiles (ListPlan); a
 // whole update call can be captured into one hipGraph and replayed.
 //
+// By default a sub-round goes through the batch-merge path: its ops are
+// partitioned into hash buckets of (key, sketch) pairs, merged in LDS into
+// one entry per distinct pair and chunk, and S1..S5 run once per entry.
+// Merged sub-rounds hold at most kMergeRound ops (or one sketch's batch, if
+// larger) so the buckets stay about two LDS chunks long.
+//
 // Device memory (one allocation): all Fat arrays, all Slim working copies,
 // the sketch table, export staging (largest sketch), the snapshot scratch
-// ([d_max][round_ops] uint32 + uint16), and a growable tile table.
+// ([d_max][round_ops] uint32 + uint16), the merge buffers (partitioned keys,
+// entries, counts for one merged sub-round) and a growable tile table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,8 +51,14 @@ struct sf_group {
     uint32_t* bpre;
     uint16_t* asnap;
     uint64_t round_ops;            // snapshot capacity in ops
+    uint64_t merge_round;          // ops of a merged sub-round (<= round_ops)
+    void* part;                    // merge buffers, merge_round entries each
+    void* ent_key;
+    uint32_t* ent_cnt;
+    MergeMeta* meta;
     uint32_t tile_j;
     bool use_graph;
+    bool merge;                    // batch-merge path (default) or per-tile merging
     // tile table (device, growable) and its pinned host staging
     TileDesc* d_tiles = nullptr;
     size_t tiles_cap = 0;
@@ -53,7 +66,11 @@ struct sf_group {
     size_t h_cap = 0;
     // the last update call's plan and its captured graph
     std::vector<TileDesc> plan;
-    std::vector<std::pair<uint32_t, uint32_t>> subrounds;  // (first tile, tiles)
+    struct SubRound {
+        uint32_t first, tiles;
+        uint64_t ops;
+    };
+    std::vector<SubRound> subrounds;
     uint32_t plan_kind = 0;
     bool plan_on_device = false;
     hipGraph_t graph = nullptr;
@@ -74,10 +91,12 @@ bool live(const sf_group* g) {
     return g && g_live.count(g);
 }
 
+constexpr uint64_t kMergeRound = 1ull << 22;
+
 struct Layout {
     std::vector<uint64_t> fat_off, slim_off;
-    uint64_t state, desc, stage, bpre, asnap, total;
-    uint64_t round_ops;
+    uint64_t state, desc, stage, bpre, asnap, part, ent_key, ent_cnt, meta, total;
+    uint64_t round_ops, merge_round;
     uint32_t d_max;
 };
 
@@ -118,6 +137,16 @@ int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) 
     off += round256(uint64_t(L.d_max) * L.round_ops * 4);
     L.asnap = off;
     off += round256(uint64_t(L.d_max) * L.round_ops * 2);
+    L.merge_round = std::max(std::min(L.round_ops, kMergeRound), max_b);
+    const uint64_t mkey = cfgs[0].key_bytes == 4 ? sizeof(MKey<4, true>) : sizeof(MKey<13, true>);
+    L.part = off;
+    off += round256(L.merge_round * mkey);
+    L.ent_key = off;
+    off += round256(L.merge_round * mkey);
+    L.ent_cnt = off;
+    off += round256(L.merge_round * 4);
+    L.meta = off;
+    off += round256(sizeof(MergeMeta));
     L.total = off;
     return SF_OK;
 }
@@ -168,11 +197,13 @@ int check_segments(const sf_group* g, const uint64_t* seg) {
 }
 
 // Cut every sketch's ops into its own batches; round k = batch k of every
-// sketch; rounds split into sub-rounds of at most round_ops ops.
+// sketch; rounds split into sub-rounds of at most round_ops ops (merged:
+// merge_round ops, tiles of kPartOps ops for the partition kernels).
 void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uint8_t* ops, uint32_t mode) {
     g->plan.clear();
     g->subrounds.clear();
-    const uint32_t tile_ops = uint32_t(kBlock) * g->tile_j;
+    const uint32_t tile_ops = g->merge ? kPartOps : uint32_t(kBlock) * g->tile_j;
+    const uint64_t limit = g->merge ? g->merge_round : g->round_ops;
     uint64_t rounds = 0;
     for (uint32_t s = 0; s < g->n; s++) {
         const uint64_t len = seg[s + 1] - seg[s], b = g->cfg[s].batch_ops;
@@ -186,8 +217,8 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
             const uint64_t lo = seg[s] + k * b;
             if (lo >= seg[s + 1]) continue;
             const uint64_t cnt = std::min(b, seg[s + 1] - lo);
-            if (used + cnt > g->round_ops) {  // close the sub-round
-                g->subrounds.emplace_back(first, uint32_t(g->plan.size()) - first);
+            if (used + cnt > limit) {  // close the sub-round
+                g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used});
                 first = uint32_t(g->plan.size());
                 used = 0;
             }
@@ -203,19 +234,29 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
             }
             used += cnt;
         }
-        if (uint32_t(g->plan.size()) > first) g->subrounds.emplace_back(first, uint32_t(g->plan.size()) - first);
+        if (uint32_t(g->plan.size()) > first) g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used});
     }
 }
 
 template <int KB>
 void launch_plan(sf_group* g, bool ins, bool del, Profiler* prof) {
+    const MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(g->part), static_cast<MKey<KB, true>*>(g->ent_key),
+                                 g->ent_cnt, g->meta, uint32_t(g->merge_round), g->bpre, g->asnap,
+                                 uint32_t(g->round_ops)};
+    const SketchTable table{g->d_desc};
     for (auto& sr : g->subrounds) {
         const ListPlan<KB> plan{g->d_tiles + sr.first, g->d_desc};
-        uint64_t items = 0;
-        if (prof)
-            for (uint32_t t = 0; t < sr.second; t++) items += g->plan[sr.first + t].count;
-        Steps<ListPlan>::by_rows<KB>(g->d_uniform, g->tile_j, plan, sr.second, ins, del, g->bpre, g->asnap,
-                                    uint32_t(g->round_ops), g->stream, prof, items);
+        const uint32_t cnt = uint32_t(sr.ops);
+        if (!g->merge) {
+            Steps<ListPlan>::by_rows<KB>(g->d_uniform, g->tile_j, plan, sr.tiles, ins, del, g->bpre, g->asnap,
+                                        uint32_t(g->round_ops), g->stream, prof, cnt);
+        } else if (g->d_uniform == 4) {
+            run.template launch<4>(plan, sr.tiles, cnt, table, ins, del, g->stream, prof);
+        } else if (g->d_uniform == 8) {
+            run.template launch<8>(plan, sr.tiles, cnt, table, ins, del, g->stream, prof);
+        } else {
+            run.template launch<0>(plan, sr.tiles, cnt, table, ins, del, g->stream, prof);
+        }
     }
 }
 
@@ -327,8 +368,10 @@ int sf_group_create(uint32_t n, const sf_config* cfgs, uint64_t round_ops, uint6
         g->own_stream = true;
     }
     g->round_ops = L.round_ops;
+    g->merge_round = L.merge_round;
     g->tile_j = 8;
     g->use_graph = true;
+    g->merge = true;
     g->state_bytes = L.state;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->base), L.total);
     if (e != hipSuccess) {
@@ -348,8 +391,13 @@ int sf_group_create(uint32_t n, const sf_config* cfgs, uint64_t round_ops, uint6
     g->stage = reinterpret_cast<uint16_t*>(g->base + L.stage);
     g->bpre = reinterpret_cast<uint32_t*>(g->base + L.bpre);
     g->asnap = reinterpret_cast<uint16_t*>(g->base + L.asnap);
+    g->part = g->base + L.part;
+    g->ent_key = g->base + L.ent_key;
+    g->ent_cnt = reinterpret_cast<uint32_t*>(g->base + L.ent_cnt);
+    g->meta = reinterpret_cast<MergeMeta*>(g->base + L.meta);
     e = hipMemcpy(g->d_desc, g->desc.data(), n * sizeof(SketchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemsetAsync(g->base, 0, L.state, g->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g->meta, 0, sizeof(MergeMeta), g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) {
         (void)hipFree(g->base);
@@ -494,6 +542,27 @@ int sf_group_set_tile(sf_group* g, uint32_t tile_ops) {
     g->tile_j = tile_ops / kBlock;
     drop_graph(g);
     g->plan_on_device = false;
+    return SF_OK;
+}
+
+int sf_group_set_merge(sf_group* g, int batch_wide) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return device_fail(e, "group sync");
+    g->merge = batch_wide != 0;
+    drop_graph(g);
+    g->plan_on_device = false;
+    return SF_OK;
+}
+
+int sf_group_merge_stats(sf_group* g, uint64_t* insert_entries, uint64_t* delete_entries) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    unsigned long long acc[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(acc, &g->meta->acc_ins, sizeof(acc), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return device_fail(e, "sf_group_merge_stats");
+    if (insert_entries) *insert_entries = acc[0];
+    if (delete_entries) *delete_entries = acc[1];
     return SF_OK;
 }
 

@@ -200,6 +200,66 @@ void launch_steps(const P& plan, unsigned tiles, bool ins, bool del, uint32_t* b
 }
 
 // Dispatch of (key width, rows, tile) to kernel instantiations.
+// The batch-merge path of one schedule batch (or round): partition the ops
+// into hash buckets, merge each bucket chunk in LDS into entries, then S1..S5
+// once per entry.  G: the merged key carries its sketch's index.
+template <int KB, bool G>
+struct MergeRun {
+    MKey<KB, G>* part;     // [cap] partitioned keys
+    MKey<KB, G>* ent_key;  // [cap] entries: inserts from 0 up, deletes from cap-1 down
+    uint32_t* ent_cnt;     // [cap]
+    MergeMeta* meta;
+    uint32_t cap;
+    uint32_t* bpre;        // [d][stride] S1 snapshot of Fat counters, per insert entry
+    uint16_t* asnap;       // [d][stride] S1 snapshot of Slim counters, per insert entry
+    uint32_t stride;
+
+    // part_groups: workgroups of the partition kernels (plan tiles of at most
+    // kPartOps ops); cnt: ops in the batch (<= cap).
+    template <int D, class P, class SR>
+    void launch(const P& plan, unsigned part_groups, uint32_t cnt, const SR& sr, bool ins, bool del,
+                hipStream_t st, Profiler* prof) const {
+        const uint32_t nb = buckets_for<KB, G>(cnt);
+        const uint32_t nb_log2 = uint32_t(__builtin_ctz(nb));
+        const unsigned eg = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
+        {
+            Timed tm(prof, st, SF_K_PARTITION, cnt);
+            k_part_count<KB, G, P><<<part_groups, kBlock, 0, st>>>(plan, meta, nb_log2);
+            k_part_start<KB, G><<<1, 2 * nb, 0, st>>>(meta);
+            k_part_scatter<KB, G, P><<<part_groups, kBlock, 0, st>>>(plan, meta, part, nb_log2);
+        }
+        {
+            Timed tm(prof, st, SF_K_MERGE, cnt);
+            k_merge<KB, G><<<blocks_for(cnt, MergeShape<KB, G>::kChunk) + 2 * nb, kBlock, 0, st>>>(
+                part, meta, ent_key, ent_cnt, cap, nb_log2);
+        }
+        if (ins) {
+            {
+                Timed tm(prof, st, SF_K_SNAPSHOT, cnt);
+                k_entries_snapshot<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, sr, bpre, asnap, stride);
+            }
+            {
+                Timed tm(prof, st, SF_K_FAT_ADD, cnt);
+                k_entries_fat<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, ent_cnt, cap, sr, 0u);
+            }
+            {
+                Timed tm(prof, st, SF_K_RAISE, cnt);
+                k_entries_raise<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, sr, bpre, asnap, stride);
+            }
+        }
+        if (del) {
+            {
+                Timed tm(prof, st, SF_K_FAT_SUB, cnt);
+                k_entries_fat<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, ent_cnt, cap, sr, 1u);
+            }
+            {
+                Timed tm(prof, st, SF_K_CLAMP, cnt);
+                k_entries_clamp<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, cap, sr);
+            }
+        }
+    }
+};
+
 template <template <int> class PT>
 struct Steps {
     template <int KB, int D>

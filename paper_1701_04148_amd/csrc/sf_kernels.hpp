@@ -29,6 +29,7 @@ struct Work {
     uint32_t count;       // ops (or query keys) in the tile
     uint32_t scr;         // snapshot index of the tile's first op
     uint32_t mode;        // OpMode
+    uint32_t sketch;      // index of the tile's sketch in its table (0 for a lone sketch)
     Geom g;
     uint32_t* fat;
     void* slim;           // uint32 working copy (updates) or uint16 export (collector queries)
@@ -47,7 +48,7 @@ template <int KB> struct UniformPlan {
         const uint32_t first = blk * tile_ops;
         const uint32_t rest = cnt - first;
         return Work{keys + size_t(first) * KB, ops ? ops + first : nullptr, out ? out + first : nullptr,
-                    rest < tile_ops ? rest : tile_ops, first, mode, g, fat, slim};
+                    rest < tile_ops ? rest : tile_ops, first, mode, 0u, g, fat, slim};
     }
 };
 
@@ -73,7 +74,7 @@ template <int KB> struct ListPlan {
     __device__ __forceinline__ Work at(uint32_t blk, uint32_t) const {
         const TileDesc t = tiles[blk];
         const SketchDesc s = sketches[t.sketch];
-        return Work{t.keys, t.ops, t.out, t.count, t.scr, t.mode, s.g, s.fat, s.slim};
+        return Work{t.keys, t.ops, t.out, t.count, t.scr, t.mode, t.sketch, s.g, s.fat, s.slim};
     }
 };
 
@@ -275,39 +276,77 @@ __global__ __launch_bounds__(kBlock) void k_pack16(const T* __restrict__ in, uin
 // Batch-wide duplicate merging ("batch merge").  The tile kernels above
 // merge duplicates inside each tile only; on skewed streams most of a
 // batch's ops repeat keys seen in other tiles.  Here the batch's keys are
-// first partitioned into kBuckets hash buckets per op type, then one
-// workgroup per chunk of a bucket merges them in the LDS table, emitting one
-// entry (key, count) per distinct key of the chunk.  Insert entries grow up
-// from index 0, delete entries down from the last index, so both fit the
-// snapshot scratch of one batch.  S1 is taken while the entries are emitted;
-// S2..S5 then run once per entry.
+// first partitioned into nb hash buckets per op type, then one workgroup per
+// chunk of a bucket merges them in an LDS table, emitting one entry (key,
+// count) per distinct key of the chunk.  Insert entries grow up from index
+// 0, delete entries down from the last index, so both fit the snapshot
+// scratch of one batch.  S1..S5 then run once per entry.  In sketch groups
+// and pools the merged key carries its sketch's index (G = true) and every
+// entry kernel looks its sketch up in the table.
 // =====================================================================
 namespace sfk {
 
-constexpr uint32_t kBuckets = 256;             // per op type
+constexpr uint32_t kMaxBuckets = 512;          // per op type; the runtime nb is a power of two <= this
 constexpr uint32_t kPartOps = 8192;            // ops per partitioning workgroup
-template <int KB> struct MergeShape {          // LDS table of the merging kernel
-    static constexpr int J = KB == 4 ? 16 : 8; // 4096 (or 2048) keys per chunk
+
+template <int KB, bool G> struct MKey { Key<KB> k; };
+template <int KB> struct MKey<KB, true> { Key<KB> k; uint32_t s; };
+
+template <int KB, bool G>
+__device__ __forceinline__ MKey<KB, G> mkey(const Key<KB>& k, uint32_t sketch) {
+    MKey<KB, G> m;
+    m.k = k;
+    if constexpr (G) m.s = sketch;
+    return m;
+}
+template <int KB, bool G> __device__ __forceinline__ uint32_t mkey_sketch(const MKey<KB, G>& m) {
+    if constexpr (G) return m.s;
+    else return 0u;
+}
+template <int KB, bool G> __device__ __forceinline__ bool mkey_eq(const MKey<KB, G>& a, const MKey<KB, G>& b) {
+    if constexpr (G) return a.s == b.s && key_eq<KB>(a.k, b.k);
+    else return key_eq<KB>(a.k, b.k);
+}
+template <int KB, bool G> __device__ __forceinline__ uint32_t mkey_hash(const MKey<KB, G>& m) {
+    if constexpr (G) {
+        uint32_t h = 0x9e3779b9u;
+#pragma unroll
+        for (int j = 0; j < int(sizeof(m.k.v) / 4); j++) h = mm_round(h, mm_mix(m.k.v[j]));
+        return mm_final(mm_round(h, mm_mix(m.s)), 0u);
+    } else {
+        return slot_hash<KB>(m.k);
+    }
+}
+
+template <int KB, bool G> struct MergeShape {  // LDS table of the merging kernel
+    // 4096 uint32 keys or 2048 13-byte keys per chunk: 48..68 KB of LDS
+    static constexpr int J = KB == 4 ? 16 : 8;
     static constexpr uint32_t kChunk = uint32_t(kBlock) * J;
     static constexpr uint32_t kSlots = 2 * kChunk;
 };
 
+// Bucket count for a batch of cnt ops: about two chunks of ops per bucket.
+template <int KB, bool G> __host__ __device__ inline uint32_t buckets_for(uint64_t cnt) {
+    uint32_t nb = 16;
+    while (nb < kMaxBuckets && uint64_t(nb) * 2 * MergeShape<KB, G>::kChunk < cnt) nb <<= 1;
+    return nb;
+}
+
 // The merge table packs a slot's owner (local key index) and count into one
-// word -- owner in the high half, count in the low half -- so a 4096-key chunk
-// needs 48 KB of LDS (3 workgroups per CU).
-template <int KB> struct MergeLDS {
-    Key<KB> key[MergeShape<KB>::kChunk];
-    uint32_t slot[MergeShape<KB>::kSlots];
+// word -- owner in the high half, count in the low half.
+template <int KB, bool G> struct MergeLDS {
+    MKey<KB, G> key[MergeShape<KB, G>::kChunk];
+    uint32_t slot[MergeShape<KB, G>::kSlots];
 };
 
-template <int KB>
-__device__ __forceinline__ void merge_insert(MergeLDS<KB>& L, const Key<KB>& k, uint32_t idx) {
-    constexpr uint32_t mask = MergeShape<KB>::kSlots - 1;
-    uint32_t s = slot_hash<KB>(k) & mask;
-    for (uint32_t probe = 0; probe < MergeShape<KB>::kSlots; probe++) {
+template <int KB, bool G>
+__device__ __forceinline__ void merge_insert(MergeLDS<KB, G>& L, const MKey<KB, G>& k, uint32_t idx) {
+    constexpr uint32_t mask = MergeShape<KB, G>::kSlots - 1;
+    uint32_t s = mkey_hash<KB, G>(k) & mask;
+    for (uint32_t probe = 0; probe < MergeShape<KB, G>::kSlots; probe++) {
         const uint32_t prev = atomicCAS(&L.slot[s], kEmpty, (idx << 16) | 1u);
         if (prev == kEmpty) return;
-        if (key_eq<KB>(L.key[prev >> 16], k)) {
+        if (mkey_eq<KB, G>(L.key[prev >> 16], k)) {
             atomicAdd(&L.slot[s], 1u);  // count < 2^16: never carries into the owner
             return;
         }
@@ -315,44 +354,51 @@ __device__ __forceinline__ void merge_insert(MergeLDS<KB>& L, const Key<KB>& k, 
     }
 }
 
-struct MergeMeta {                 // device-side bookkeeping of one batch
-    uint32_t total[2 * kBuckets];  // keys per bucket (zeroed again by k_part_start)
-    uint32_t start[2 * kBuckets];  // first position of each bucket in part_keys
-    uint32_t size[2 * kBuckets];
-    uint32_t cursor[2 * kBuckets]; // scatter cursors
-    uint32_t chunk0[2 * kBuckets + 1];  // first chunk of each bucket (prefix)
-    uint32_t n_ins, n_del;         // entries emitted
+struct MergeMeta {                    // device-side bookkeeping of one batch
+    uint32_t total[2 * kMaxBuckets];  // keys per bucket (zeroed again by k_part_start)
+    uint32_t start[2 * kMaxBuckets];  // first position of each bucket in the partitioned keys
+    uint32_t size[2 * kMaxBuckets];
+    uint32_t cursor[2 * kMaxBuckets]; // scatter cursors
+    uint32_t chunk0[2 * kMaxBuckets + 1];  // first chunk of each bucket (prefix)
+    uint32_t n_ins, n_del;            // entries emitted
+    unsigned long long acc_ins, acc_del;  // entries emitted since creation
 };
 
-template <int KB> __device__ __forceinline__ uint32_t bucket_of(const Key<KB>& k, bool del) {
-    return (slot_hash<KB>(k) >> 24) + (del ? kBuckets : 0u);   // top 8 bits; the table uses low bits
+// Bucket of a key: top log2(nb) bits of its hash (the LDS table uses low bits).
+template <int KB, bool G>
+__device__ __forceinline__ uint32_t bucket_of(const MKey<KB, G>& k, bool del, uint32_t nb_log2) {
+    return (mkey_hash<KB, G>(k) >> (32u - nb_log2)) + (del ? (1u << nb_log2) : 0u);
 }
 
 // Counts the ops of every bucket.
-template <int KB, class P>
-__global__ __launch_bounds__(kBlock) void k_part_count(P plan, MergeMeta* __restrict__ meta) {
-    __shared__ uint32_t hist[2 * kBuckets];
+template <int KB, bool G, class P>
+__global__ __launch_bounds__(kBlock) void k_part_count(P plan, MergeMeta* __restrict__ meta, uint32_t nb_log2) {
+    __shared__ uint32_t hist[2 * kMaxBuckets];
+    const uint32_t nbt = 2u << nb_log2;
     const Work w = plan.at(blockIdx.x, kPartOps);
-    for (uint32_t b = threadIdx.x; b < 2 * kBuckets; b += kBlock) hist[b] = 0;
+    for (uint32_t b = threadIdx.x; b < nbt; b += kBlock) hist[b] = 0;
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock)
-        atomicAdd(&hist[bucket_of<KB>(load_key<KB>(w.keys, t), is_delete(w.ops, t, w.mode))], 1u);
+    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock) {
+        const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
+        atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u);
+    }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < 2 * kBuckets; b += kBlock)
+    for (uint32_t b = threadIdx.x; b < nbt; b += kBlock)
         if (hist[b]) atomicAdd(&meta->total[b], hist[b]);
 }
 
-// One workgroup of 2*kBuckets threads: bucket starts, cursors and chunk
-// prefix; clears the totals and entry counters for the next batch.
-template <int KB>
-__global__ __launch_bounds__(2 * kBuckets) void k_part_start(MergeMeta* __restrict__ meta) {
-    __shared__ uint32_t a[2 * kBuckets], c[2 * kBuckets];
-    const uint32_t b = threadIdx.x;
+// One workgroup of 2*nb threads: bucket starts, cursors and chunk prefix;
+// clears the totals and the entry counters for the next batch.
+template <int KB, bool G>
+__global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __restrict__ meta) {
+    constexpr uint32_t chunk = MergeShape<KB, G>::kChunk;
+    __shared__ uint32_t a[2 * kMaxBuckets], c[2 * kMaxBuckets];
+    const uint32_t b = threadIdx.x, nbt = blockDim.x;
     const uint32_t sz = meta->total[b];
     a[b] = sz;
-    c[b] = (sz + MergeShape<KB>::kChunk - 1) / MergeShape<KB>::kChunk;
+    c[b] = (sz + chunk - 1) / chunk;
     __syncthreads();
-    for (uint32_t off = 1; off < 2 * kBuckets; off <<= 1) {  // inclusive scans
+    for (uint32_t off = 1; off < nbt; off <<= 1) {  // inclusive scans
         const uint32_t va = b >= off ? a[b - off] : 0u, vc = b >= off ? c[b - off] : 0u;
         __syncthreads();
         a[b] += va;
@@ -372,54 +418,58 @@ __global__ __launch_bounds__(2 * kBuckets) void k_part_start(MergeMeta* __restri
 }
 
 // Scatters the keys into their buckets (order inside a bucket is free).
-template <int KB, class P>
+template <int KB, bool G, class P>
 __global__ __launch_bounds__(kBlock) void k_part_scatter(P plan, MergeMeta* __restrict__ meta,
-                                                         Key<KB>* __restrict__ part) {
-    __shared__ uint32_t hist[2 * kBuckets];
+                                                         MKey<KB, G>* __restrict__ part, uint32_t nb_log2) {
+    __shared__ uint32_t hist[2 * kMaxBuckets];
+    const uint32_t nbt = 2u << nb_log2;
     const Work w = plan.at(blockIdx.x, kPartOps);
-    for (uint32_t b = threadIdx.x; b < 2 * kBuckets; b += kBlock) hist[b] = 0;
+    for (uint32_t b = threadIdx.x; b < nbt; b += kBlock) hist[b] = 0;
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock)
-        atomicAdd(&hist[bucket_of<KB>(load_key<KB>(w.keys, t), is_delete(w.ops, t, w.mode))], 1u);
+    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock) {
+        const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
+        atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u);
+    }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < 2 * kBuckets; b += kBlock)
+    for (uint32_t b = threadIdx.x; b < nbt; b += kBlock)
         if (hist[b]) hist[b] = atomicAdd(&meta->cursor[b], hist[b]);  // this group's first position
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < w.count; t += kBlock) {
-        const Key<KB> k = load_key<KB>(w.keys, t);
-        part[atomicAdd(&hist[bucket_of<KB>(k, is_delete(w.ops, t, w.mode))], 1u)] = k;
+        const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
+        part[atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u)] = k;
     }
 }
 
 // Merges one chunk of one bucket and emits its entries (key, count).
 // cap = entry capacity (insert entries at [0, n_ins), delete entries at
 // [cap - n_del, cap)).
-template <int KB>
-__global__ __launch_bounds__(kBlock) void k_merge(const Key<KB>* __restrict__ part, MergeMeta* __restrict__ meta,
-                                                  Key<KB>* __restrict__ ent_key, uint32_t* __restrict__ ent_cnt,
-                                                  uint32_t cap) {
-    constexpr int J = MergeShape<KB>::J;
-    constexpr uint32_t kChunk = MergeShape<KB>::kChunk, kSlots = MergeShape<KB>::kSlots;
-    __shared__ MergeLDS<KB> L;
-    __shared__ uint32_t chunk0[2 * kBuckets + 1];
+template <int KB, bool G>
+__global__ __launch_bounds__(kBlock) void k_merge(const MKey<KB, G>* __restrict__ part,
+                                                  MergeMeta* __restrict__ meta, MKey<KB, G>* __restrict__ ent_key,
+                                                  uint32_t* __restrict__ ent_cnt, uint32_t cap, uint32_t nb_log2) {
+    constexpr int J = MergeShape<KB, G>::J;
+    constexpr uint32_t kChunk = MergeShape<KB, G>::kChunk, kSlots = MergeShape<KB, G>::kSlots;
+    __shared__ MergeLDS<KB, G> L;
+    __shared__ uint32_t chunk0[2 * kMaxBuckets + 1];
     __shared__ uint32_t nloc, base;
+    const uint32_t nbt = 2u << nb_log2;
     const uint32_t c = blockIdx.x;
-    if (c >= meta->chunk0[2 * kBuckets]) return;
-    for (uint32_t i = threadIdx.x; i <= 2 * kBuckets; i += kBlock) chunk0[i] = meta->chunk0[i];
+    if (c >= meta->chunk0[nbt]) return;
+    for (uint32_t i = threadIdx.x; i <= nbt; i += kBlock) chunk0[i] = meta->chunk0[i];
     for (uint32_t i = threadIdx.x; i < kSlots; i += kBlock) L.slot[i] = kEmpty;
     if (threadIdx.x == 0) nloc = 0;
     __syncthreads();
-    uint32_t lo = 0, hi = 2 * kBuckets;           // bucket b with chunk0[b] <= c < chunk0[b+1]
+    uint32_t lo = 0, hi = nbt;                    // bucket b with chunk0[b] <= c < chunk0[b+1]
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
         if (chunk0[mid] <= c) lo = mid; else hi = mid;
     }
     const uint32_t b = lo;
-    const bool del = b >= kBuckets;
+    const bool del = b >= (nbt >> 1);
     const uint32_t first = meta->start[b] + (c - chunk0[b]) * kChunk;
     const uint32_t end = meta->start[b] + meta->size[b];
     const uint32_t n = end - first < kChunk ? end - first : kChunk;
-    Key<KB> k[J];
+    MKey<KB, G> k[J];
 #pragma unroll
     for (int j = 0; j < J; j++) {
         const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
@@ -432,14 +482,17 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Key<KB>* __restrict__ pa
 #pragma unroll
     for (int j = 0; j < J; j++) {
         const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
-        if (idx < n) merge_insert<KB>(L, k[j], idx);
+        if (idx < n) merge_insert<KB, G>(L, k[j], idx);
     }
     __syncthreads();
     uint32_t mine = 0;                            // entries this thread will emit
     for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) mine += L.slot[s] != kEmpty;
     uint32_t rank = atomicAdd(&nloc, mine);
     __syncthreads();
-    if (threadIdx.x == 0) base = atomicAdd(del ? &meta->n_del : &meta->n_ins, nloc);
+    if (threadIdx.x == 0) {
+        base = atomicAdd(del ? &meta->n_del : &meta->n_ins, nloc);
+        atomicAdd(del ? &meta->acc_del : &meta->acc_ins, (unsigned long long)nloc);
+    }
     __syncthreads();
     rank += base;
     for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
@@ -452,28 +505,40 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Key<KB>* __restrict__ pa
     }
 }
 
+// Where an entry's sketch lives: one sketch, or a table of them.
+struct OneSketch {
+    Geom g;
+    uint32_t* fat;
+    uint32_t* slim;
+    __device__ __forceinline__ SketchDesc of(uint32_t) const { return SketchDesc{g, fat, slim}; }
+};
+struct SketchTable {
+    const SketchDesc* t;
+    __device__ __forceinline__ SketchDesc of(uint32_t s) const { return t[s]; }
+};
+
 // S1 over merged insert entries: Slim and Fat counters before the batch.
-template <int KB, int D>
+template <int KB, int D, bool G, class SR>
 __global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __restrict__ meta,
-                                                             const Key<KB>* __restrict__ ent_key, Geom g,
-                                                             const uint32_t* __restrict__ fat,
-                                                             const uint32_t* __restrict__ slim,
+                                                             const MKey<KB, G>* __restrict__ ent_key, SR sr,
                                                              uint32_t* __restrict__ bpre,
                                                              uint16_t* __restrict__ asnap, uint32_t stride) {
     constexpr int R = D ? D : kMaxD;
     const uint32_t n = meta->n_ins;
-    const uint32_t d = SF_ROWS(D, g);
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
-        const Mixed<KB> mx(ent_key[e]);
+        const MKey<KB, G> m = ent_key[e];
+        const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
+        const uint32_t d = SF_ROWS(D, sd.g);
+        const Mixed<KB> mx(m.k);
         uint32_t av[R], bv[R];
 #pragma unroll
         for (int i = 0; i < R; i++) {
             if (uint32_t(i) < d) {
                 uint32_t h, f;
-                split(g, mx.row(g.seed_base + i), h, f);
-                const size_t cell = size_t(i) * g.w + h;
-                av[i] = slim[cell];
-                bv[i] = fat[cell * g.z + f];
+                split(sd.g, mx.row(sd.g.seed_base + i), h, f);
+                const size_t cell = size_t(i) * sd.g.w + h;
+                av[i] = sd.slim[cell];
+                bv[i] = sd.fat[cell * sd.g.z + f];
             }
         }
 #pragma unroll
@@ -487,41 +552,43 @@ __global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __
 }
 
 // S2 / S4 over merged entries: one atomic per entry and row carrying its count.
-template <int KB, int D>
+template <int KB, int D, bool G, class SR>
 __global__ __launch_bounds__(kBlock) void k_entries_fat(const MergeMeta* __restrict__ meta,
-                                                        const Key<KB>* __restrict__ ent_key,
+                                                        const MKey<KB, G>* __restrict__ ent_key,
                                                         const uint32_t* __restrict__ ent_cnt, uint32_t cap,
-                                                        Geom g, uint32_t* __restrict__ fat, uint32_t del) {
+                                                        SR sr, uint32_t del) {
     const uint32_t n = del ? meta->n_del : meta->n_ins;
-    const uint32_t d = SF_ROWS(D, g);
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
         const uint32_t id = del ? cap - 1 - e : e;
         const uint32_t v = del ? 0u - ent_cnt[id] : ent_cnt[id];
-        const Mixed<KB> mx(ent_key[id]);
+        const MKey<KB, G> m = ent_key[id];
+        const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
+        const uint32_t d = SF_ROWS(D, sd.g);
+        const Mixed<KB> mx(m.k);
 #pragma unroll
         for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
             if (i < d) {
                 uint32_t h, f;
-                split(g, mx.row(g.seed_base + i), h, f);
-                atomic_add_u32(&fat[(size_t(i) * g.w + h) * g.z + f], v);
+                split(sd.g, mx.row(sd.g.seed_base + i), h, f);
+                atomic_add_u32(&sd.fat[(size_t(i) * sd.g.w + h) * sd.g.z + f], v);
             }
         }
     }
 }
 
 // S3 over merged insert entries.
-template <int KB, int D>
+template <int KB, int D, bool G, class SR>
 __global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __restrict__ meta,
-                                                          const Key<KB>* __restrict__ ent_key, Geom g,
-                                                          const uint32_t* __restrict__ fat,
-                                                          uint32_t* __restrict__ slim,
+                                                          const MKey<KB, G>* __restrict__ ent_key, SR sr,
                                                           const uint32_t* __restrict__ bpre,
                                                           const uint16_t* __restrict__ asnap, uint32_t stride) {
     constexpr int R = D ? D : kMaxD;
     const uint32_t n = meta->n_ins;
-    const uint32_t d = SF_ROWS(D, g);
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
-        const Mixed<KB> mx(ent_key[e]);
+        const MKey<KB, G> m = ent_key[e];
+        const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
+        const uint32_t d = SF_ROWS(D, sd.g);
+        const Mixed<KB> mx(m.k);
         size_t cell[R];
         uint32_t a[R];
         uint32_t m0 = ~0u, bmin = ~0u, delta = ~0u;
@@ -531,10 +598,10 @@ __global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __res
             a[i] = kSlimMax;
             if (uint32_t(i) < d) {
                 uint32_t h, f;
-                split(g, mx.row(g.seed_base + i), h, f);
-                cell[i] = size_t(i) * g.w + h;
+                split(sd.g, mx.row(sd.g.seed_base + i), h, f);
+                cell[i] = size_t(i) * sd.g.w + h;
                 a[i] = asnap[size_t(i) * stride + e];
-                const uint32_t post = fat[cell[i] * g.z + f];
+                const uint32_t post = sd.fat[cell[i] * sd.g.z + f];
                 const uint32_t grew = post - bpre[size_t(i) * stride + e];
                 m0 = min(m0, a[i]);
                 bmin = min(bmin, post);
@@ -547,28 +614,29 @@ __global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __res
         const uint32_t T = uint32_t(tt < kSlimMax ? tt : kSlimMax);
 #pragma unroll
         for (int i = 0; i < R; i++)
-            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&slim[cell[i]], T);
+            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&sd.slim[cell[i]], T);
     }
 }
 
 // S5 over merged delete entries.
-template <int KB, int D>
+template <int KB, int D, bool G, class SR>
 __global__ __launch_bounds__(kBlock) void k_entries_clamp(const MergeMeta* __restrict__ meta,
-                                                          const Key<KB>* __restrict__ ent_key, uint32_t cap,
-                                                          Geom g, const uint32_t* __restrict__ fat,
-                                                          uint32_t* __restrict__ slim) {
+                                                          const MKey<KB, G>* __restrict__ ent_key, uint32_t cap,
+                                                          SR sr) {
     const uint32_t n = meta->n_del;
-    const uint32_t d = SF_ROWS(D, g);
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
-        const Mixed<KB> mx(ent_key[cap - 1 - e]);
+        const MKey<KB, G> m = ent_key[cap - 1 - e];
+        const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
+        const uint32_t d = SF_ROWS(D, sd.g);
+        const Mixed<KB> mx(m.k);
 #pragma unroll
         for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
             if (i < d) {
                 uint32_t h, f;
-                split(g, mx.row(g.seed_base + i), h, f);
-                const size_t cell = size_t(i) * g.w + h;
-                const uint32_t m = bucket_max(fat, cell, g);
-                if (slim[cell] > m) atomic_min_u32(&slim[cell], m);
+                split(sd.g, mx.row(sd.g.seed_base + i), h, f);
+                const size_t cell = size_t(i) * sd.g.w + h;
+                const uint32_t mval = bucket_max(sd.fat, cell, sd.g);
+                if (sd.slim[cell] > mval) atomic_min_u32(&sd.slim[cell], mval);
             }
         }
     }

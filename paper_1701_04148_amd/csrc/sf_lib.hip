@@ -83,51 +83,13 @@ Sizes sizes_of(const sf_config* c) {
     return s;
 }
 
-// Batch-wide merge: partition, merge (+ S1), then S2..S5 over the entries.
+// Batch-wide merge: partition, merge, then S1..S5 over the entries.
 template <int KB, int D>
 void launch_merged(sf_sketch* s, const UniformPlan<KB>& plan, uint32_t cnt, bool ins, bool del) {
-    hipStream_t st = s->stream;
-    Key<KB>* part = static_cast<Key<KB>*>(s->part);
-    Key<KB>* ek = static_cast<Key<KB>*>(s->ent_key);
-    const unsigned pt = blocks_for(cnt, kPartOps);
-    const unsigned eg = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
-    {
-        Timed tm(&s->prof, st, SF_K_PARTITION, cnt);
-        k_part_count<KB, UniformPlan<KB>><<<pt, kBlock, 0, st>>>(plan, s->meta);
-        k_part_start<KB><<<1, 2 * kBuckets, 0, st>>>(s->meta);
-        k_part_scatter<KB, UniformPlan<KB>><<<pt, kBlock, 0, st>>>(plan, s->meta, part);
-    }
-    {
-        Timed tm(&s->prof, st, SF_K_MERGE, cnt);
-        k_merge<KB><<<blocks_for(cnt, MergeShape<KB>::kChunk) + 2 * kBuckets, kBlock, 0, st>>>(
-            part, s->meta, ek, s->ent_cnt, s->stride);
-    }
-    if (ins) {
-        {
-            Timed tm(&s->prof, st, SF_K_SNAPSHOT, cnt);
-            k_entries_snapshot<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->g, s->fat, s->slim, s->bpre,
-                                                             s->asnap, s->stride);
-        }
-        {
-            Timed tm(&s->prof, st, SF_K_FAT_ADD, cnt);
-            k_entries_fat<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->ent_cnt, s->stride, s->g, s->fat, 0u);
-        }
-        {
-            Timed tm(&s->prof, st, SF_K_RAISE, cnt);
-            k_entries_raise<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->g, s->fat, s->slim, s->bpre, s->asnap,
-                                                          s->stride);
-        }
-    }
-    if (del) {
-        {
-            Timed tm(&s->prof, st, SF_K_FAT_SUB, cnt);
-            k_entries_fat<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->ent_cnt, s->stride, s->g, s->fat, 1u);
-        }
-        {
-            Timed tm(&s->prof, st, SF_K_CLAMP, cnt);
-            k_entries_clamp<KB, D><<<eg, kBlock, 0, st>>>(s->meta, ek, s->stride, s->g, s->fat, s->slim);
-        }
-    }
+    MergeRun<KB, false> run{static_cast<MKey<KB, false>*>(s->part), static_cast<MKey<KB, false>*>(s->ent_key),
+                            s->ent_cnt, s->meta, s->stride, s->bpre, s->asnap, s->stride};
+    run.template launch<D>(plan, blocks_for(cnt, kPartOps), cnt, OneSketch{s->g, s->fat, s->slim}, ins, del,
+                           s->stream, &s->prof);
 }
 
 template <int KB>
@@ -369,6 +331,17 @@ int sf_set_tile(sf_sketch* s, uint32_t tile_ops) {
 int sf_set_merge(sf_sketch* s, int batch_wide) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
     s->merge_batch = batch_wide != 0;
+    return SF_OK;
+}
+
+int sf_merge_stats(sf_sketch* s, uint64_t* insert_entries, uint64_t* delete_entries) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    unsigned long long acc[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(acc, &s->meta->acc_ins, sizeof(acc), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return device_fail(e, "sf_merge_stats");
+    if (insert_entries) *insert_entries = acc[0];
+    if (delete_entries) *delete_entries = acc[1];
     return SF_OK;
 }
 

@@ -11,6 +11,10 @@
 // the same alone and in any mix.  Launches are queued on the pool's stream
 // and complete in order; each returns a ticket backed by a HIP event.
 //
+// Update sub-rounds take the batch-merge path by default (duplicate (key,
+// slot) pairs merged across the sub-round, S1..S5 once per merged entry);
+// merged sub-rounds hold at most 2^22 ops, or one batch if larger.
+//
 // Tile descriptors of in-flight launches live in a device ring; a region is
 // reused only after the launch that reads it has completed.
 #include <hip/hip_runtime.h>
@@ -41,7 +45,13 @@ struct sf_pool {
     uint16_t* asnap;
     uint16_t* stage;
     uint64_t round_ops;
+    uint64_t merge_round;          // ops of a merged sub-round
+    void* part;                    // merge buffers, merge_round entries each
+    void* ent_key;
+    uint32_t* ent_cnt;
+    MergeMeta* meta;
     uint32_t tile_j;
+    bool merge;
     std::vector<uint8_t> in_use;
     std::vector<uint32_t> free_list;
     TileDesc* d_ring;
@@ -73,7 +83,12 @@ bool live(const sf_pool* p) {
 constexpr size_t kRingTiles = size_t(1) << 21;  // 2M tiles (80 MiB) of in-flight descriptors
 
 struct PoolLayout {
-    uint64_t slot_fat, slot_slim, per_slot, shared, round_ops;
+    uint64_t slot_fat, slot_slim, per_slot, shared, round_ops, merge_round, mkey;
+};
+
+struct SubRound {
+    uint32_t first, tiles;
+    uint64_t ops;
 };
 
 PoolLayout pool_layout(const sf_config* c, uint64_t round_ops) {
@@ -83,8 +98,11 @@ PoolLayout pool_layout(const sf_config* c, uint64_t round_ops) {
     L.slot_slim = round256(cells * 4);
     L.per_slot = L.slot_fat + L.slot_slim + round256(sizeof(SketchDesc));
     L.round_ops = std::max<uint64_t>(round_ops ? round_ops : (1ull << 24), c->batch_ops);
+    L.merge_round = std::max<uint64_t>(std::min<uint64_t>(L.round_ops, 1ull << 22), c->batch_ops);
+    L.mkey = c->key_bytes == 4 ? sizeof(MKey<4, true>) : sizeof(MKey<13, true>);
     L.shared = round256(uint64_t(c->d) * L.round_ops * 4) + round256(uint64_t(c->d) * L.round_ops * 2) +
-               round256(cells * 2) + round256(kRingTiles * sizeof(TileDesc));
+               round256(cells * 2) + round256(kRingTiles * sizeof(TileDesc)) +
+               2 * round256(L.merge_round * L.mkey) + round256(L.merge_round * 4) + round256(sizeof(MergeMeta));
     return L;
 }
 
@@ -125,20 +143,31 @@ int ring_alloc(sf_pool* p, size_t k, size_t* begin) {
 }
 
 template <int KB>
-void launch_updates(sf_pool* p, const TileDesc* d_tiles, const std::vector<std::pair<uint32_t, uint32_t>>& subs,
+void launch_updates(sf_pool* p, const TileDesc* d_tiles, const std::vector<SubRound>& subs,
                     const std::vector<TileDesc>& host) {
+    const MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(p->part), static_cast<MKey<KB, true>*>(p->ent_key),
+                                 p->ent_cnt, p->meta, uint32_t(p->merge_round), p->bpre, p->asnap,
+                                 uint32_t(p->round_ops)};
+    const SketchTable table{p->d_desc};
     for (auto& sr : subs) {
         bool ins = false, del = false;
-        uint64_t items = 0;
-        for (uint32_t t = 0; t < sr.second; t++) {
+        for (uint32_t t = 0; t < sr.tiles; t++) {
             const TileDesc& td = host[sr.first + t];
             ins = ins || td.mode != kAllDelete;
             del = del || td.mode != kAllInsert;
-            items += td.count;
         }
         const ListPlan<KB> plan{d_tiles + sr.first, p->d_desc};
-        Steps<ListPlan>::by_rows<KB>(p->cfg.d, p->tile_j, plan, sr.second, ins, del, p->bpre, p->asnap,
-                                    uint32_t(p->round_ops), p->stream, &p->prof, items);
+        const uint32_t cnt = uint32_t(sr.ops);
+        if (!p->merge) {
+            Steps<ListPlan>::by_rows<KB>(p->cfg.d, p->tile_j, plan, sr.tiles, ins, del, p->bpre, p->asnap,
+                                        uint32_t(p->round_ops), p->stream, &p->prof, cnt);
+        } else if (p->cfg.d == 4) {
+            run.template launch<4>(plan, sr.tiles, cnt, table, ins, del, p->stream, &p->prof);
+        } else if (p->cfg.d == 8) {
+            run.template launch<8>(plan, sr.tiles, cnt, table, ins, del, p->stream, &p->prof);
+        } else {
+            run.template launch<0>(plan, sr.tiles, cnt, table, ins, del, p->stream, &p->prof);
+        }
     }
 }
 
@@ -172,7 +201,9 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
     p->slot_fat = L.slot_fat;
     p->slot_slim = L.slot_slim;
     p->round_ops = L.round_ops;
+    p->merge_round = L.merge_round;
     p->tile_j = 8;
+    p->merge = true;
     p->ring_cap = kRingTiles;
     p->next_ticket = 1;
     p->stream = static_cast<hipStream_t>(hip_stream);
@@ -205,6 +236,14 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
     p->stage = reinterpret_cast<uint16_t*>(q);
     q += round256(uint64_t(cfg->d) * cfg->w * 2);
     p->d_ring = reinterpret_cast<TileDesc*>(q);
+    q += round256(kRingTiles * sizeof(TileDesc));
+    p->part = q;
+    q += round256(L.merge_round * L.mkey);
+    p->ent_key = q;
+    q += round256(L.merge_round * L.mkey);
+    p->ent_cnt = reinterpret_cast<uint32_t*>(q);
+    q += round256(L.merge_round * 4);
+    p->meta = reinterpret_cast<MergeMeta*>(q);
     p->desc.resize(slots);
     const Geom geo = geom_of(cfg);
     for (uint64_t i = 0; i < slots; i++) {
@@ -213,6 +252,8 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
         p->desc[i].slim = reinterpret_cast<uint32_t*>(p->base + i * (L.slot_fat + L.slot_slim) + L.slot_fat);
     }
     e = hipMemcpy(p->d_desc, p->desc.data(), slots * sizeof(SketchDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemsetAsync(p->meta, 0, sizeof(MergeMeta), p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         (void)hipFree(p->base);
         if (p->own_stream) (void)hipStreamDestroy(p->stream);
@@ -297,11 +338,13 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
             if ((rc = check_gpu_ptr(q.out, q.n * 4, "out"))) return rc;
         }
     }
-    // update tiles: round k = batch k of every update request; sub-rounds bounded by round_ops
-    const uint32_t tile_ops = uint32_t(kBlock) * p->tile_j;
+    // update tiles: round k = batch k of every update request; sub-rounds bounded by
+    // round_ops (merged: merge_round, tiles of kPartOps ops for the partition kernels)
+    const uint32_t tile_ops = p->merge ? kPartOps : uint32_t(kBlock) * p->tile_j;
+    const uint64_t limit = p->merge ? p->merge_round : p->round_ops;
     const uint64_t b = p->cfg.batch_ops;
     std::vector<TileDesc> tiles;
-    std::vector<std::pair<uint32_t, uint32_t>> subs;
+    std::vector<SubRound> subs;
     uint64_t rounds = 0;
     for (uint32_t r = 0; r < n; r++)
         if (reqs[r].kind != SF_REQ_QUERY) rounds = std::max(rounds, (reqs[r].n + b - 1) / b);
@@ -312,8 +355,8 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
             const sf_request& q = reqs[r];
             if (q.kind == SF_REQ_QUERY || k * b >= q.n) continue;
             const uint64_t lo = k * b, cnt = std::min(b, q.n - lo);
-            if (used + cnt > p->round_ops) {
-                subs.emplace_back(first, uint32_t(tiles.size()) - first);
+            if (used + cnt > limit) {
+                subs.push_back({first, uint32_t(tiles.size()) - first, used});
                 first = uint32_t(tiles.size());
                 used = 0;
             }
@@ -331,7 +374,7 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
             }
             used += cnt;
         }
-        if (uint32_t(tiles.size()) > first) subs.emplace_back(first, uint32_t(tiles.size()) - first);
+        if (uint32_t(tiles.size()) > first) subs.push_back({first, uint32_t(tiles.size()) - first, used});
     }
     const size_t n_update_tiles = tiles.size();
     for (uint32_t r = 0; r < n; r++) {
@@ -452,6 +495,23 @@ int sf_pool_set_tile(sf_pool* p, uint32_t tile_ops) {
     if (tile_ops != 256 && tile_ops != 1024 && tile_ops != 2048)
         return fail(SF_EINVAL, "tile_ops must be 256, 1024 or 2048");
     p->tile_j = tile_ops / kBlock;
+    return SF_OK;
+}
+
+int sf_pool_set_merge(sf_pool* p, int batch_wide) {
+    if (!live(p)) return fail(SF_ESTATE, "pool handle is not live");
+    p->merge = batch_wide != 0;
+    return SF_OK;
+}
+
+int sf_pool_merge_stats(sf_pool* p, uint64_t* insert_entries, uint64_t* delete_entries) {
+    if (!live(p)) return fail(SF_ESTATE, "pool handle is not live");
+    unsigned long long acc[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(acc, &p->meta->acc_ins, sizeof(acc), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return device_fail(e, "sf_pool_merge_stats");
+    if (insert_entries) *insert_entries = acc[0];
+    if (delete_entries) *delete_entries = acc[1];
     return SF_OK;
 }
 

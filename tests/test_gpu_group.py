@@ -38,21 +38,44 @@ def _check_group(G, m, refs):
         assert_same(ans[int(m.qseg[i]):int(m.qseg[i + 1])], refs[i][2], f"queries of sketch {i}")
 
 
+@pytest.mark.parametrize("merge", [True, False])
 @pytest.mark.parametrize("graph", [True, False])
 @pytest.mark.parametrize("round_ops", [0, 20_000])
-def test_group_matches_oracle_per_sketch(graph, round_ops):
+def test_group_matches_oracle_per_sketch(graph, round_ops, merge):
     """48 sketches of different widths, stream lengths and batch sizes, mixed ops."""
     import torch
     m = sfgen.config_multi(seed=3, n_sketches=48, length_scale=0.03, fat_log2=(8, 13))
     rng = np.random.default_rng(1)
     batch = rng.choice([700, 2048, 5000, 1 << 20], size=m.n)
     cfgs = _cfgs(m.w, np.full(m.n, 4), batch)
-    say(f"[case] group n={m.n} ops={m.keys.size} graph={graph} round_ops={round_ops}")
+    say(f"[case] group n={m.n} ops={m.keys.size} graph={graph} round_ops={round_ops} merge={merge}")
     G = sf.SketchGroup(cfgs, round_ops=round_ops)
     G.set_graph(graph)
+    G.set_merge(merge)
     G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
     sub, tiles = G.rounds()
     say(f"  sub-rounds {sub}, tiles {tiles}")
+    _check_group(G, m, _oracle_parts(m, cfgs))
+    G.close()
+
+
+def test_group_merged_subrounds():
+    """Merged sub-rounds much smaller than a round: many partition/merge passes
+    per round, (key, sketch) pairs of different sketches in one bucket."""
+    import torch
+    m = sfgen.config_multi(seed=11, n_sketches=40, length_scale=0.03, fat_log2=(8, 12))
+    rng = np.random.default_rng(4)
+    cfgs = _cfgs(m.w, np.full(m.n, 4), rng.choice([700, 2048, 5000], size=m.n))
+    say(f"[case] group merged sub-rounds n={m.n} ops={m.keys.size}")
+    G = sf.SketchGroup(cfgs, round_ops=12_000)
+    G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
+    sub, tiles = G.rounds()
+    say(f"  sub-rounds {sub}, tiles {tiles}")
+    lens = np.diff(m.seg.astype(np.int64))
+    rounds = int(np.ceil(lens / np.array([c.batch_ops for c in cfgs])).max())
+    assert sub > rounds                          # some rounds were split
+    ie, de = G.merge_stats()
+    assert 0 < ie + de <= m.keys.size
     _check_group(G, m, _oracle_parts(m, cfgs))
     G.close()
 
@@ -117,8 +140,9 @@ def test_group_equals_lone_sketches_and_tiles():
         s.sync()
         lone.append((s.export_fat(), s.export_slim(), s.query(dev_keys(q)).cpu().numpy().view(np.uint32)))
         s.close()
-    for tile in (256, 2048):
+    for merge, tile in ((True, 2048), (False, 256), (False, 2048)):
         G = sf.SketchGroup(cfgs)
+        G.set_merge(merge)
         G.set_tile(tile)
         G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
         _check_group(G, m, lone)

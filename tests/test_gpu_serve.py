@@ -19,7 +19,7 @@ def _workload(seed=1, n_streams=40, per_stream=6):
                          pool_keys=1 << 18, universe=20_000, open_window=0.02, stream_rate=400.0)
 
 
-def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15):
+def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15, merge=True):
     import torch
     pool_t = torch.from_numpy(w.pool.view(np.int32)).cuda()
     outs = {i: torch.full((r.n,), -1, dtype=torch.int32, device="cuda")
@@ -28,6 +28,7 @@ def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15):
     slims = {s: torch.zeros(CFG["d"] * CFG["w"], dtype=torch.int16, device="cuda")
              for s in range(w.n_streams)}
     pool = sf.SketchPool(sf.make_config(**CFG), max_slots=max_slots)
+    pool.set_merge(merge)
     srv = Server(pool, max_launch_keys=max_launch_keys, max_in_flight=3)
     st = srv.run(w.requests, key_of=lambda r: pool_t[r.off:r.off + r.n],
                  out_of=lambda r: outs[index[id(r)]], export_to=lambda s: slims[s], realtime=realtime)
@@ -74,11 +75,11 @@ def _oracle_stream(w, stream):
     return ref.slim(), ref.fat(), ans
 
 
-@pytest.mark.parametrize("realtime", [False, True])
-def test_alone_equals_mixed_and_oracle(realtime):
+@pytest.mark.parametrize("realtime,merge", [(False, True), (True, True), (False, False)])
+def test_alone_equals_mixed_and_oracle(realtime, merge):
     w = _workload()
-    say(f"[case] serving mix realtime={realtime}: {len(w.requests)} requests, {w.n_streams} streams")
-    st, res, ans = _run_mixed(w, max_slots=8, realtime=realtime)
+    say(f"[case] serving mix realtime={realtime} merge={merge}: {len(w.requests)} requests, {w.n_streams} streams")
+    st, res, ans = _run_mixed(w, max_slots=8, realtime=realtime, merge=merge)
     say(f"  launches {st.launches}, mean {st.mean_requests_per_launch:.1f} req/launch, "
         f"latency {st.latency_ms}, peak resident {st.peak_resident}")
     assert st.peak_resident <= 8 and st.launches > 1 and st.mean_requests_per_launch > 1
