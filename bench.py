@@ -149,6 +149,24 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
             "kernels": kernels}
 
 
+def summarize_stats(stats_csv: str) -> str:
+    """Text table of a rocprofv3 --stats kernel_stats.csv (per-kernel calls and durations)."""
+    import csv
+    rows = []
+    with open(stats_csv) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+            name = name.replace("sfk::", "").split("(")[0]
+            rows.append((name[:44], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+                         float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                         float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[2])
+    lines = [f"{'kernel':44s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'pct':>6s}"]
+    for n, c, t, a, lo, hi, pct in rows:
+        lines.append(f"{n:44s} {c:6d} {t:9.3f} {a:8.1f} {lo:8.1f} {hi:8.1f} {pct:6.2f}")
+    return "\n".join(lines)
+
+
 def workload_tag(args) -> str:
     """Name of the timed workload (sketch shape, stream, schedule, tile) for stored counters."""
     return (f"c2_d4_w{2**20 // args.scale}_z4_ops{32_000_000 // args.scale}_zipf{args.skew}_del10"
@@ -405,10 +423,15 @@ def main():
     ap.add_argument("--serve-shape", choices=tuple(SERVE_SHAPES), default="flows")
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / saturation")
     ap.add_argument("--serve-launch-keys", type=int, default=1 << 24)
+    ap.add_argument("--stats-summary", metavar="STATS_CSV",
+                    help="print a rocprofv3 --stats kernel table and exit")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_traffic.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
 
+    if args.stats_summary:
+        print(summarize_stats(args.stats_summary))
+        return
     if args.pmc_summary:
         rec = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], workload_tag(args),
                             args.copy_calibration_mib << 20)

@@ -224,13 +224,13 @@ struct MergeRun {
         const unsigned eg = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
         {
             Timed tm(prof, st, SF_K_PARTITION, cnt);
-            k_part_count<KB, G, P><<<part_groups, kBlock, 0, st>>>(plan, meta, nb_log2);
+            k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, meta, nb_log2);
             k_part_start<KB, G><<<1, 2 * nb, 0, st>>>(meta);
-            k_part_scatter<KB, G, P><<<part_groups, kBlock, 0, st>>>(plan, meta, part, nb_log2);
+            k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, meta, part, nb_log2);
         }
         {
             Timed tm(prof, st, SF_K_MERGE, cnt);
-            k_merge<KB, G><<<blocks_for(cnt, MergeShape<KB, G>::kChunk) + 2 * nb, kBlock, 0, st>>>(
+            k_merge<KB, G><<<blocks_for(cnt, MergeShape<KB, G>::kChunk) + 2 * nb, MergeShape<KB, G>::kThreads, 0, st>>>(
                 part, meta, ent_key, ent_cnt, cap, nb_log2);
         }
         if (ins) {

@@ -288,6 +288,8 @@ namespace sfk {
 
 constexpr uint32_t kMaxBuckets = 512;          // per op type; the runtime nb is a power of two <= this
 constexpr uint32_t kPartOps = 8192;            // ops per partitioning workgroup
+constexpr uint32_t kPartThreads = 1024;        // its threads (16 waves)
+constexpr uint32_t kLine = 32;                 // uint32 words per 128-byte line
 
 template <int KB, bool G> struct MKey { Key<KB> k; };
 template <int KB> struct MKey<KB, true> { Key<KB> k; uint32_t s; };
@@ -319,9 +321,11 @@ template <int KB, bool G> __device__ __forceinline__ uint32_t mkey_hash(const MK
 }
 
 template <int KB, bool G> struct MergeShape {  // LDS table of the merging kernel
-    // 4096 uint32 keys or 2048 13-byte keys per chunk: 48..68 KB of LDS
-    static constexpr int J = KB == 4 ? 16 : 8;
-    static constexpr uint32_t kChunk = uint32_t(kBlock) * J;
+    // 4096 uint32 keys or 2048 13-byte keys per chunk: 53..73 KB of LDS, so
+    // 2-3 workgroups of 8 waves share a CU
+    static constexpr uint32_t kThreads = 512;
+    static constexpr int J = KB == 4 ? 8 : 4;
+    static constexpr uint32_t kChunk = kThreads * J;
     static constexpr uint32_t kSlots = 2 * kChunk;
 };
 
@@ -339,29 +343,83 @@ template <int KB, bool G> struct MergeLDS {
     uint32_t slot[MergeShape<KB, G>::kSlots];
 };
 
+// Adds cnt copies of key k (local index idx) to the table.
 template <int KB, bool G>
-__device__ __forceinline__ void merge_insert(MergeLDS<KB, G>& L, const MKey<KB, G>& k, uint32_t idx) {
+__device__ __forceinline__ void merge_insert(MergeLDS<KB, G>& L, const MKey<KB, G>& k, uint32_t idx, uint32_t cnt) {
     constexpr uint32_t mask = MergeShape<KB, G>::kSlots - 1;
     uint32_t s = mkey_hash<KB, G>(k) & mask;
     for (uint32_t probe = 0; probe < MergeShape<KB, G>::kSlots; probe++) {
-        const uint32_t prev = atomicCAS(&L.slot[s], kEmpty, (idx << 16) | 1u);
+        const uint32_t prev = atomicCAS(&L.slot[s], kEmpty, (idx << 16) | cnt);
         if (prev == kEmpty) return;
         if (mkey_eq<KB, G>(L.key[prev >> 16], k)) {
-            atomicAdd(&L.slot[s], 1u);  // count < 2^16: never carries into the owner
+            atomicAdd(&L.slot[s], cnt);  // counts stay < 2^16: never carry into the owner
             return;
         }
         s = (s + 1) & mask;
     }
 }
 
+// Value of x in lane `lane` (wave-uniform) of the wavefront.
+template <class T> __device__ __forceinline__ T read_lane(const T& x, int lane) {
+    static_assert(sizeof(T) % 4 == 0, "read_lane moves whole dwords");
+    T r;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&x);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); i++) dst[i] = __builtin_amdgcn_readlane(src[i], lane);
+    return r;
+}
+
+// Skewed streams put many copies of one key (or bucket) in one wavefront, and
+// LDS atomics on one address serialise.  K rounds of "peeling": the first
+// unclaimed lane leads, every lane holding the leader's value joins it, and
+// the leader alone carries the group.  Returns this lane's weight: the group
+// size for a leader, 0 for a follower (or an invalid lane), 1 for a lane
+// left unclaimed.  *leader_of / *rank (optional) say which lane leads this
+// lane's group and this lane's place in it.  Call with the whole wavefront.
+template <int K, class T, class Eq>
+__device__ __forceinline__ uint32_t wave_peel(const T& v, bool valid, Eq eq, int* leader_of = nullptr,
+                                              uint32_t* rank = nullptr) {
+    bool claimed = !valid;
+    uint32_t w = valid ? 1u : 0u;
+    const int lane = int(lane_id());
+    if (leader_of) *leader_of = lane;
+    if (rank) *rank = 0;
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+        const unsigned long long act = __ballot(!claimed);
+        if (act == 0) break;
+        const int leader = __ffsll(act) - 1;
+        const T lv = read_lane(v, leader);
+        const bool same = !claimed && eq(v, lv);
+        const unsigned long long m = __ballot(same);
+        if (same) {
+            claimed = true;
+            w = lane == leader ? uint32_t(__popcll(m)) : 0u;
+            if (leader_of) *leader_of = leader;
+            if (rank) *rank = uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
+        }
+    }
+    return w;
+}
+
+constexpr int kPeel = 2;       // merging: keys
+constexpr int kPartPeel = 0;   // partitioning: buckets
+
 struct MergeMeta {                    // device-side bookkeeping of one batch
-    uint32_t total[2 * kMaxBuckets];  // keys per bucket (zeroed again by k_part_start)
+    // per-bucket counters bumped by every partitioning workgroup: one per
+    // kLine words, i.e. one 128-byte line each
+    uint32_t total[2 * kMaxBuckets * kLine];  // keys per bucket (zeroed again by k_part_start)
     uint32_t start[2 * kMaxBuckets];  // first position of each bucket in the partitioned keys
     uint32_t size[2 * kMaxBuckets];
-    uint32_t cursor[2 * kMaxBuckets]; // scatter cursors
+    uint32_t cursor[2 * kMaxBuckets * kLine];  // scatter cursors
     uint32_t chunk0[2 * kMaxBuckets + 1];  // first chunk of each bucket (prefix)
-    uint32_t n_ins, n_del;            // entries emitted
-    unsigned long long acc_ins, acc_del;  // entries emitted since creation
+    // Entries emitted.  Every merging workgroup bumps one of these once, so
+    // each sits on its own 256-byte line (atomics on one line serialise).
+    alignas(256) uint32_t n_ins;
+    alignas(256) uint32_t n_del;
+    alignas(256) unsigned long long acc_ins;  // entries emitted since creation
+    unsigned long long acc_del;
 };
 
 // Bucket of a key: top log2(nb) bits of its hash (the LDS table uses low bits).
@@ -372,19 +430,25 @@ __device__ __forceinline__ uint32_t bucket_of(const MKey<KB, G>& k, bool del, ui
 
 // Counts the ops of every bucket.
 template <int KB, bool G, class P>
-__global__ __launch_bounds__(kBlock) void k_part_count(P plan, MergeMeta* __restrict__ meta, uint32_t nb_log2) {
+__global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, MergeMeta* __restrict__ meta, uint32_t nb_log2) {
     __shared__ uint32_t hist[2 * kMaxBuckets];
     const uint32_t nbt = 2u << nb_log2;
     const Work w = plan.at(blockIdx.x, kPartOps);
-    for (uint32_t b = threadIdx.x; b < nbt; b += kBlock) hist[b] = 0;
+    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock) {
-        const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
-        atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u);
+    for (uint32_t base = 0; base < w.count; base += kPartThreads) {  // same trip count for the whole group
+        const uint32_t t = base + threadIdx.x;
+        uint32_t b = 0;
+        if (t < w.count) {
+            const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
+            b = bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2);
+        }
+        const uint32_t wgt = wave_peel<kPartPeel>(b, t < w.count, [](uint32_t x, uint32_t y) { return x == y; });
+        if (wgt) atomicAdd(&hist[b], wgt);
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nbt; b += kBlock)
-        if (hist[b]) atomicAdd(&meta->total[b], hist[b]);
+    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
+        if (hist[b]) atomicAdd(&meta->total[b * kLine], hist[b]);
 }
 
 // One workgroup of 2*nb threads: bucket starts, cursors and chunk prefix;
@@ -394,7 +458,7 @@ __global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __res
     constexpr uint32_t chunk = MergeShape<KB, G>::kChunk;
     __shared__ uint32_t a[2 * kMaxBuckets], c[2 * kMaxBuckets];
     const uint32_t b = threadIdx.x, nbt = blockDim.x;
-    const uint32_t sz = meta->total[b];
+    const uint32_t sz = meta->total[b * kLine];
     a[b] = sz;
     c[b] = (sz + chunk - 1) / chunk;
     __syncthreads();
@@ -407,36 +471,54 @@ __global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __res
     }
     meta->size[b] = sz;
     meta->start[b] = a[b] - sz;
-    meta->cursor[b] = a[b] - sz;
+    meta->cursor[b * kLine] = a[b] - sz;
     meta->chunk0[b + 1] = c[b];
     if (b == 0) {
         meta->chunk0[0] = 0;
         meta->n_ins = 0;
         meta->n_del = 0;
     }
-    meta->total[b] = 0;
+    meta->total[b * kLine] = 0;
 }
 
 // Scatters the keys into their buckets (order inside a bucket is free).
 template <int KB, bool G, class P>
-__global__ __launch_bounds__(kBlock) void k_part_scatter(P plan, MergeMeta* __restrict__ meta,
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, MergeMeta* __restrict__ meta,
                                                          MKey<KB, G>* __restrict__ part, uint32_t nb_log2) {
     __shared__ uint32_t hist[2 * kMaxBuckets];
     const uint32_t nbt = 2u << nb_log2;
     const Work w = plan.at(blockIdx.x, kPartOps);
-    for (uint32_t b = threadIdx.x; b < nbt; b += kBlock) hist[b] = 0;
+    constexpr uint32_t R = kPartOps / kPartThreads;  // keys per thread
+    MKey<KB, G> k[R];
+    uint32_t bk[R];
+    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock) {
-        const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
-        atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u);
+#pragma unroll
+    for (uint32_t r = 0; r < R; r++) {
+        const uint32_t t = r * kPartThreads + threadIdx.x;
+        bk[r] = 0;
+        if (t < w.count) {
+            k[r] = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
+            bk[r] = bucket_of<KB, G>(k[r], is_delete(w.ops, t, w.mode), nb_log2);
+        }
+        const uint32_t wgt = wave_peel<kPartPeel>(bk[r], t < w.count, [](uint32_t x, uint32_t y) { return x == y; });
+        if (wgt) atomicAdd(&hist[bk[r]], wgt);
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nbt; b += kBlock)
-        if (hist[b]) hist[b] = atomicAdd(&meta->cursor[b], hist[b]);  // this group's first position
+    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
+        if (hist[b]) hist[b] = atomicAdd(&meta->cursor[b * kLine], hist[b]);  // this group's first position
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < w.count; t += kBlock) {
-        const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
-        part[atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u)] = k;
+#pragma unroll
+    for (uint32_t r = 0; r < R; r++) {
+        const uint32_t t = r * kPartThreads + threadIdx.x;
+        int leader;
+        uint32_t rank;
+        const uint32_t wgt = wave_peel<kPartPeel>(bk[r], t < w.count, [](uint32_t x, uint32_t y) { return x == y; },
+                                              &leader, &rank);
+        uint32_t pos = 0;
+        if (wgt) pos = atomicAdd(&hist[bk[r]], wgt);   // a leader reserves its whole group
+        const uint32_t lead_pos = __shfl(pos, leader);
+        if (t < w.count) part[(wgt ? pos : lead_pos) + (wgt ? 0u : rank)] = k[r];
     }
 }
 
@@ -444,10 +526,11 @@ __global__ __launch_bounds__(kBlock) void k_part_scatter(P plan, MergeMeta* __re
 // cap = entry capacity (insert entries at [0, n_ins), delete entries at
 // [cap - n_del, cap)).
 template <int KB, bool G>
-__global__ __launch_bounds__(kBlock) void k_merge(const MKey<KB, G>* __restrict__ part,
+__global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const MKey<KB, G>* __restrict__ part,
                                                   MergeMeta* __restrict__ meta, MKey<KB, G>* __restrict__ ent_key,
                                                   uint32_t* __restrict__ ent_cnt, uint32_t cap, uint32_t nb_log2) {
     constexpr int J = MergeShape<KB, G>::J;
+    constexpr uint32_t kThreads = MergeShape<KB, G>::kThreads;
     constexpr uint32_t kChunk = MergeShape<KB, G>::kChunk, kSlots = MergeShape<KB, G>::kSlots;
     __shared__ MergeLDS<KB, G> L;
     __shared__ uint32_t chunk0[2 * kMaxBuckets + 1];
@@ -455,8 +538,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(const MKey<KB, G>* __restrict_
     const uint32_t nbt = 2u << nb_log2;
     const uint32_t c = blockIdx.x;
     if (c >= meta->chunk0[nbt]) return;
-    for (uint32_t i = threadIdx.x; i <= nbt; i += kBlock) chunk0[i] = meta->chunk0[i];
-    for (uint32_t i = threadIdx.x; i < kSlots; i += kBlock) L.slot[i] = kEmpty;
+    for (uint32_t i = threadIdx.x; i <= nbt; i += kThreads) chunk0[i] = meta->chunk0[i];
+    for (uint32_t i = threadIdx.x; i < kSlots; i += kThreads) L.slot[i] = kEmpty;
     if (threadIdx.x == 0) nloc = 0;
     __syncthreads();
     uint32_t lo = 0, hi = nbt;                    // bucket b with chunk0[b] <= c < chunk0[b+1]
@@ -472,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const MKey<KB, G>* __restrict_
     MKey<KB, G> k[J];
 #pragma unroll
     for (int j = 0; j < J; j++) {
-        const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
+        const uint32_t idx = uint32_t(j) * kThreads + threadIdx.x;
         if (idx < n) {
             k[j] = part[first + idx];
             L.key[idx] = k[j];
@@ -481,21 +564,23 @@ __global__ __launch_bounds__(kBlock) void k_merge(const MKey<KB, G>* __restrict_
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; j++) {
-        const uint32_t idx = uint32_t(j) * kBlock + threadIdx.x;
-        if (idx < n) merge_insert<KB, G>(L, k[j], idx);
+        const uint32_t idx = uint32_t(j) * kThreads + threadIdx.x;
+        const uint32_t wgt = wave_peel<kPeel>(k[j], idx < n, [](const MKey<KB, G>& a, const MKey<KB, G>& b) {
+            return mkey_eq<KB, G>(a, b);
+        });
+        if (wgt) merge_insert<KB, G>(L, k[j], idx, wgt);
     }
     __syncthreads();
     uint32_t mine = 0;                            // entries this thread will emit
-    for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) mine += L.slot[s] != kEmpty;
+    for (uint32_t s = threadIdx.x; s < kSlots; s += kThreads) mine += L.slot[s] != kEmpty;
     uint32_t rank = atomicAdd(&nloc, mine);
     __syncthreads();
     if (threadIdx.x == 0) {
         base = atomicAdd(del ? &meta->n_del : &meta->n_ins, nloc);
-        atomicAdd(del ? &meta->acc_del : &meta->acc_ins, (unsigned long long)nloc);
     }
     __syncthreads();
     rank += base;
-    for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
+    for (uint32_t s = threadIdx.x; s < kSlots; s += kThreads) {
         const uint32_t v = L.slot[s];
         if (v == kEmpty) continue;
         const uint32_t id = del ? cap - 1 - rank : rank;
@@ -553,11 +638,12 @@ __global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __
 
 // S2 / S4 over merged entries: one atomic per entry and row carrying its count.
 template <int KB, int D, bool G, class SR>
-__global__ __launch_bounds__(kBlock) void k_entries_fat(const MergeMeta* __restrict__ meta,
+__global__ __launch_bounds__(kBlock) void k_entries_fat(MergeMeta* __restrict__ meta,
                                                         const MKey<KB, G>* __restrict__ ent_key,
                                                         const uint32_t* __restrict__ ent_cnt, uint32_t cap,
                                                         SR sr, uint32_t del) {
     const uint32_t n = del ? meta->n_del : meta->n_ins;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(del ? &meta->acc_del : &meta->acc_ins, (unsigned long long)n);
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
         const uint32_t id = del ? cap - 1 - e : e;
         const uint32_t v = del ? 0u - ent_cnt[id] : ent_cnt[id];
