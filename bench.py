@@ -496,8 +496,6 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} done")
-    sk.profile(True)
-    sk.profile_read(reset=True)
     ie0, de0 = sk.merge_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -505,12 +503,24 @@ def main():
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = sk.profile_read(reset=True)
-    sk.profile(False)
     ms_step = elapsed * 1e3 / args.steps
     items = (wl.n_ops + wl.n_queries) * args.steps
     value = items / elapsed / 1e6
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} M items/s")
+    ie1, de1 = sk.merge_stats()
+    # Per-kernel durations: the same steps again with a HIP event pair around every
+    # kernel on the sketch's stream.  The event packets add a gap of about 10 us after
+    # each kernel, so these steps are not the timed ones.
+    sk.profile(True)
+    sk.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof_ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    prof = sk.profile_read(reset=True)
+    sk.profile(False)
+    log(f"[bench] profiled steps: {prof_ms_step:.3f} ms/step")
 
     # sanity on the device result: Fat row sums = net stream weight (Section 3.4 CM property)
     fat = sk.export_fat()
@@ -521,7 +531,6 @@ def main():
 
     # per-kernel accounting from the events on the sketch's stream
     kernels = {}
-    ie1, de1 = sk.merge_stats()
     units = dict(ins=n_ins * args.steps, dels=n_del * args.steps, ops=wl.n_ops * args.steps,
                  q=wl.n_queries * args.steps, cells=cells * args.steps, mixed=True,
                  ie=(ie1 - ie0) if args.merge == "batch" else n_ins * args.steps,
@@ -564,6 +573,8 @@ def main():
                           "bytes_per_step": step_bytes,
                           "merged_entries_per_step": [units["ie"] // args.steps, units["de"] // args.steps]},
         "kernels": kernels,
+        "kernels_note": "HIP-event durations from the same steps run once more with events on",
+        "profiled_ms_per_step": round(prof_ms_step, 3),
     }
 
     if not args.no_micro:
