@@ -107,7 +107,10 @@ int sf_delete(sf_sketch *sk, const void *keys, uint64_t n);
 int sf_update(sf_sketch *sk, const void *keys, const uint8_t *ops, uint64_t n);
 
 /* Point query (Section 3.1 query rule, unchanged in SF_F): out[t] = the
- * smallest of the d Slim counters of keys[t], as uint32 (device pointer). */
+ * smallest of the d Slim counters of keys[t], as uint32 (device pointer).
+ * Between an sf_export_slim and the next update or reset, the query reads
+ * the dense uint16 copy that export made (same values, a fifth of the
+ * memory footprint); otherwise it reads the Slim words of the sketch. */
 int sf_query(sf_sketch *sk, const void *keys, uint64_t n, uint32_t *out);
 
 /* Collector-side point query over an exported Slim (slim: device pointer to
@@ -117,7 +120,8 @@ int sf_query_slim(const uint16_t *slim, const sf_config *cfg, const void *keys, 
 
 /* Slim export, the structure sent to the collector (Sections 1 and 3): d*w
  * uint16 counters, row-major [d][w].  out may be host or device memory with
- * room for out_elems >= d*w elements.  Synchronous. */
+ * room for out_elems >= d*w elements.  Synchronous.  The sketch keeps its
+ * own copy of what it exported, for sf_query. */
 int sf_export_slim(sf_sketch *sk, uint16_t *out, uint64_t out_elems);
 
 /* Fat export: d*w*z uint32 counters, [d][w][z] (row, bucket, slot), host or

@@ -16,6 +16,7 @@ constexpr int kBlock = 256;  // 4 wavefronts
 // Sizes of one sketch's arrays and its index split.
 struct Geom {
     uint32_t d, w, z, seed_base;
+    uint32_t rs;       // words per cell record: the z Fat counters, then the Slim working copy
     uint32_t pow2;     // w and z are powers of two: masks and shifts
     uint32_t wz32;     // w*z mod 2^32 (0 encodes 2^32)
     uint32_t w_mask;   // w - 1 (pow2 only)

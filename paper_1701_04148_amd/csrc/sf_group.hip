@@ -16,8 +16,9 @@
 // Merged sub-rounds hold at most kMergeRound ops (or one sketch's batch, if
 // larger) so the buckets stay about two LDS chunks long.
 //
-// Device memory (one allocation): all Fat arrays, all Slim working copies,
-// the sketch table, export staging (largest sketch), the snapshot scratch
+// Device memory (one allocation): every sketch's cell records (Fat bucket
+// and Slim working copy of a cell side by side), the sketch table, export
+// staging (largest dense Fat), the snapshot scratch
 // ([d_max][round_ops] uint32 + uint16), the merge buffers (partitioned keys,
 // entries, counts for one merged sub-round) and a growable tile table.
 #include <hip/hip_runtime.h>
@@ -94,7 +95,7 @@ bool live(const sf_group* g) {
 constexpr uint64_t kMergeRound = 1ull << 22;
 
 struct Layout {
-    std::vector<uint64_t> fat_off, slim_off;
+    std::vector<uint64_t> fat_off;  // each sketch's cell records (Fat bucket + Slim per cell)
     uint64_t state, desc, stage, bpre, asnap, part, ent_key, ent_cnt, meta, total;
     uint64_t round_ops, merge_round;
     uint32_t d_max;
@@ -102,24 +103,19 @@ struct Layout {
 
 int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) {
     if (n == 0 || !cfgs) return fail(SF_EINVAL, "a group needs at least one sketch config");
-    uint64_t off = 0, max_b = 0, max_cells = 0;
+    uint64_t off = 0, max_b = 0, max_stage = 0;
     L.d_max = 0;
     L.fat_off.resize(n);
-    L.slim_off.resize(n);
     for (uint32_t i = 0; i < n; i++) {
         int rc = validate(&cfgs[i]);
         if (rc) return fail(rc, "sketch " + std::to_string(i) + ": " + last_error());
         if (cfgs[i].key_bytes != cfgs[0].key_bytes) return fail(SF_EINVAL, "key_bytes must match across a group");
         const uint64_t cells = uint64_t(cfgs[i].d) * cfgs[i].w;
         L.fat_off[i] = off;
-        off += round256(cells * cfgs[i].z * 4);
+        off += round256(cells * (cfgs[i].z + 1) * 4);
         max_b = std::max<uint64_t>(max_b, cfgs[i].batch_ops);
-        max_cells = std::max(max_cells, cells);
+        max_stage = std::max<uint64_t>(max_stage, cells * cfgs[i].z * 4);  // dense Fat export
         L.d_max = std::max(L.d_max, cfgs[i].d);
-    }
-    for (uint32_t i = 0; i < n; i++) {
-        L.slim_off[i] = off;
-        off += round256(uint64_t(cfgs[i].d) * cfgs[i].w * 4);
     }
     L.state = off;
     if (round_ops == 0) {
@@ -132,7 +128,7 @@ int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) 
     L.desc = off;
     off += round256(uint64_t(n) * sizeof(SketchDesc));
     L.stage = off;
-    off += round256(max_cells * 2);
+    off += round256(max_stage);
     L.bpre = off;
     off += round256(uint64_t(L.d_max) * L.round_ops * 4);
     L.asnap = off;
@@ -385,7 +381,7 @@ int sf_group_create(uint32_t n, const sf_config* cfgs, uint64_t round_ops, uint6
     for (uint32_t i = 0; i < n; i++) {
         g->desc[i].g = geom_of(&cfgs[i]);
         g->desc[i].fat = reinterpret_cast<uint32_t*>(g->base + L.fat_off[i]);
-        g->desc[i].slim = reinterpret_cast<uint32_t*>(g->base + L.slim_off[i]);
+        g->desc[i].slim = g->desc[i].fat + cfgs[i].z;
     }
     g->d_desc = reinterpret_cast<SketchDesc*>(g->base + L.desc);
     g->stage = reinterpret_cast<uint16_t*>(g->base + L.stage);
@@ -499,7 +495,7 @@ int sf_group_export_slim(sf_group* g, uint32_t i, uint16_t* out, uint64_t out_el
     }
     uint16_t* dst = host ? g->stage : out;
     const unsigned grid = blocks_for(cells, kBlock) < 4096u ? blocks_for(cells, kBlock) : 4096u;
-    k_pack16<uint32_t><<<dim3(grid), dim3(kBlock), 0, g->stream>>>(g->desc[i].slim, dst, cells);
+    k_pack16<uint32_t><<<dim3(grid), dim3(kBlock), 0, g->stream>>>(g->desc[i].slim, dst, cells, g->desc[i].g.rs, nullptr);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && host) e = hipMemcpyAsync(out, g->stage, cells * 2, hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
@@ -512,11 +508,17 @@ int sf_group_export_fat(sf_group* g, uint32_t i, uint32_t* out, uint64_t out_ele
     const uint64_t n = uint64_t(g->cfg[i].d) * g->cfg[i].w * g->cfg[i].z;
     if (!out) return fail(SF_EINVAL, "out is null");
     if (out_elems < n) return fail(SF_EINVAL, "out_elems < d*w*z");
-    if (!host_dest(out)) {
+    const bool host = host_dest(out);
+    if (!host) {
         int rc = check_gpu_ptr(out, n * 4, "out");
         if (rc) return rc;
     }
-    hipError_t e = hipMemcpyAsync(out, g->desc[i].fat, n * 4, hipMemcpyDefault, g->stream);
+    uint32_t* dst = host ? reinterpret_cast<uint32_t*>(g->stage) : out;
+    const unsigned grid = blocks_for(n, kBlock) < 4096u ? blocks_for(n, kBlock) : 4096u;
+    k_unpack_fat<uint32_t><<<dim3(grid), dim3(kBlock), 0, g->stream>>>(
+        g->desc[i].fat, dst, uint64_t(g->cfg[i].d) * g->cfg[i].w, g->cfg[i].z);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && host) e = hipMemcpyAsync(out, dst, n * 4, hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_group_export_fat");
 }

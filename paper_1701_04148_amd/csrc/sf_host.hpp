@@ -48,6 +48,7 @@ inline Geom geom_of(const sf_config* c) {
     g.d = c->d;
     g.w = c->w;
     g.z = c->z;
+    g.rs = c->z + 1;
     g.seed_base = c->seed_base;
     const uint64_t wz = uint64_t(c->w) * c->z;
     g.wz32 = uint32_t(wz);  // 2^32 wraps to 0

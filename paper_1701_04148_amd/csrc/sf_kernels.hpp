@@ -103,8 +103,8 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(P plan, uint32_t* __restric
                 uint32_t h, f;
                 split(w.g, mx.row(w.g.seed_base + i), h, f);
                 const size_t cell = size_t(i) * w.g.w + h;
-                asnap[size_t(i) * stride + s] = uint16_t(slim[cell]);
-                bpre[size_t(i) * stride + s] = w.fat[cell * w.g.z + f];
+                asnap[size_t(i) * stride + s] = uint16_t(slim[cell * w.g.rs]);
+                bpre[size_t(i) * stride + s] = w.fat[cell * w.g.rs + f];
             }
         }
     }
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_fat_update(P plan, uint32_t want_del
             if (i < d) {
                 uint32_t h, f;
                 split(w.g, mx.row(w.g.seed_base + i), h, f);
-                atomic_add_u32(&w.fat[(size_t(i) * w.g.w + h) * w.g.z + f], v);
+                atomic_add_u32(&w.fat[(size_t(i) * w.g.w + h) * w.g.rs + f], v);
             }
         }
     }
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_raise(P plan, const uint32_t* __rest
                 split(w.g, mx.row(w.g.seed_base + i), h, f);
                 cell[i] = size_t(i) * w.g.w + h;
                 a[i] = asnap[size_t(i) * stride + t];
-                const uint32_t post = w.fat[cell[i] * w.g.z + f];
+                const uint32_t post = w.fat[cell[i] * w.g.rs + f];
                 const uint32_t grew = post - bpre[size_t(i) * stride + t];
                 m0 = min(m0, a[i]);
                 bmin = min(bmin, post);
@@ -199,19 +199,17 @@ __global__ __launch_bounds__(kBlock) void k_raise(P plan, const uint32_t* __rest
         const uint32_t T = uint32_t(tt < kSlimMax ? tt : kSlimMax);
 #pragma unroll
         for (int i = 0; i < R; i++)
-            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&slim[cell[i]], T);
+            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&slim[cell[i] * w.g.rs], T);
     }
 }
 
-// Largest counter of a Fat bucket.
+// Largest counter of a Fat bucket (the first z words of the cell's record).
 __device__ __forceinline__ uint32_t bucket_max(const uint32_t* __restrict__ fat, size_t cell,
                                                const Geom& g) {
-    if (g.z == 4) {
-        const uint4 v = *reinterpret_cast<const uint4*>(fat + cell * 4);
-        return max(max(v.x, v.y), max(v.z, v.w));
-    }
+    const uint32_t* b = fat + cell * g.rs;
+    if (g.z == 4) return max(max(b[0], b[1]), max(b[2], b[3]));
     uint32_t m = 0;
-    for (uint32_t j = 0; j < g.z; j++) m = max(m, fat[cell * g.z + j]);
+    for (uint32_t j = 0; j < g.z; j++) m = max(m, b[j]);
     return m;
 }
 
@@ -235,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_clamp(P plan) {
                 split(w.g, mx.row(w.g.seed_base + i), h, f);
                 const size_t cell = size_t(i) * w.g.w + h;
                 const uint32_t m = bucket_max(w.fat, cell, w.g);
-                if (slim[cell] > m) atomic_min_u32(&slim[cell], m);
+                if (slim[cell * w.g.rs] > m) atomic_min_u32(&slim[cell * w.g.rs], m);
             }
         }
     }
@@ -248,6 +246,9 @@ __global__ __launch_bounds__(kBlock) void k_query(P plan) {
     const uint32_t t = threadIdx.x;
     if (t >= w.count) return;
     const S* slim = static_cast<const S*>(w.slim);
+    // a uint32 Slim is the working copy inside the cell records; a uint16 one
+    // is a dense exported [d][w] array
+    const uint32_t qs = sizeof(S) == 4 ? w.g.rs : 1u;
     const Mixed<KB> mx(load_key<KB>(w.keys, t));
     const uint32_t d = SF_ROWS(D, w.g);
     uint32_t q = ~0u;
@@ -256,18 +257,31 @@ __global__ __launch_bounds__(kBlock) void k_query(P plan) {
         if (i < d) {
             uint32_t h, f;
             split(w.g, mx.row(w.g.seed_base + i), h, f);
-            q = min(q, uint32_t(slim[size_t(i) * w.g.w + h]));
+            q = min(q, uint32_t(slim[(size_t(i) * w.g.w + h) * qs]));
         }
     }
     w.out[t] = q;
 }
 
-// Narrowing copy of a 32-bit Slim working copy into the uint16 export form.
+// The Fat-subsketch in its dense [d][w][z] form, out of the cell records.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_unpack_fat(const T* __restrict__ rec, T* __restrict__ out,
+                                                       size_t cells, uint32_t z) {
+    const size_t n = cells * z;
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock)
+        out[i] = rec[(i / z) * (z + 1) + i % z];
+}
+
+// Narrowing copy of a 32-bit Slim working copy (every stride-th word) into
+// the dense uint16 export form (to out, and to out2 unless it is null).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pack16(const T* __restrict__ in, uint16_t* __restrict__ out,
-                                                   size_t n) {
-    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock)
-        out[i] = uint16_t(in[i]);
+                                                   size_t n, uint32_t stride, uint16_t* __restrict__ out2) {
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock) {
+        const uint16_t v = uint16_t(in[i * stride]);
+        out[i] = v;
+        if (out2) out2[i] = v;
+    }
 }
 
 }  // namespace sfk
@@ -622,8 +636,8 @@ __global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __
                 uint32_t h, f;
                 split(sd.g, mx.row(sd.g.seed_base + i), h, f);
                 const size_t cell = size_t(i) * sd.g.w + h;
-                av[i] = sd.slim[cell];
-                bv[i] = sd.fat[cell * sd.g.z + f];
+                av[i] = sd.slim[cell * sd.g.rs];     // same record as the Fat counter below
+                bv[i] = sd.fat[cell * sd.g.rs + f];
             }
         }
 #pragma unroll
@@ -656,7 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_fat(MergeMeta* __restrict__ 
             if (i < d) {
                 uint32_t h, f;
                 split(sd.g, mx.row(sd.g.seed_base + i), h, f);
-                atomic_add_u32(&sd.fat[(size_t(i) * sd.g.w + h) * sd.g.z + f], v);
+                atomic_add_u32(&sd.fat[(size_t(i) * sd.g.w + h) * sd.g.rs + f], v);
             }
         }
     }
@@ -687,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __res
                 split(sd.g, mx.row(sd.g.seed_base + i), h, f);
                 cell[i] = size_t(i) * sd.g.w + h;
                 a[i] = asnap[size_t(i) * stride + e];
-                const uint32_t post = sd.fat[cell[i] * sd.g.z + f];
+                const uint32_t post = sd.fat[cell[i] * sd.g.rs + f];
                 const uint32_t grew = post - bpre[size_t(i) * stride + e];
                 m0 = min(m0, a[i]);
                 bmin = min(bmin, post);
@@ -700,7 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __res
         const uint32_t T = uint32_t(tt < kSlimMax ? tt : kSlimMax);
 #pragma unroll
         for (int i = 0; i < R; i++)
-            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&sd.slim[cell[i]], T);
+            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&sd.slim[cell[i] * sd.g.rs], T);
     }
 }
 
@@ -722,7 +736,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_clamp(const MergeMeta* __res
                 split(sd.g, mx.row(sd.g.seed_base + i), h, f);
                 const size_t cell = size_t(i) * sd.g.w + h;
                 const uint32_t mval = bucket_max(sd.fat, cell, sd.g);
-                if (sd.slim[cell] > mval) atomic_min_u32(&sd.slim[cell], mval);
+                if (sd.slim[cell * sd.g.rs] > mval) atomic_min_u32(&sd.slim[cell * sd.g.rs], mval);
             }
         }
     }

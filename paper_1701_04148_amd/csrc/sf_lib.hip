@@ -2,13 +2,16 @@
 // single-sketch entry points (sketch groups live in sf_group.hip).
 //
 // Device state of one sketch (all in HBM, one allocation made by sf_create):
-//   fat   uint32 [d][w][z]  Fat-subsketch, bucket-major (the layout of the
-//                           paper's Section 3.4): a bucket is z consecutive
-//                           counters (z=4: one aligned 16-byte load)
-//   slim  uint32 [d][w]     Slim working copy; values stay <= 65535, so the
-//                           exported uint16 array is a narrowing copy.  32-bit
-//                           cells give native atomic max / min.
-//   stage uint16 [d][w]     export staging for host destinations
+//   rec   uint32 [d][w][z+1]  one record per cell: the cell's Fat bucket (z
+//                             counters, Section 3.4) then the cell's Slim
+//                             working copy, so S1, S3 and S5 read the Fat
+//                             counter and the Slim counter of a cell from one
+//                             cache line.  Slim values stay <= 65535 (the
+//                             uint16 export is a narrowing copy); 32-bit cells
+//                             give native atomic max / min.  fat points at
+//                             the records, slim at word z of the first one.
+//   stage                     export staging for host destinations (the larger
+//                             of the dense uint16 Slim and uint32 Fat)
 //   bpre  uint32 [d][b]     per-batch snapshot of insert ops' Fat counters
 //   asnap uint16 [d][b]     per-batch snapshot of their Slim counters
 // Each schedule batch runs the five steps of sf_kernels.hpp on the sketch's
@@ -40,6 +43,8 @@ struct sf_sketch {
     uint32_t* fat;
     uint32_t* slim;
     uint16_t* stage;
+    uint16_t* view;   // dense uint16 Slim as of the last export (queries read it while fresh)
+    bool view_fresh;  // no update or reset since view was packed
     uint32_t* bpre;
     uint16_t* asnap;
     uint32_t stride;  // snapshot capacity in ops (= batch_ops)
@@ -63,17 +68,18 @@ bool live(const sf_sketch* s) {
 }
 
 struct Sizes {
-    uint64_t fat, slim, stage, bpre, asnap, part, ent_key, ent_cnt, meta;
-    uint64_t total() const { return fat + slim + stage + bpre + asnap + part + ent_key + ent_cnt + meta; }
+    uint64_t fat, slim, stage, view, bpre, asnap, part, ent_key, ent_cnt, meta;
+    uint64_t total() const { return fat + slim + stage + view + bpre + asnap + part + ent_key + ent_cnt + meta; }
 };
 
 Sizes sizes_of(const sf_config* c) {
     Sizes s;
     const uint64_t cells = uint64_t(c->d) * c->w;
     const uint64_t key = c->key_bytes == 4 ? sizeof(Key<4>) : sizeof(Key<13>);
-    s.fat = round256(cells * c->z * 4);
-    s.slim = round256(cells * 4);
-    s.stage = round256(cells * 2);
+    s.fat = round256(cells * (c->z + 1) * 4);  // the cell records
+    s.slim = 0;                                 // inside the records
+    s.stage = round256(cells * c->z * 4);
+    s.view = round256(cells * 2);
     s.bpre = round256(uint64_t(c->d) * c->batch_ops * 4);
     s.asnap = round256(uint64_t(c->d) * c->batch_ops * 2);
     s.part = round256(uint64_t(c->batch_ops) * key);
@@ -120,6 +126,7 @@ int run_updates(sf_sketch* s, const void* keys, const uint8_t* ops, uint64_t n, 
     if (kind == kMixed && (rc = check_gpu_ptr(ops, n, "ops"))) return rc;
     const uint8_t* k8 = static_cast<const uint8_t*>(keys);
     const uint64_t b = s->cfg.batch_ops;
+    s->view_fresh = false;
     const uint32_t mode = kind == kMixed ? kOpsArray : kind == kDelete ? kAllDelete : kAllInsert;
     for (uint64_t lo = 0; lo < n; lo += b) {
         const uint32_t cnt = uint32_t(n - lo < b ? n - lo : b);
@@ -201,11 +208,13 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
                                         : device_fail(e, "sf_create");
     }
     s->fat = reinterpret_cast<uint32_t*>(base);
-    s->slim = reinterpret_cast<uint32_t*>(base + sz.fat);
+    s->slim = reinterpret_cast<uint32_t*>(base) + cfg->z;
     s->stage = reinterpret_cast<uint16_t*>(base + sz.fat + sz.slim);
-    s->bpre = reinterpret_cast<uint32_t*>(base + sz.fat + sz.slim + sz.stage);
-    s->asnap = reinterpret_cast<uint16_t*>(base + sz.fat + sz.slim + sz.stage + sz.bpre);
-    char* mq = base + sz.fat + sz.slim + sz.stage + sz.bpre + sz.asnap;
+    s->view = reinterpret_cast<uint16_t*>(base + sz.fat + sz.slim + sz.stage);
+    s->view_fresh = false;
+    s->bpre = reinterpret_cast<uint32_t*>(base + sz.fat + sz.slim + sz.stage + sz.view);
+    s->asnap = reinterpret_cast<uint16_t*>(base + sz.fat + sz.slim + sz.stage + sz.view + sz.bpre);
+    char* mq = base + sz.fat + sz.slim + sz.stage + sz.view + sz.bpre + sz.asnap;
     s->part = mq;
     s->ent_key = mq + sz.part;
     s->ent_cnt = reinterpret_cast<uint32_t*>(mq + sz.part + sz.ent_key);
@@ -243,6 +252,7 @@ int sf_reset(sf_sketch* s) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
     const Sizes sz = sizes_of(&s->cfg);
     hipError_t e = hipMemsetAsync(s->fat, 0, sz.fat + sz.slim, s->stream);
+    s->view_fresh = false;
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_reset");
 }
 
@@ -264,6 +274,8 @@ int sf_update(sf_sketch* s, const void* keys, const uint8_t* ops, uint64_t n) {
 
 int sf_query(sf_sketch* s, const void* keys, uint64_t n, uint32_t* out) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    if (s->view_fresh)  // the dense uint16 Slim: a fifth of the records' footprint
+        return query_common(&s->prof, &s->cfg, s->g, s->view, true, keys, n, out, s->stream);
     return query_common(&s->prof, &s->cfg, s->g, s->slim, false, keys, n, out, s->stream);
 }
 
@@ -288,14 +300,18 @@ int sf_export_slim(sf_sketch* s, uint16_t* out, uint64_t out_elems) {
         int rc = check_gpu_ptr(out, cells * 2, "out");
         if (rc) return rc;
     }
-    uint16_t* dst = host ? s->stage : out;
     const unsigned grid = blocks_for(cells, kBlock) < 4096u ? blocks_for(cells, kBlock) : 4096u;
-    {
+    hipError_t e = hipSuccess;
+    if (!s->view_fresh) {  // pack the records' Slim words into the view and (device) out at once
         Timed tm(&s->prof, s->stream, SF_K_EXPORT, cells);
-        k_pack16<uint32_t><<<dim3(grid), dim3(kBlock), 0, s->stream>>>(s->slim, dst, cells);
+        k_pack16<uint32_t><<<dim3(grid), dim3(kBlock), 0, s->stream>>>(s->slim, s->view, cells, s->g.rs,
+                                                                       host ? nullptr : out);
+        e = hipGetLastError();
+        s->view_fresh = e == hipSuccess;
+    } else if (!host) {
+        e = hipMemcpyAsync(out, s->view, cells * 2, hipMemcpyDeviceToDevice, s->stream);
     }
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && host) e = hipMemcpyAsync(out, s->stage, cells * 2, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && host) e = hipMemcpyAsync(out, s->view, cells * 2, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_export_slim");
 }
@@ -305,11 +321,17 @@ int sf_export_fat(sf_sketch* s, uint32_t* out, uint64_t out_elems) {
     const uint64_t n = uint64_t(s->cfg.d) * s->cfg.w * s->cfg.z;
     if (!out) return fail(SF_EINVAL, "out is null");
     if (out_elems < n) return fail(SF_EINVAL, "out_elems < d*w*z");
-    if (!host_dest(out)) {
+    const bool host = host_dest(out);
+    if (!host) {
         int rc = check_gpu_ptr(out, n * 4, "out");
         if (rc) return rc;
     }
-    hipError_t e = hipMemcpyAsync(out, s->fat, n * 4, hipMemcpyDefault, s->stream);
+    uint32_t* dst = host ? reinterpret_cast<uint32_t*>(s->stage) : out;
+    const uint64_t cells = uint64_t(s->cfg.d) * s->cfg.w;
+    const unsigned grid = blocks_for(n, kBlock) < 4096u ? blocks_for(n, kBlock) : 4096u;
+    k_unpack_fat<uint32_t><<<dim3(grid), dim3(kBlock), 0, s->stream>>>(s->fat, dst, cells, s->cfg.z);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && host) e = hipMemcpyAsync(out, dst, n * 4, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_export_fat");
 }

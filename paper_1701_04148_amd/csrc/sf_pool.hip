@@ -35,7 +35,7 @@ using namespace sfh;
 struct sf_pool {
     sf_config cfg;
     uint32_t slots;
-    uint64_t slot_fat, slot_slim;  // bytes of one slot's Fat and Slim (rounded)
+    uint64_t slot_bytes;           // one slot's cell records (Fat bucket + Slim per cell), rounded
     hipStream_t stream;
     bool own_stream;
     char* base;
@@ -83,7 +83,7 @@ bool live(const sf_pool* p) {
 constexpr size_t kRingTiles = size_t(1) << 21;  // 2M tiles (80 MiB) of in-flight descriptors
 
 struct PoolLayout {
-    uint64_t slot_fat, slot_slim, per_slot, shared, round_ops, merge_round, mkey;
+    uint64_t slot_bytes, per_slot, shared, round_ops, merge_round, mkey;
 };
 
 struct SubRound {
@@ -94,14 +94,13 @@ struct SubRound {
 PoolLayout pool_layout(const sf_config* c, uint64_t round_ops) {
     PoolLayout L;
     const uint64_t cells = uint64_t(c->d) * c->w;
-    L.slot_fat = round256(cells * c->z * 4);
-    L.slot_slim = round256(cells * 4);
-    L.per_slot = L.slot_fat + L.slot_slim + round256(sizeof(SketchDesc));
+    L.slot_bytes = round256(cells * (c->z + 1) * 4);
+    L.per_slot = L.slot_bytes + round256(sizeof(SketchDesc));
     L.round_ops = std::max<uint64_t>(round_ops ? round_ops : (1ull << 24), c->batch_ops);
     L.merge_round = std::max<uint64_t>(std::min<uint64_t>(L.round_ops, 1ull << 22), c->batch_ops);
     L.mkey = c->key_bytes == 4 ? sizeof(MKey<4, true>) : sizeof(MKey<13, true>);
     L.shared = round256(uint64_t(c->d) * L.round_ops * 4) + round256(uint64_t(c->d) * L.round_ops * 2) +
-               round256(cells * 2) + round256(kRingTiles * sizeof(TileDesc)) +
+               round256(cells * c->z * 4) + round256(kRingTiles * sizeof(TileDesc)) +
                2 * round256(L.merge_round * L.mkey) + round256(L.merge_round * 4) + round256(sizeof(MergeMeta));
     return L;
 }
@@ -198,8 +197,7 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
     sf_pool* p = new sf_pool{};
     p->cfg = *cfg;
     p->slots = uint32_t(slots);
-    p->slot_fat = L.slot_fat;
-    p->slot_slim = L.slot_slim;
+    p->slot_bytes = L.slot_bytes;
     p->round_ops = L.round_ops;
     p->merge_round = L.merge_round;
     p->tile_j = 8;
@@ -216,7 +214,7 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
         }
         p->own_stream = true;
     }
-    const uint64_t state = slots * (L.slot_fat + L.slot_slim);
+    const uint64_t state = slots * L.slot_bytes;
     const uint64_t total = state + round256(slots * sizeof(SketchDesc)) + L.shared;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->base), total);
     if (e != hipSuccess) {
@@ -234,7 +232,7 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
     p->asnap = reinterpret_cast<uint16_t*>(q);
     q += round256(uint64_t(cfg->d) * L.round_ops * 2);
     p->stage = reinterpret_cast<uint16_t*>(q);
-    q += round256(uint64_t(cfg->d) * cfg->w * 2);
+    q += round256(uint64_t(cfg->d) * cfg->w * cfg->z * 4);
     p->d_ring = reinterpret_cast<TileDesc*>(q);
     q += round256(kRingTiles * sizeof(TileDesc));
     p->part = q;
@@ -248,8 +246,8 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
     const Geom geo = geom_of(cfg);
     for (uint64_t i = 0; i < slots; i++) {
         p->desc[i].g = geo;
-        p->desc[i].fat = reinterpret_cast<uint32_t*>(p->base + i * (L.slot_fat + L.slot_slim));
-        p->desc[i].slim = reinterpret_cast<uint32_t*>(p->base + i * (L.slot_fat + L.slot_slim) + L.slot_fat);
+        p->desc[i].fat = reinterpret_cast<uint32_t*>(p->base + i * L.slot_bytes);
+        p->desc[i].slim = p->desc[i].fat + cfg->z;
     }
     e = hipMemcpy(p->d_desc, p->desc.data(), slots * sizeof(SketchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemsetAsync(p->meta, 0, sizeof(MergeMeta), p->stream);
@@ -299,7 +297,7 @@ int sf_pool_acquire(sf_pool* p, uint32_t* slot) {
     if (p->free_list.empty()) return fail(SF_ENOMEM, "no free slot in the pool's HBM budget");
     const uint32_t s = p->free_list.back();
     // zeroed on the pool stream: ordered after every launch that used the slot before
-    hipError_t e = hipMemsetAsync(p->desc[s].fat, 0, p->slot_fat + p->slot_slim, p->stream);
+    hipError_t e = hipMemsetAsync(p->desc[s].fat, 0, p->slot_bytes, p->stream);
     if (e != hipSuccess) return device_fail(e, "sf_pool_acquire");
     p->free_list.pop_back();
     p->in_use[s] = 1;
@@ -461,7 +459,7 @@ int sf_pool_export_slim(sf_pool* p, uint32_t slot, uint16_t* out, uint64_t out_e
     }
     uint16_t* dst = host ? p->stage : out;
     const unsigned grid = blocks_for(cells, kBlock) < 4096u ? blocks_for(cells, kBlock) : 4096u;
-    k_pack16<uint32_t><<<dim3(grid), dim3(kBlock), 0, p->stream>>>(p->desc[slot].slim, dst, cells);
+    k_pack16<uint32_t><<<dim3(grid), dim3(kBlock), 0, p->stream>>>(p->desc[slot].slim, dst, cells, p->desc[slot].g.rs, nullptr);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && host) e = hipMemcpyAsync(out, p->stage, cells * 2, hipMemcpyDeviceToHost, p->stream);
     if (e == hipSuccess && !async) e = hipStreamSynchronize(p->stream);
@@ -474,11 +472,17 @@ int sf_pool_export_fat(sf_pool* p, uint32_t slot, uint32_t* out, uint64_t out_el
     const uint64_t n = uint64_t(p->cfg.d) * p->cfg.w * p->cfg.z;
     if (!out) return fail(SF_EINVAL, "out is null");
     if (out_elems < n) return fail(SF_EINVAL, "out_elems < d*w*z");
-    if (!host_dest(out)) {
+    const bool host = host_dest(out);
+    if (!host) {
         int rc = check_gpu_ptr(out, n * 4, "out");
         if (rc) return rc;
     }
-    hipError_t e = hipMemcpyAsync(out, p->desc[slot].fat, n * 4, hipMemcpyDefault, p->stream);
+    uint32_t* dst = host ? reinterpret_cast<uint32_t*>(p->stage) : out;
+    const unsigned grid = blocks_for(n, kBlock) < 4096u ? blocks_for(n, kBlock) : 4096u;
+    k_unpack_fat<uint32_t><<<dim3(grid), dim3(kBlock), 0, p->stream>>>(
+        p->desc[slot].fat, dst, uint64_t(p->cfg.d) * p->cfg.w, p->cfg.z);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && host) e = hipMemcpyAsync(out, dst, n * 4, hipMemcpyDeviceToHost, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_pool_export_fat");
 }

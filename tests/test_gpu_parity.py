@@ -153,6 +153,31 @@ def test_query_exported_slim_collector():
         sk.close()
 
 
+def test_query_reads_exported_copy_only_while_fresh():
+    """sf_query answers from the sketch's dense copy made by sf_export_slim until
+    the next update or reset: before export, after export, after more updates
+    (stale copy must not be used), after reset -- all equal to the oracle."""
+    import torch
+    rng = np.random.default_rng(17)
+    keys, ops, uni = random_turnstile(rng, 30_000, 3000, 0.15)
+    half = keys.shape[0] // 2
+    ref = oracle.Sketch(4, 1024, 4)
+    sk = sf.Sketch(4, 1024, 4, batch_ops=5000)
+    dev16 = torch.empty(4 * 1024, dtype=torch.int16, device="cuda")
+    for lo, hi in ((0, half), (half, keys.shape[0])):
+        sk.update(dev_keys(keys[lo:hi]), torch.from_numpy(ops[lo:hi]).cuda())
+        assert ref.batch(keys[lo:hi], ops[lo:hi], 5000, checked=True) == 0
+        exp = ref.query(uni)
+        assert_same(sk.query(dev_keys(uni)).cpu().numpy().view(np.uint32), exp, "query before export")
+        sf.sf_export_slim(sk._h, dev16)                     # device destination
+        assert_same(dev16.cpu().numpy().view(np.uint16).reshape(4, 1024), ref.slim(), "exported Slim")
+        assert_same(sk.query(dev_keys(uni)).cpu().numpy().view(np.uint32), exp, "query after export")
+        assert_same(sk.export_slim(), ref.slim(), "second export (host destination)")
+    sk.reset()
+    assert not sk.query(dev_keys(uni)).cpu().numpy().any()
+    sk.close()
+
+
 def test_empty_and_tiny_inputs():
     import torch
     sk = sf.Sketch(4, 64, 4, batch_ops=8)
