@@ -463,10 +463,13 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, MergeMeta* 
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
         if (hist[b]) atomicAdd(&meta->total[b * kLine], hist[b]);
+
 }
 
 // One workgroup of 2*nb threads: bucket starts, cursors and chunk prefix;
-// clears the totals and the entry counters for the next batch.
+// clears the totals and the entry counters for the next batch.  (Folding
+// this into the counting kernel's last group costs more than the launch:
+// every group would need a device-scope fence, i.e. an L2 write-back.)
 template <int KB, bool G>
 __global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __restrict__ meta) {
     constexpr uint32_t chunk = MergeShape<KB, G>::kChunk;
@@ -690,20 +693,21 @@ __global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __res
         const uint32_t d = SF_ROWS(D, sd.g);
         const Mixed<KB> mx(m.k);
         size_t cell[R];
-        uint32_t a[R];
+        uint32_t cur[R];
         uint32_t m0 = ~0u, bmin = ~0u, delta = ~0u;
 #pragma unroll
         for (int i = 0; i < R; i++) {
             cell[i] = 0;
-            a[i] = kSlimMax;
+            cur[i] = kSlimMax;
             if (uint32_t(i) < d) {
                 uint32_t h, f;
                 split(sd.g, mx.row(sd.g.seed_base + i), h, f);
                 cell[i] = size_t(i) * sd.g.w + h;
-                a[i] = asnap[size_t(i) * stride + e];
-                const uint32_t post = sd.fat[cell[i] * sd.g.rs + f];
+                const uint32_t* rec = sd.fat + cell[i] * sd.g.rs;
+                const uint32_t post = rec[f];
+                cur[i] = rec[sd.g.z];  // the Slim word of the same record: no extra line
                 const uint32_t grew = post - bpre[size_t(i) * stride + e];
-                m0 = min(m0, a[i]);
+                m0 = min(m0, uint32_t(asnap[size_t(i) * stride + e]));
                 bmin = min(bmin, post);
                 delta = min(delta, grew);
             }
@@ -712,9 +716,11 @@ __global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __res
         const uint64_t level = m0 > bmin ? m0 : bmin;
         const uint64_t tt = rise < level ? rise : level;
         const uint32_t T = uint32_t(tt < kSlimMax ? tt : kSlimMax);
+        // Slim words only grow during S3 and cur is at least the snapshot, so a
+        // cell already at T or above (raised by another entry) needs no atomic.
 #pragma unroll
         for (int i = 0; i < R; i++)
-            if (uint32_t(i) < d && a[i] < T) atomic_max_u32(&sd.slim[cell[i] * sd.g.rs], T);
+            if (uint32_t(i) < d && cur[i] < T) atomic_max_u32(&sd.slim[cell[i] * sd.g.rs], T);
     }
 }
 
