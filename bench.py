@@ -39,7 +39,8 @@ def log(*a):
 def source_digest() -> str:
     """Digest of the kernel sources; a stored counter reading is valid only for it."""
     h = hashlib.sha256()
-    for rel in ("paper_1701_04148_amd/csrc/sf_lib.hip", "paper_1701_04148_amd/csrc/sf_device.hpp"):
+    for rel in ("paper_1701_04148_amd/csrc/sf_lib.hip", "paper_1701_04148_amd/csrc/sf_device.hpp",
+                "paper_1701_04148_amd/csrc/sf_kernels.hpp", "paper_1701_04148_amd/csrc/sf_host.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -65,8 +66,9 @@ def algorithmic_bytes(kind: str, d: int, u: dict) -> int:
 
 
 def random_accesses(kind: str, d: int, u: dict) -> int:
-    """Random (uncoalesced) accesses of a kernel kind over the timed steps."""
-    return {"snapshot": 2 * d * u["ie"], "fat_add": d * u["ie"], "raise": d * u["ie"],
+    """Random (uncoalesced) accesses of a kernel kind over the timed steps: one per cell
+    record touched (a record holds the cell's Fat bucket and Slim word), one per atomic."""
+    return {"snapshot": d * u["ie"], "fat_add": d * u["ie"], "raise": 2 * d * u["ie"],
             "fat_sub": d * u["de"], "clamp": 2 * d * u["de"], "query": d * u["q"]}.get(kind, 0)
 
 
@@ -102,8 +104,9 @@ KIND_OF_KERNEL = {"k_snapshot": "snapshot", "k_raise": "raise", "k_clamp": "clam
 
 
 def _kernel_base(name: str) -> str:
+    """Bare kernel name: no return type, namespace, template or argument list."""
     base = name.replace("(anonymous namespace)::", "").replace("void ", "").strip()
-    return base.split("(")[0].split("<")[0].strip()
+    return base.split("(")[0].split("<")[0].strip().split("::")[-1]
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int) -> dict:
