@@ -417,8 +417,7 @@ __device__ __forceinline__ uint32_t wave_peel(const T& v, bool valid, Eq eq, int
     return w;
 }
 
-constexpr int kPeel = 2;       // merging: keys
-constexpr int kPartPeel = 0;   // partitioning: buckets
+constexpr int kPeel = 2;
 
 struct MergeMeta {                    // device-side bookkeeping of one batch
     // per-bucket counters bumped by every partitioning workgroup: one per
@@ -450,20 +449,13 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, MergeMeta* 
     const Work w = plan.at(blockIdx.x, kPartOps);
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
     __syncthreads();
-    for (uint32_t base = 0; base < w.count; base += kPartThreads) {  // same trip count for the whole group
-        const uint32_t t = base + threadIdx.x;
-        uint32_t b = 0;
-        if (t < w.count) {
-            const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
-            b = bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2);
-        }
-        const uint32_t wgt = wave_peel<kPartPeel>(b, t < w.count, [](uint32_t x, uint32_t y) { return x == y; });
-        if (wgt) atomicAdd(&hist[b], wgt);
+    for (uint32_t t = threadIdx.x; t < w.count; t += kPartThreads) {
+        const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
+        atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u);
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
         if (hist[b]) atomicAdd(&meta->total[b * kLine], hist[b]);
-
 }
 
 // One workgroup of 2*nb threads: bucket starts, cursors and chunk prefix;
@@ -499,43 +491,75 @@ __global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __res
 }
 
 // Scatters the keys into their buckets (order inside a bucket is free).
+// uint32 keys are first sorted by bucket inside the group (LDS), so that the
+// group writes each bucket's keys as one contiguous run; wider keys go
+// straight to their slots.
 template <int KB, bool G, class P>
 __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, MergeMeta* __restrict__ meta,
                                                          MKey<KB, G>* __restrict__ part, uint32_t nb_log2) {
-    __shared__ uint32_t hist[2 * kMaxBuckets];
+    constexpr uint32_t R = kPartOps / kPartThreads;  // keys per thread
+    constexpr bool kStage = sizeof(MKey<KB, G>) <= 8;
+    __shared__ uint32_t hist[2 * kMaxBuckets];       // local counts, then the group's first global slot
+    __shared__ uint32_t lstart[2 * kMaxBuckets];     // exclusive prefix of the local counts
+    __shared__ MKey<KB, G> stage[kStage ? kPartOps : 1];
+    __shared__ uint16_t sbk[kStage ? kPartOps : 1];
     const uint32_t nbt = 2u << nb_log2;
     const Work w = plan.at(blockIdx.x, kPartOps);
-    constexpr uint32_t R = kPartOps / kPartThreads;  // keys per thread
     MKey<KB, G> k[R];
-    uint32_t bk[R];
+    uint32_t bk[R], rank[R];
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
     __syncthreads();
 #pragma unroll
     for (uint32_t r = 0; r < R; r++) {
         const uint32_t t = r * kPartThreads + threadIdx.x;
         bk[r] = 0;
+        rank[r] = 0;
         if (t < w.count) {
             k[r] = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
             bk[r] = bucket_of<KB, G>(k[r], is_delete(w.ops, t, w.mode), nb_log2);
+            rank[r] = atomicAdd(&hist[bk[r]], 1u);   // place among the group's keys of the bucket
         }
-        const uint32_t wgt = wave_peel<kPartPeel>(bk[r], t < w.count, [](uint32_t x, uint32_t y) { return x == y; });
-        if (wgt) atomicAdd(&hist[bk[r]], wgt);
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
-        if (hist[b]) hist[b] = atomicAdd(&meta->cursor[b * kLine], hist[b]);  // this group's first position
-    __syncthreads();
+    if constexpr (kStage) {
+        const uint32_t b = threadIdx.x;             // kPartThreads == 2 * kMaxBuckets >= nbt
+        const uint32_t v = b < nbt ? hist[b] : 0u;
+        lstart[b] = v;
+        __syncthreads();
+        for (uint32_t off = 1; off < nbt; off <<= 1) {  // inclusive scan
+            const uint32_t x = b >= off ? lstart[b - off] : 0u;
+            __syncthreads();
+            lstart[b] += x;
+            __syncthreads();
+        }
+        const uint32_t excl = lstart[b] - v;
+        __syncthreads();
+        lstart[b] = excl;
+        if (v) hist[b] = atomicAdd(&meta->cursor[b * kLine], v);
+        __syncthreads();
 #pragma unroll
-    for (uint32_t r = 0; r < R; r++) {
-        const uint32_t t = r * kPartThreads + threadIdx.x;
-        int leader;
-        uint32_t rank;
-        const uint32_t wgt = wave_peel<kPartPeel>(bk[r], t < w.count, [](uint32_t x, uint32_t y) { return x == y; },
-                                              &leader, &rank);
-        uint32_t pos = 0;
-        if (wgt) pos = atomicAdd(&hist[bk[r]], wgt);   // a leader reserves its whole group
-        const uint32_t lead_pos = __shfl(pos, leader);
-        if (t < w.count) part[(wgt ? pos : lead_pos) + (wgt ? 0u : rank)] = k[r];
+        for (uint32_t r = 0; r < R; r++) {
+            const uint32_t t = r * kPartThreads + threadIdx.x;
+            if (t < w.count) {
+                const uint32_t i = lstart[bk[r]] + rank[r];
+                stage[i] = k[r];
+                sbk[i] = uint16_t(bk[r]);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < w.count; i += kPartThreads) {
+            const uint32_t bb = sbk[i];
+            part[hist[bb] + (i - lstart[bb])] = stage[i];
+        }
+    } else {
+        for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
+            if (hist[b]) hist[b] = atomicAdd(&meta->cursor[b * kLine], hist[b]);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < R; r++) {
+            const uint32_t t = r * kPartThreads + threadIdx.x;
+            if (t < w.count) part[hist[bk[r]] + rank[r]] = k[r];
+        }
     }
 }
 
