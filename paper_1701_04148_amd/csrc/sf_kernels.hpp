@@ -357,20 +357,23 @@ template <int KB, bool G> struct MergeLDS {
     uint32_t slot[MergeShape<KB, G>::kSlots];
 };
 
-// Adds cnt copies of key k (local index idx) to the table.
+// Adds cnt copies of key k (local index idx) to the table.  Returns the slot
+// if this call created it (the key was new), else kEmpty.
 template <int KB, bool G>
-__device__ __forceinline__ void merge_insert(MergeLDS<KB, G>& L, const MKey<KB, G>& k, uint32_t idx, uint32_t cnt) {
+__device__ __forceinline__ uint32_t merge_insert(MergeLDS<KB, G>& L, const MKey<KB, G>& k, uint32_t idx,
+                                                 uint32_t cnt) {
     constexpr uint32_t mask = MergeShape<KB, G>::kSlots - 1;
     uint32_t s = mkey_hash<KB, G>(k) & mask;
     for (uint32_t probe = 0; probe < MergeShape<KB, G>::kSlots; probe++) {
         const uint32_t prev = atomicCAS(&L.slot[s], kEmpty, (idx << 16) | cnt);
-        if (prev == kEmpty) return;
+        if (prev == kEmpty) return s;
         if (mkey_eq<KB, G>(L.key[prev >> 16], k)) {
             atomicAdd(&L.slot[s], cnt);  // counts stay < 2^16: never carry into the owner
-            return;
+            return kEmpty;
         }
         s = (s + 1) & mask;
     }
+    return kEmpty;
 }
 
 // Value of x in lane `lane` (wave-uniform) of the wavefront.
@@ -603,31 +606,39 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
         }
     }
     __syncthreads();
+    uint32_t made[J];                             // slots this thread created (one per new key)
+    uint32_t mine = 0;
 #pragma unroll
     for (int j = 0; j < J; j++) {
         const uint32_t idx = uint32_t(j) * kThreads + threadIdx.x;
         const uint32_t wgt = wave_peel<kPeel>(k[j], idx < n, [](const MKey<KB, G>& a, const MKey<KB, G>& b) {
             return mkey_eq<KB, G>(a, b);
         });
-        if (wgt) merge_insert<KB, G>(L, k[j], idx, wgt);
+        made[j] = wgt ? merge_insert<KB, G>(L, k[j], idx, wgt) : kEmpty;
+        mine += made[j] != kEmpty;
     }
-    __syncthreads();
-    uint32_t mine = 0;                            // entries this thread will emit
-    for (uint32_t s = threadIdx.x; s < kSlots; s += kThreads) mine += L.slot[s] != kEmpty;
-    uint32_t rank = atomicAdd(&nloc, mine);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        base = atomicAdd(del ? &meta->n_del : &meta->n_ins, nloc);
+    // The creator of a slot emits its entry: a wavefront prefix sum of the
+    // creators' counts, one LDS atomic per wavefront, one global atomic per group.
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t x = __shfl_up(incl, off);
+        if (int(lane_id()) >= off) incl += x;
     }
+    uint32_t wbase = 0;
+    if (lane_id() == 63u) wbase = atomicAdd(&nloc, incl);
+    wbase = __shfl(wbase, 63);
+    __syncthreads();                              // every count final, nloc complete
+    if (threadIdx.x == 0) base = atomicAdd(del ? &meta->n_del : &meta->n_ins, nloc);
     __syncthreads();
-    rank += base;
-    for (uint32_t s = threadIdx.x; s < kSlots; s += kThreads) {
-        const uint32_t v = L.slot[s];
-        if (v == kEmpty) continue;
+    uint32_t rank = base + wbase + incl - mine;
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        if (made[j] == kEmpty) continue;
         const uint32_t id = del ? cap - 1 - rank : rank;
         rank++;
-        ent_key[id] = L.key[v >> 16];
-        ent_cnt[id] = v & 0xffffu;
+        ent_key[id] = k[j];
+        ent_cnt[id] = L.slot[made[j]] & 0xffffu;
     }
 }
 
