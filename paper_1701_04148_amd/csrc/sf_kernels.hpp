@@ -335,18 +335,19 @@ template <int KB, bool G> __device__ __forceinline__ uint32_t mkey_hash(const MK
 }
 
 template <int KB, bool G> struct MergeShape {  // LDS table of the merging kernel
-    // 4096 uint32 keys or 2048 13-byte keys per chunk: 53..73 KB of LDS, so
-    // 2-3 workgroups of 8 waves share a CU
-    static constexpr uint32_t kThreads = 512;
+    // 8192 uint32 keys (100-132 KB of LDS, one group of 16 waves per CU) or
+    // 2048 13-byte keys (61 KB, two groups of 8 waves) per chunk
+    static constexpr uint32_t kThreads = KB == 4 ? 1024 : 512;
     static constexpr int J = KB == 4 ? 8 : 4;
     static constexpr uint32_t kChunk = kThreads * J;
     static constexpr uint32_t kSlots = 2 * kChunk;
 };
 
-// Bucket count for a batch of cnt ops: about two chunks of ops per bucket.
+// Bucket count for a batch of cnt ops: about one chunk of ops per bucket, so
+// that few keys are split between two chunks (each part becomes an entry).
 template <int KB, bool G> __host__ __device__ inline uint32_t buckets_for(uint64_t cnt) {
     uint32_t nb = 16;
-    while (nb < kMaxBuckets && uint64_t(nb) * 2 * MergeShape<KB, G>::kChunk < cnt) nb <<= 1;
+    while (nb < kMaxBuckets && uint64_t(nb) * MergeShape<KB, G>::kChunk < cnt) nb <<= 1;
     return nb;
 }
 
