@@ -57,6 +57,8 @@ struct sf_group {
     void* ent_key;
     uint32_t* ent_cnt;
     MergeMeta* meta;
+    uint32_t* hist;                // per-group bucket histograms of a merged sub-round
+    uint64_t hist_groups;          // partition groups (tiles) a merged sub-round may have
     uint32_t tile_j;
     bool use_graph;
     bool merge;                    // batch-merge path (default) or per-tile merging
@@ -93,10 +95,11 @@ bool live(const sf_group* g) {
 }
 
 constexpr uint64_t kMergeRound = 1ull << 22;
+constexpr uint64_t kHistExtra = 1024;  // partial tiles (one per sketch) a merged sub-round may add
 
 struct Layout {
     std::vector<uint64_t> fat_off;  // each sketch's cell records (Fat bucket + Slim per cell)
-    uint64_t state, desc, stage, bpre, asnap, part, ent_key, ent_cnt, meta, total;
+    uint64_t state, desc, stage, bpre, asnap, part, ent_key, ent_cnt, meta, hist, total;
     uint64_t round_ops, merge_round;
     uint32_t d_max;
 };
@@ -143,6 +146,8 @@ int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) 
     off += round256(L.merge_round * 4);
     L.meta = off;
     off += round256(sizeof(MergeMeta));
+    L.hist = off;
+    off += round256(part_groups_max(L.merge_round, kHistExtra) * 2 * kMaxBuckets * 4);
     L.total = off;
     return SF_OK;
 }
@@ -200,6 +205,7 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
     g->subrounds.clear();
     const uint32_t tile_ops = g->merge ? kPartOps : uint32_t(kBlock) * g->tile_j;
     const uint64_t limit = g->merge ? g->merge_round : g->round_ops;
+    const uint64_t max_tiles = g->merge ? g->hist_groups : ~0ull;
     uint64_t rounds = 0;
     for (uint32_t s = 0; s < g->n; s++) {
         const uint64_t len = seg[s + 1] - seg[s], b = g->cfg[s].batch_ops;
@@ -213,7 +219,8 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
             const uint64_t lo = seg[s] + k * b;
             if (lo >= seg[s + 1]) continue;
             const uint64_t cnt = std::min(b, seg[s + 1] - lo);
-            if (used + cnt > limit) {  // close the sub-round
+            const uint64_t tiles = (cnt + tile_ops - 1) / tile_ops;
+            if (used && (used + cnt > limit || g->plan.size() - first + tiles > max_tiles)) {  // close the sub-round
                 g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used});
                 first = uint32_t(g->plan.size());
                 used = 0;
@@ -237,7 +244,7 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
 template <int KB>
 void launch_plan(sf_group* g, bool ins, bool del, Profiler* prof) {
     const MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(g->part), static_cast<MKey<KB, true>*>(g->ent_key),
-                                 g->ent_cnt, g->meta, uint32_t(g->merge_round), g->bpre, g->asnap,
+                                 g->ent_cnt, g->meta, g->hist, uint32_t(g->merge_round), g->bpre, g->asnap,
                                  uint32_t(g->round_ops)};
     const SketchTable table{g->d_desc};
     for (auto& sr : g->subrounds) {
@@ -391,6 +398,8 @@ int sf_group_create(uint32_t n, const sf_config* cfgs, uint64_t round_ops, uint6
     g->ent_key = g->base + L.ent_key;
     g->ent_cnt = reinterpret_cast<uint32_t*>(g->base + L.ent_cnt);
     g->meta = reinterpret_cast<MergeMeta*>(g->base + L.meta);
+    g->hist = reinterpret_cast<uint32_t*>(g->base + L.hist);
+    g->hist_groups = part_groups_max(L.merge_round, kHistExtra);
     e = hipMemcpy(g->d_desc, g->desc.data(), n * sizeof(SketchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemsetAsync(g->base, 0, L.state, g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->meta, 0, sizeof(MergeMeta), g->stream);

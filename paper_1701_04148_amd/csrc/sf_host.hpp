@@ -210,6 +210,7 @@ struct MergeRun {
     MKey<KB, G>* ent_key;  // [cap] entries: inserts from 0 up, deletes from cap-1 down
     uint32_t* ent_cnt;     // [cap]
     MergeMeta* meta;
+    uint32_t* hist;        // [part groups][2 * kMaxBuckets] per-group bucket histograms / offsets
     uint32_t cap;
     uint32_t* bpre;        // [d][stride] S1 snapshot of Fat counters, per insert entry
     uint16_t* asnap;       // [d][stride] S1 snapshot of Slim counters, per insert entry
@@ -225,9 +226,11 @@ struct MergeRun {
         const unsigned eg = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
         {
             Timed tm(prof, st, SF_K_PARTITION, cnt);
-            k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, meta, nb_log2);
+            k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, nb_log2);
+            k_part_colscan<uint32_t><<<blocks_for(2 * nb, kScanBuckets), kScanBuckets * kScanSegs, 0, st>>>(
+                hist, part_groups, 2 * nb, meta);
             k_part_start<KB, G><<<1, 2 * nb, 0, st>>>(meta);
-            k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, meta, part, nb_log2);
+            k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, meta, part, nb_log2);
         }
         {
             Timed tm(prof, st, SF_K_MERGE, cnt);

@@ -303,7 +303,11 @@ namespace sfk {
 constexpr uint32_t kMaxBuckets = 512;          // per op type; the runtime nb is a power of two <= this
 constexpr uint32_t kPartOps = 8192;            // ops per partitioning workgroup
 constexpr uint32_t kPartThreads = 1024;        // its threads (16 waves)
-constexpr uint32_t kLine = 32;                 // uint32 words per 128-byte line
+// Partitioning groups one batch (or merged sub-round) of cap ops may use:
+// full tiles plus one partial tile per sketch, at most extra sketches.
+__host__ __device__ constexpr uint64_t part_groups_max(uint64_t cap, uint64_t extra) {
+    return (cap + kPartOps - 1) / kPartOps + extra;
+}
 
 template <int KB, bool G> struct MKey { Key<KB> k; };
 template <int KB> struct MKey<KB, true> { Key<KB> k; uint32_t s; };
@@ -424,12 +428,9 @@ __device__ __forceinline__ uint32_t wave_peel(const T& v, bool valid, Eq eq, int
 constexpr int kPeel = 2;
 
 struct MergeMeta {                    // device-side bookkeeping of one batch
-    // per-bucket counters bumped by every partitioning workgroup: one per
-    // kLine words, i.e. one 128-byte line each
-    uint32_t total[2 * kMaxBuckets * kLine];  // keys per bucket (zeroed again by k_part_start)
+    uint32_t total[2 * kMaxBuckets];  // keys per bucket (written by k_part_colscan)
     uint32_t start[2 * kMaxBuckets];  // first position of each bucket in the partitioned keys
     uint32_t size[2 * kMaxBuckets];
-    uint32_t cursor[2 * kMaxBuckets * kLine];  // scatter cursors
     uint32_t chunk0[2 * kMaxBuckets + 1];  // first chunk of each bucket (prefix)
     // Entries emitted.  Every merging workgroup bumps one of these once, so
     // each sits on its own 256-byte line (atomics on one line serialise).
@@ -439,15 +440,21 @@ struct MergeMeta {                    // device-side bookkeeping of one batch
     unsigned long long acc_del;
 };
 
+// The partition takes no global atomics: each group writes its bucket
+// histogram to its row of hist [groups][nbt]; k_part_colscan turns every
+// column into the groups' offsets inside the bucket (and the bucket total);
+// k_part_start lays the buckets out; k_part_scatter adds the two.
+
 // Bucket of a key: top log2(nb) bits of its hash (the LDS table uses low bits).
 template <int KB, bool G>
 __device__ __forceinline__ uint32_t bucket_of(const MKey<KB, G>& k, bool del, uint32_t nb_log2) {
     return (mkey_hash<KB, G>(k) >> (32u - nb_log2)) + (del ? (1u << nb_log2) : 0u);
 }
 
-// Counts the ops of every bucket.
+// Counts the ops of every bucket in each group's tile.
 template <int KB, bool G, class P>
-__global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, MergeMeta* __restrict__ meta, uint32_t nb_log2) {
+__global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* __restrict__ hist_out,
+                                                         uint32_t nb_log2) {
     __shared__ uint32_t hist[2 * kMaxBuckets];
     const uint32_t nbt = 2u << nb_log2;
     const Work w = plan.at(blockIdx.x, kPartOps);
@@ -458,20 +465,45 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, MergeMeta* 
         atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u);
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
-        if (hist[b]) atomicAdd(&meta->total[b * kLine], hist[b]);
+    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist_out[size_t(blockIdx.x) * nbt + b] = hist[b];
 }
 
-// One workgroup of 2*nb threads: bucket starts, cursors and chunk prefix;
-// clears the totals and the entry counters for the next batch.  (Folding
-// this into the counting kernel's last group costs more than the launch:
-// every group would need a device-scope fence, i.e. an L2 write-back.)
+// Column scans of hist: 16 buckets per workgroup, the groups split into 16
+// segments.  hist[g][b] becomes the number of bucket-b keys of groups < g.
+constexpr uint32_t kScanBuckets = 16, kScanSegs = 16;
+template <typename T>
+__global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan(
+    T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
+    __shared__ T seg_sum[kScanSegs][kScanBuckets];
+    const uint32_t lb = threadIdx.x % kScanBuckets, sg = threadIdx.x / kScanBuckets;
+    const uint32_t b = blockIdx.x * kScanBuckets + lb;
+    const uint32_t rows = (groups + kScanSegs - 1) / kScanSegs;
+    const uint32_t g0 = sg * rows, g1 = min(groups, g0 + rows);
+    T sum = 0;
+    if (b < nbt)
+        for (uint32_t g = g0; g < g1; g++) sum += hist[size_t(g) * nbt + b];
+    seg_sum[sg][lb] = sum;
+    __syncthreads();
+    T run = 0;                                    // keys of this bucket in earlier segments
+    for (uint32_t s2 = 0; s2 < sg; s2++) run += seg_sum[s2][lb];
+    if (b < nbt) {
+        for (uint32_t g = g0; g < g1; g++) {
+            const T v = hist[size_t(g) * nbt + b];
+            hist[size_t(g) * nbt + b] = run;
+            run += v;
+        }
+        if (sg == kScanSegs - 1) meta->total[b] = run;
+    }
+}
+
+// One workgroup of 2*nb threads: bucket starts and chunk prefix; clears the
+// entry counters for the next batch.
 template <int KB, bool G>
 __global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __restrict__ meta) {
     constexpr uint32_t chunk = MergeShape<KB, G>::kChunk;
     __shared__ uint32_t a[2 * kMaxBuckets], c[2 * kMaxBuckets];
     const uint32_t b = threadIdx.x, nbt = blockDim.x;
-    const uint32_t sz = meta->total[b * kLine];
+    const uint32_t sz = meta->total[b];
     a[b] = sz;
     c[b] = (sz + chunk - 1) / chunk;
     __syncthreads();
@@ -484,14 +516,12 @@ __global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __res
     }
     meta->size[b] = sz;
     meta->start[b] = a[b] - sz;
-    meta->cursor[b * kLine] = a[b] - sz;
     meta->chunk0[b + 1] = c[b];
     if (b == 0) {
         meta->chunk0[0] = 0;
         meta->n_ins = 0;
         meta->n_del = 0;
     }
-    meta->total[b * kLine] = 0;
 }
 
 // Scatters the keys into their buckets (order inside a bucket is free).
@@ -499,7 +529,8 @@ __global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __res
 // group writes each bucket's keys as one contiguous run; wider keys go
 // straight to their slots.
 template <int KB, bool G, class P>
-__global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, MergeMeta* __restrict__ meta,
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uint32_t* __restrict__ offs,
+                                                         const MergeMeta* __restrict__ meta,
                                                          MKey<KB, G>* __restrict__ part, uint32_t nb_log2) {
     constexpr uint32_t R = kPartOps / kPartThreads;  // keys per thread
     constexpr bool kStage = sizeof(MKey<KB, G>) <= 8;
@@ -539,7 +570,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, MergeMeta
         const uint32_t excl = lstart[b] - v;
         __syncthreads();
         lstart[b] = excl;
-        if (v) hist[b] = atomicAdd(&meta->cursor[b * kLine], v);
+        if (b < nbt) hist[b] = meta->start[b] + offs[size_t(blockIdx.x) * nbt + b];
         __syncthreads();
 #pragma unroll
         for (uint32_t r = 0; r < R; r++) {
@@ -556,8 +587,9 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, MergeMeta
             part[hist[bb] + (i - lstart[bb])] = stage[i];
         }
     } else {
+        __syncthreads();
         for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
-            if (hist[b]) hist[b] = atomicAdd(&meta->cursor[b * kLine], hist[b]);
+            hist[b] = meta->start[b] + offs[size_t(blockIdx.x) * nbt + b];
         __syncthreads();
 #pragma unroll
         for (uint32_t r = 0; r < R; r++) {

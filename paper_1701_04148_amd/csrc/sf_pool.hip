@@ -50,6 +50,8 @@ struct sf_pool {
     void* ent_key;
     uint32_t* ent_cnt;
     MergeMeta* meta;
+    uint32_t* hist;                // per-group bucket histograms of a merged sub-round
+    uint64_t hist_groups;          // partition groups (tiles) a merged sub-round may have
     uint32_t tile_j;
     bool merge;
     std::vector<uint8_t> in_use;
@@ -81,6 +83,7 @@ bool live(const sf_pool* p) {
 }
 
 constexpr size_t kRingTiles = size_t(1) << 21;  // 2M tiles (80 MiB) of in-flight descriptors
+constexpr uint64_t kHistExtra = 1024;            // partial tiles (one per request) a merged sub-round may add
 
 struct PoolLayout {
     uint64_t slot_bytes, per_slot, shared, round_ops, merge_round, mkey;
@@ -101,7 +104,8 @@ PoolLayout pool_layout(const sf_config* c, uint64_t round_ops) {
     L.mkey = c->key_bytes == 4 ? sizeof(MKey<4, true>) : sizeof(MKey<13, true>);
     L.shared = round256(uint64_t(c->d) * L.round_ops * 4) + round256(uint64_t(c->d) * L.round_ops * 2) +
                round256(cells * c->z * 4) + round256(kRingTiles * sizeof(TileDesc)) +
-               2 * round256(L.merge_round * L.mkey) + round256(L.merge_round * 4) + round256(sizeof(MergeMeta));
+               2 * round256(L.merge_round * L.mkey) + round256(L.merge_round * 4) + round256(sizeof(MergeMeta)) +
+               round256(part_groups_max(L.merge_round, kHistExtra) * 2 * kMaxBuckets * 4);
     return L;
 }
 
@@ -145,7 +149,7 @@ template <int KB>
 void launch_updates(sf_pool* p, const TileDesc* d_tiles, const std::vector<SubRound>& subs,
                     const std::vector<TileDesc>& host) {
     const MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(p->part), static_cast<MKey<KB, true>*>(p->ent_key),
-                                 p->ent_cnt, p->meta, uint32_t(p->merge_round), p->bpre, p->asnap,
+                                 p->ent_cnt, p->meta, p->hist, uint32_t(p->merge_round), p->bpre, p->asnap,
                                  uint32_t(p->round_ops)};
     const SketchTable table{p->d_desc};
     for (auto& sr : subs) {
@@ -242,6 +246,9 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
     p->ent_cnt = reinterpret_cast<uint32_t*>(q);
     q += round256(L.merge_round * 4);
     p->meta = reinterpret_cast<MergeMeta*>(q);
+    q += round256(sizeof(MergeMeta));
+    p->hist = reinterpret_cast<uint32_t*>(q);
+    p->hist_groups = part_groups_max(L.merge_round, kHistExtra);
     p->desc.resize(slots);
     const Geom geo = geom_of(cfg);
     for (uint64_t i = 0; i < slots; i++) {
@@ -340,6 +347,7 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
     // round_ops (merged: merge_round, tiles of kPartOps ops for the partition kernels)
     const uint32_t tile_ops = p->merge ? kPartOps : uint32_t(kBlock) * p->tile_j;
     const uint64_t limit = p->merge ? p->merge_round : p->round_ops;
+    const uint64_t max_tiles = p->merge ? p->hist_groups : ~0ull;
     const uint64_t b = p->cfg.batch_ops;
     std::vector<TileDesc> tiles;
     std::vector<SubRound> subs;
@@ -353,7 +361,8 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
             const sf_request& q = reqs[r];
             if (q.kind == SF_REQ_QUERY || k * b >= q.n) continue;
             const uint64_t lo = k * b, cnt = std::min(b, q.n - lo);
-            if (used + cnt > limit) {
+            const uint64_t ntiles = (cnt + tile_ops - 1) / tile_ops;
+            if (used && (used + cnt > limit || tiles.size() - first + ntiles > max_tiles)) {
                 subs.push_back({first, uint32_t(tiles.size()) - first, used});
                 first = uint32_t(tiles.size());
                 used = 0;
