@@ -58,6 +58,7 @@ struct sf_group {
     uint32_t* ent_cnt;
     MergeMeta* meta;
     uint32_t* hist;                // per-group bucket histograms of a merged sub-round
+    MergeChunk* chunks;            // key range of every merge chunk of a merged sub-round
     uint64_t hist_groups;          // partition groups (tiles) a merged sub-round may have
     uint32_t tile_j;
     bool use_graph;
@@ -99,7 +100,7 @@ constexpr uint64_t kHistExtra = 1024;  // partial tiles (one per sketch) a merge
 
 struct Layout {
     std::vector<uint64_t> fat_off;  // each sketch's cell records (Fat bucket + Slim per cell)
-    uint64_t state, desc, stage, bpre, asnap, part, ent_key, ent_cnt, meta, hist, total;
+    uint64_t state, desc, stage, bpre, asnap, part, ent_key, ent_cnt, meta, hist, chunks, total;
     uint64_t round_ops, merge_round;
     uint32_t d_max;
 };
@@ -148,6 +149,8 @@ int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) 
     off += round256(sizeof(MergeMeta));
     L.hist = off;
     off += round256(part_groups_max(L.merge_round, kHistExtra) * 2 * kMaxBuckets * 4);
+    L.chunks = off;
+    off += round256(merge_chunks_max(L.merge_round) * sizeof(MergeChunk));
     L.total = off;
     return SF_OK;
 }
@@ -244,7 +247,8 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
 template <int KB>
 void launch_plan(sf_group* g, bool ins, bool del, Profiler* prof) {
     const MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(g->part), static_cast<MKey<KB, true>*>(g->ent_key),
-                                 g->ent_cnt, g->meta, g->hist, uint32_t(g->merge_round), g->bpre, g->asnap,
+                                 g->ent_cnt, g->meta, g->hist, g->chunks, uint32_t(g->merge_round), g->bpre,
+                                 g->asnap,
                                  uint32_t(g->round_ops)};
     const SketchTable table{g->d_desc};
     for (auto& sr : g->subrounds) {
@@ -399,6 +403,7 @@ int sf_group_create(uint32_t n, const sf_config* cfgs, uint64_t round_ops, uint6
     g->ent_cnt = reinterpret_cast<uint32_t*>(g->base + L.ent_cnt);
     g->meta = reinterpret_cast<MergeMeta*>(g->base + L.meta);
     g->hist = reinterpret_cast<uint32_t*>(g->base + L.hist);
+    g->chunks = reinterpret_cast<MergeChunk*>(g->base + L.chunks);
     g->hist_groups = part_groups_max(L.merge_round, kHistExtra);
     e = hipMemcpy(g->d_desc, g->desc.data(), n * sizeof(SketchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemsetAsync(g->base, 0, L.state, g->stream);

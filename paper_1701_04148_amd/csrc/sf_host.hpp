@@ -211,6 +211,7 @@ struct MergeRun {
     uint32_t* ent_cnt;     // [cap]
     MergeMeta* meta;
     uint32_t* hist;        // [part groups][2 * kMaxBuckets] per-group bucket histograms / offsets
+    MergeChunk* chunks;    // [merge_chunks_max(cap)] key range of every merge chunk
     uint32_t cap;
     uint32_t* bpre;        // [d][stride] S1 snapshot of Fat counters, per insert entry
     uint16_t* asnap;       // [d][stride] S1 snapshot of Slim counters, per insert entry
@@ -229,13 +230,13 @@ struct MergeRun {
             k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, nb_log2);
             k_part_colscan<uint32_t><<<blocks_for(2 * nb, kScanBuckets), kScanBuckets * kScanSegs, 0, st>>>(
                 hist, part_groups, 2 * nb, meta);
-            k_part_start<KB, G><<<1, 2 * nb, 0, st>>>(meta);
+            k_part_start<KB, G><<<1, 2 * nb, 0, st>>>(meta, chunks);
             k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, meta, part, nb_log2);
         }
         {
             Timed tm(prof, st, SF_K_MERGE, cnt);
             k_merge<KB, G><<<blocks_for(cnt, MergeShape<KB, G>::kChunk) + 2 * nb, MergeShape<KB, G>::kThreads, 0, st>>>(
-                part, meta, ent_key, ent_cnt, cap, nb_log2);
+                part, meta, chunks, ent_key, ent_cnt, cap, nb_log2);
         }
         if (ins) {
             {

@@ -339,13 +339,25 @@ template <int KB, bool G> __device__ __forceinline__ uint32_t mkey_hash(const MK
 }
 
 template <int KB, bool G> struct MergeShape {  // LDS table of the merging kernel
-    // 8192 uint32 keys (100-132 KB of LDS, one group of 16 waves per CU) or
-    // 2048 13-byte keys (61 KB, two groups of 8 waves) per chunk
+    // Chunks of 8192 uint32 keys (16 waves) or 2048 13-byte keys (8 waves).
+    // A lone sketch's table has 12280 slots (load <= 2/3), so keys and slots
+    // take just under 80 KB and two groups share a CU; the others use 2x the
+    // chunk (pow2 slots: 128 KB with the sketch index, 57 KB for 13-byte keys).
     static constexpr uint32_t kThreads = KB == 4 ? 1024 : 512;
     static constexpr int J = KB == 4 ? 8 : 4;
     static constexpr uint32_t kChunk = kThreads * J;
-    static constexpr uint32_t kSlots = 2 * kChunk;
+    static constexpr uint32_t kSlots = (KB == 4 && !G) ? 12280u : 2 * kChunk;
+    static constexpr bool kPow2 = (kSlots & (kSlots - 1)) == 0;
 };
+constexpr uint32_t kMinChunk = 2048;  // smallest kChunk of any shape
+
+// One merge chunk: a range of the partitioned keys inside one bucket.
+struct MergeChunk {
+    uint32_t first, n, del;
+};
+// Chunks one batch (or merged sub-round) of cap ops can have: full chunks
+// plus one partial chunk per bucket.
+__host__ __device__ constexpr uint64_t merge_chunks_max(uint64_t cap) { return cap / kMinChunk + 2 * 1024 + 1; }
 
 // Bucket count for a batch of cnt ops: about one chunk of ops per bucket, so
 // that few keys are split between two chunks (each part becomes an entry).
@@ -367,16 +379,18 @@ template <int KB, bool G> struct MergeLDS {
 template <int KB, bool G>
 __device__ __forceinline__ uint32_t merge_insert(MergeLDS<KB, G>& L, const MKey<KB, G>& k, uint32_t idx,
                                                  uint32_t cnt) {
-    constexpr uint32_t mask = MergeShape<KB, G>::kSlots - 1;
-    uint32_t s = mkey_hash<KB, G>(k) & mask;
-    for (uint32_t probe = 0; probe < MergeShape<KB, G>::kSlots; probe++) {
+    constexpr uint32_t kSlots = MergeShape<KB, G>::kSlots;
+    const uint32_t h = mkey_hash<KB, G>(k);
+    // the bucket came from the hash's top bits, so the slot takes the low ones
+    uint32_t s = MergeShape<KB, G>::kPow2 ? (h & (kSlots - 1)) : __umulhi(__builtin_rotateleft32(h, 16), kSlots);
+    for (uint32_t probe = 0; probe < kSlots; probe++) {
         const uint32_t prev = atomicCAS(&L.slot[s], kEmpty, (idx << 16) | cnt);
         if (prev == kEmpty) return s;
         if (mkey_eq<KB, G>(L.key[prev >> 16], k)) {
             atomicAdd(&L.slot[s], cnt);  // counts stay < 2^16: never carry into the owner
             return kEmpty;
         }
-        s = (s + 1) & mask;
+        s = s + 1 == kSlots ? 0u : s + 1;
     }
     return kEmpty;
 }
@@ -496,10 +510,11 @@ __global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan(
     }
 }
 
-// One workgroup of 2*nb threads: bucket starts and chunk prefix; clears the
-// entry counters for the next batch.
+// One workgroup of 2*nb threads: bucket starts, the chunk prefix and every
+// chunk's key range; clears the entry counters for the next batch.
 template <int KB, bool G>
-__global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __restrict__ meta) {
+__global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __restrict__ meta,
+                                                                MergeChunk* __restrict__ chunks) {
     constexpr uint32_t chunk = MergeShape<KB, G>::kChunk;
     __shared__ uint32_t a[2 * kMaxBuckets], c[2 * kMaxBuckets];
     const uint32_t b = threadIdx.x, nbt = blockDim.x;
@@ -517,6 +532,9 @@ __global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __res
     meta->size[b] = sz;
     meta->start[b] = a[b] - sz;
     meta->chunk0[b + 1] = c[b];
+    const uint32_t c0 = c[b] - (sz + chunk - 1) / chunk;  // this bucket's first chunk
+    for (uint32_t q = 0; q * chunk < sz; q++)
+        chunks[c0 + q] = MergeChunk{a[b] - sz + q * chunk, min(chunk, sz - q * chunk), b >= nbt / 2 ? 1u : 0u};
     if (b == 0) {
         meta->chunk0[0] = 0;
         meta->n_ins = 0;
@@ -604,31 +622,24 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
 // [cap - n_del, cap)).
 template <int KB, bool G>
 __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const MKey<KB, G>* __restrict__ part,
-                                                  MergeMeta* __restrict__ meta, MKey<KB, G>* __restrict__ ent_key,
+                                                  MergeMeta* __restrict__ meta,
+                                                  const MergeChunk* __restrict__ chunks,
+                                                  MKey<KB, G>* __restrict__ ent_key,
                                                   uint32_t* __restrict__ ent_cnt, uint32_t cap, uint32_t nb_log2) {
     constexpr int J = MergeShape<KB, G>::J;
     constexpr uint32_t kThreads = MergeShape<KB, G>::kThreads;
-    constexpr uint32_t kChunk = MergeShape<KB, G>::kChunk, kSlots = MergeShape<KB, G>::kSlots;
+    constexpr uint32_t kSlots = MergeShape<KB, G>::kSlots;
     __shared__ MergeLDS<KB, G> L;
-    __shared__ uint32_t chunk0[2 * kMaxBuckets + 1];
     __shared__ uint32_t nloc, base;
     const uint32_t nbt = 2u << nb_log2;
     const uint32_t c = blockIdx.x;
     if (c >= meta->chunk0[nbt]) return;
-    for (uint32_t i = threadIdx.x; i <= nbt; i += kThreads) chunk0[i] = meta->chunk0[i];
+    const MergeChunk ck = chunks[c];
+    const bool del = ck.del != 0;
+    const uint32_t first = ck.first, n = ck.n;
     for (uint32_t i = threadIdx.x; i < kSlots; i += kThreads) L.slot[i] = kEmpty;
     if (threadIdx.x == 0) nloc = 0;
     __syncthreads();
-    uint32_t lo = 0, hi = nbt;                    // bucket b with chunk0[b] <= c < chunk0[b+1]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (chunk0[mid] <= c) lo = mid; else hi = mid;
-    }
-    const uint32_t b = lo;
-    const bool del = b >= (nbt >> 1);
-    const uint32_t first = meta->start[b] + (c - chunk0[b]) * kChunk;
-    const uint32_t end = meta->start[b] + meta->size[b];
-    const uint32_t n = end - first < kChunk ? end - first : kChunk;
     MKey<KB, G> k[J];
 #pragma unroll
     for (int j = 0; j < J; j++) {

@@ -54,6 +54,7 @@ struct sf_sketch {
     void* ent_key;    // batch merge: one key per merged entry        [b] keys
     uint32_t* ent_cnt;//              its op count                    [b]
     uint32_t* hist;   //              per-group bucket histograms     [b/8192+1][1024]
+    MergeChunk* chunks;//             key range of every merge chunk
     MergeMeta* meta;
     Profiler prof;
 };
@@ -69,9 +70,9 @@ bool live(const sf_sketch* s) {
 }
 
 struct Sizes {
-    uint64_t fat, slim, stage, view, bpre, asnap, part, ent_key, ent_cnt, meta, hist;
+    uint64_t fat, slim, stage, view, bpre, asnap, part, ent_key, ent_cnt, meta, hist, chunks;
     uint64_t total() const {
-        return fat + slim + stage + view + bpre + asnap + part + ent_key + ent_cnt + meta + hist;
+        return fat + slim + stage + view + bpre + asnap + part + ent_key + ent_cnt + meta + hist + chunks;
     }
 };
 
@@ -90,6 +91,7 @@ Sizes sizes_of(const sf_config* c) {
     s.ent_cnt = round256(uint64_t(c->batch_ops) * 4);
     s.meta = round256(sizeof(MergeMeta));
     s.hist = round256(part_groups_max(c->batch_ops, 1) * 2 * kMaxBuckets * 4);
+    s.chunks = round256(merge_chunks_max(c->batch_ops) * sizeof(MergeChunk));
     return s;
 }
 
@@ -97,7 +99,7 @@ Sizes sizes_of(const sf_config* c) {
 template <int KB, int D>
 void launch_merged(sf_sketch* s, const UniformPlan<KB>& plan, uint32_t cnt, bool ins, bool del) {
     MergeRun<KB, false> run{static_cast<MKey<KB, false>*>(s->part), static_cast<MKey<KB, false>*>(s->ent_key),
-                            s->ent_cnt, s->meta, s->hist, s->stride, s->bpre, s->asnap, s->stride};
+                            s->ent_cnt, s->meta, s->hist, s->chunks, s->stride, s->bpre, s->asnap, s->stride};
     run.template launch<D>(plan, blocks_for(cnt, kPartOps), cnt, OneSketch{s->g, s->fat, s->slim}, ins, del,
                            s->stream, &s->prof);
 }
@@ -224,6 +226,7 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     s->ent_cnt = reinterpret_cast<uint32_t*>(mq + sz.part + sz.ent_key);
     s->meta = reinterpret_cast<MergeMeta*>(mq + sz.part + sz.ent_key + sz.ent_cnt);
     s->hist = reinterpret_cast<uint32_t*>(mq + sz.part + sz.ent_key + sz.ent_cnt + sz.meta);
+    s->chunks = reinterpret_cast<MergeChunk*>(mq + sz.part + sz.ent_key + sz.ent_cnt + sz.meta + sz.hist);
     e = hipMemsetAsync(s->meta, 0, sizeof(MergeMeta), s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(base, 0, sz.fat + sz.slim, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);

@@ -51,6 +51,7 @@ struct sf_pool {
     uint32_t* ent_cnt;
     MergeMeta* meta;
     uint32_t* hist;                // per-group bucket histograms of a merged sub-round
+    MergeChunk* chunks;            // key range of every merge chunk of a merged sub-round
     uint64_t hist_groups;          // partition groups (tiles) a merged sub-round may have
     uint32_t tile_j;
     bool merge;
@@ -105,7 +106,8 @@ PoolLayout pool_layout(const sf_config* c, uint64_t round_ops) {
     L.shared = round256(uint64_t(c->d) * L.round_ops * 4) + round256(uint64_t(c->d) * L.round_ops * 2) +
                round256(cells * c->z * 4) + round256(kRingTiles * sizeof(TileDesc)) +
                2 * round256(L.merge_round * L.mkey) + round256(L.merge_round * 4) + round256(sizeof(MergeMeta)) +
-               round256(part_groups_max(L.merge_round, kHistExtra) * 2 * kMaxBuckets * 4);
+               round256(part_groups_max(L.merge_round, kHistExtra) * 2 * kMaxBuckets * 4) +
+               round256(merge_chunks_max(L.merge_round) * sizeof(MergeChunk));
     return L;
 }
 
@@ -149,7 +151,8 @@ template <int KB>
 void launch_updates(sf_pool* p, const TileDesc* d_tiles, const std::vector<SubRound>& subs,
                     const std::vector<TileDesc>& host) {
     const MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(p->part), static_cast<MKey<KB, true>*>(p->ent_key),
-                                 p->ent_cnt, p->meta, p->hist, uint32_t(p->merge_round), p->bpre, p->asnap,
+                                 p->ent_cnt, p->meta, p->hist, p->chunks, uint32_t(p->merge_round), p->bpre,
+                                 p->asnap,
                                  uint32_t(p->round_ops)};
     const SketchTable table{p->d_desc};
     for (auto& sr : subs) {
@@ -249,6 +252,8 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
     q += round256(sizeof(MergeMeta));
     p->hist = reinterpret_cast<uint32_t*>(q);
     p->hist_groups = part_groups_max(L.merge_round, kHistExtra);
+    q += round256(p->hist_groups * 2 * kMaxBuckets * 4);
+    p->chunks = reinterpret_cast<MergeChunk*>(q);
     p->desc.resize(slots);
     const Geom geo = geom_of(cfg);
     for (uint64_t i = 0; i < slots; i++) {
