@@ -99,7 +99,8 @@ KIND_OF_KERNEL = {"k_snapshot": "snapshot", "k_raise": "raise", "k_clamp": "clam
                   "k_query": "query", "k_pack16": "export", "k_merge": "merge",
                   "k_entries_snapshot": "snapshot",
                   "k_entries_raise": "raise", "k_entries_clamp": "clamp",
-                  "k_part_count": "part_count", "k_part_start": "part_start",
+                  "k_part_count": "part_count", "k_part_colscan": "part_colscan", "k_part_start": "part_start",
+                  "k_unpack_fat": "fat_export",
                   "k_part_scatter": "part_scatter"}
 
 
@@ -221,7 +222,7 @@ def run_multi(args, torch, np, sf, sfgen):
     """1024 sketches in one group (graph-captured rounds) vs one sketch per launch."""
     t_gen = time.time()
     m = sfgen.config_multi(seed=0, length_scale=1.0 / args.scale,
-                           workers=min(16, os.cpu_count() or 1))
+                           workers=args.gen_workers or min(16, os.cpu_count() or 1))
     n_ops, n_q = int(m.keys.size), int(m.queries.size)
     log(f"[bench] workload {m.name}: {m.n} sketches, {n_ops} ops ({int(m.ops.sum())} deletes), "
         f"{n_q} queries, generated in {time.time() - t_gen:.1f}s")
@@ -352,15 +353,21 @@ SERVE_SHAPES = {
 }
 
 
-def run_serve(args, torch, np, sf, sfgen):
-    """4096 streams of insert/delete/query requests through the continuous-batching loop."""
-    from paper_1701_04148_amd.serve import Server
+def serve_workload(args, sfgen):
     t_gen = time.time()
     w = sfgen.serving(seed=0, n_streams=4096 // args.scale, per_stream=16)
-    total_keys = sum(r.n for r in w.requests)
     log(f"[bench] serving workload: {len(w.requests)} requests, {w.n_streams} streams, "
-        f"{total_keys} keys, generated in {time.time() - t_gen:.1f}s")
-    shape = SERVE_SHAPES[args.serve_shape]
+        f"{sum(r.n for r in w.requests)} keys, generated in {time.time() - t_gen:.1f}s")
+    return w
+
+
+def run_serve(args, torch, np, sf, sfgen, shape_name, w=None):
+    """4096 streams of insert/delete/query requests through the continuous-batching loop."""
+    from paper_1701_04148_amd.serve import Server
+    if w is None:
+        w = serve_workload(args, sfgen)
+    total_keys = sum(r.n for r in w.requests)
+    shape = SERVE_SHAPES[shape_name]
     cfg = sf.make_config(shape["d"], shape["w"], shape["z"], 4, 1, batch_for_width(shape["w"]))
     budget = 64 << 30
     pool = sf.SketchPool(cfg, hbm_budget_bytes=budget)
@@ -381,7 +388,7 @@ def run_serve(args, torch, np, sf, sfgen):
     pool.sync()
     sat = go(w.requests, False)
     pool.sync()
-    log(f"[bench] serving saturation: {sat.keys_per_s / 1e6:.1f} M keys/s, {sat.launches} launches, "
+    log(f"[bench] serving ({shape_name}) saturation: {sat.keys_per_s / 1e6:.1f} M keys/s, {sat.launches} launches, "
         f"{sat.mean_requests_per_launch:.1f} requests/launch, peak resident {sat.peak_resident}/{slots}")
     span = max(r.arrival for r in w.requests)
     offered = total_keys / span
@@ -392,7 +399,7 @@ def run_serve(args, torch, np, sf, sfgen):
         r.arrival *= f
     res = go(paced, True)
     pool.sync()
-    log(f"[bench] serving at {args.serve_load:.2f} x saturation: {res.keys_per_s / 1e6:.1f} M keys/s, "
+    log(f"[bench] serving ({shape_name}) at {args.serve_load:.2f} x saturation: {res.keys_per_s / 1e6:.1f} M keys/s, "
         f"latency {res.latency_ms}, queueing {res.queue_ms}")
     pool.close()
     return {"workload": f"{w.n_streams} streams x 16 requests (insert/delete/query 0.7/0.1/0.2, "
@@ -428,8 +435,12 @@ def main():
                          "--no-multi / --no-serve); multi: 1024 sketches in one group; serve: the "
                          "request loop alone")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="processes generating the 1024-sketch streams (0: up to 16; 1 under a profiler)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-shape", choices=tuple(SERVE_SHAPES), default="flows")
+    ap.add_argument("--serve-shape", choices=tuple(SERVE_SHAPES) + ("both",), default="both",
+                    help="per-stream sketch: flows (d=8, the flow configuration; admission binds), "
+                         "small (d=4, Fat 4 x 2^20; every stream fits) or both")
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / saturation")
     ap.add_argument("--serve-launch-keys", type=int, default=1 << 24)
     ap.add_argument("--stats-summary", metavar="STATS_CSV",
@@ -467,7 +478,9 @@ def main():
         print(json.dumps(run_multi(args, torch, np, sf, sfgen)), flush=True)
         return
     if args.workload == "serve":
-        print(json.dumps(run_serve(args, torch, np, sf, sfgen)), flush=True)
+        shapes = ("flows", "small") if args.serve_shape == "both" else (args.serve_shape,)
+        w = serve_workload(args, sfgen)
+        print(json.dumps({sh: run_serve(args, torch, np, sf, sfgen, sh, w) for sh in shapes}), flush=True)
         return
 
     t_gen = time.time()
@@ -625,7 +638,10 @@ def main():
             result["sketches_1024"]["cpu_baseline"] = multi["cpu_baseline"]
         torch.cuda.empty_cache()
     if not args.no_serve:
-        result["serving"] = run_serve(args, torch, np, sf, sfgen)
+        w = serve_workload(args, sfgen)
+        shapes = ("flows", "small") if args.serve_shape == "both" else (args.serve_shape,)
+        for sh in shapes:
+            result["serving" if sh == "flows" else f"serving_{sh}"] = run_serve(args, torch, np, sf, sfgen, sh, w)
     print(json.dumps(result), flush=True)
 
 

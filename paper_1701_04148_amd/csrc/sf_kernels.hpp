@@ -482,9 +482,9 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* _
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist_out[size_t(blockIdx.x) * nbt + b] = hist[b];
 }
 
-// Column scans of hist: 16 buckets per workgroup, the groups split into 16
+// Column scans of hist: 4 buckets per workgroup, the groups split into 64
 // segments.  hist[g][b] becomes the number of bucket-b keys of groups < g.
-constexpr uint32_t kScanBuckets = 16, kScanSegs = 16;
+constexpr uint32_t kScanBuckets = 4, kScanSegs = 64;
 template <typename T>
 __global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan(
     T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
