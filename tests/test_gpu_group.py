@@ -80,6 +80,44 @@ def test_group_merged_subrounds():
     G.close()
 
 
+def _many_small(n, seed, kb=4):
+    """n short mixed streams (120-400 ops over 60 keys each), every sketch one partial tile."""
+    rng = np.random.default_rng(seed)
+    parts, opss, qs, seg, qseg = [], [], [], [0], [0]
+    for i in range(n):
+        L = int(rng.integers(120, 400))
+        if kb == 4:
+            uni = rng.integers(0, 2**32, 60, dtype=np.uint64).astype(np.uint32)
+        else:
+            uni = rng.integers(0, 256, size=(60, 13), dtype=np.uint8)
+        k, o = sfgen.turnstile(uni[rng.zipf(1.2, L) % 60], rng, 0.1)
+        parts.append(k)
+        opss.append(o)
+        qs.append(uni)
+        seg.append(seg[-1] + L)
+        qseg.append(qseg[-1] + 60)
+    return sfgen.MultiWorkload(f"small{n}", 4, 4, rng.choice([64, 128, 256], n), np.concatenate(parts),
+                               np.concatenate(opss), np.array(seg, np.uint64), np.concatenate(qs),
+                               np.array(qseg, np.uint64))
+
+
+@pytest.mark.parametrize("kb", [4, 13])
+def test_group_more_sketches_than_a_subround_holds(kb):
+    """2500 sketches of a few hundred ops: each adds a partial partition tile, so a
+    merged sub-round closes on its tile budget (not on ops) and the round splits."""
+    import torch
+    m = _many_small(2500, seed=21, kb=kb)
+    cfgs = _cfgs(m.w, np.full(m.n, 4), np.full(m.n, 4096), kb=kb)
+    say(f"[case] group of {m.n} small sketches, {m.keys.shape[0]} ops, key_bytes={kb}")
+    G = sf.SketchGroup(cfgs)
+    G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
+    sub, tiles = G.rounds()
+    say(f"  sub-rounds {sub}, tiles {tiles}")
+    assert tiles == m.n and sub >= 2
+    _check_group(G, m, _oracle_parts(m, cfgs, kb=kb))
+    G.close()
+
+
 def test_group_replay_and_replan():
     """A repeated call replays the captured graph; new buffers rebuild the plan."""
     import torch

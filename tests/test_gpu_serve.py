@@ -116,6 +116,28 @@ def test_admission_by_budget():
     assert st.peak_resident <= 3 and st.requests == len(w.requests)
 
 
+def test_pool_launch_with_more_requests_than_a_subround_holds():
+    """1700 small insert requests in one launch: each adds a partial partition
+    tile, so the merged sub-round closes on its tile budget; every slot still
+    matches the oracle."""
+    import torch
+    cfg = sf.make_config(4, 64, 4, 4, 1, 1000)
+    pool = sf.SketchPool(cfg, max_slots=1700)
+    rng = np.random.default_rng(5)
+    slots = [pool.acquire() for _ in range(1700)]
+    keys = [rng.integers(0, 500, int(rng.integers(50, 300))).astype(np.uint32) for _ in slots]
+    dk = [torch.from_numpy(k.view(np.int32)).cuda() for k in keys]
+    say(f"[case] pool launch of {len(slots)} insert requests")
+    t = pool.launch([(sl, sf.SF_REQ_INSERT, k, None, None) for sl, k in zip(slots, dk)])
+    pool.wait(t)
+    for i in range(0, 1700, 37):
+        ref = oracle.Sketch(4, 64, 4)
+        assert ref.batch(keys[i], None, 1000, checked=True) == 0
+        assert_same(pool.export_fat(slots[i]), ref.fat(), f"fat of slot {i}")
+        assert_same(pool.export_slim(slots[i]), ref.slim(), f"slim of slot {i}")
+    pool.close()
+
+
 def test_pool_rejects_bad_requests():
     import torch
     pool = sf.SketchPool(sf.make_config(**CFG), max_slots=2)
