@@ -212,7 +212,7 @@ int sf_group_sync(sf_group *g);
 int sf_group_set_graph(sf_group *g, int enable);
 int sf_group_set_tile(sf_group *g, uint32_t tile_ops);
 /* As sf_set_merge, per group (default 1).  Batch-wide merging treats each
- * (key, sketch) pair as one key; merged sub-rounds hold at most 2^22 ops
+ * (key, sketch) pair as one key; merged sub-rounds hold at most 2^24 ops
  * (or the largest batch_ops), tiles of the per-tile path at most round_ops.
  * Waits for the stream; the next update call re-plans. */
 int sf_group_set_merge(sf_group *g, int batch_wide);
@@ -273,7 +273,7 @@ int sf_pool_export_fat(sf_pool *p, uint32_t slot, uint32_t *out, uint64_t out_el
 int sf_pool_sync(sf_pool *p);
 int sf_pool_set_tile(sf_pool *p, uint32_t tile_ops);
 /* As sf_set_merge for the pool's later launches (default 1); (key, slot)
- * pairs are merged across a sub-round of at most 2^22 ops (or batch_ops). */
+ * pairs are merged across a sub-round of at most 2^24 ops (or batch_ops). */
 int sf_pool_set_merge(sf_pool *p, int batch_wide);
 /* As sf_merge_stats, summed over all launches of the pool; waits for it. */
 int sf_pool_merge_stats(sf_pool *p, uint64_t *insert_entries, uint64_t *delete_entries);

@@ -14,7 +14,8 @@
 // partitioned into hash buckets of (key, sketch) pairs, merged in LDS into
 // one entry per distinct pair and chunk, and S1..S5 run once per entry.
 // Merged sub-rounds hold at most kMergeRound ops (or one sketch's batch, if
-// larger) so the buckets stay about two LDS chunks long.
+// larger): larger sub-rounds mean fewer launches, but past 2^24 ops the 512
+// buckets per op type span several LDS chunks each and fewer duplicates merge.
 //
 // Device memory (one allocation): every sketch's cell records (Fat bucket
 // and Slim working copy of a cell side by side), the sketch table, export
@@ -95,7 +96,7 @@ bool live(const sf_group* g) {
     return g && g_live.count(g);
 }
 
-constexpr uint64_t kMergeRound = 1ull << 22;
+constexpr uint64_t kMergeRound = 1ull << 24;
 constexpr uint64_t kHistExtra = 1024;  // partial tiles (one per sketch) a merged sub-round may add
 
 struct Layout {

@@ -13,7 +13,7 @@
 //
 // Update sub-rounds take the batch-merge path by default (duplicate (key,
 // slot) pairs merged across the sub-round, S1..S5 once per merged entry);
-// merged sub-rounds hold at most 2^22 ops, or one batch if larger.
+// merged sub-rounds hold at most 2^24 ops, or one batch if larger.
 //
 // Tile descriptors of in-flight launches live in a device ring; a region is
 // reused only after the launch that reads it has completed.
@@ -101,7 +101,7 @@ PoolLayout pool_layout(const sf_config* c, uint64_t round_ops) {
     L.slot_bytes = round256(cells * (c->z + 1) * 4);
     L.per_slot = L.slot_bytes + round256(sizeof(SketchDesc));
     L.round_ops = std::max<uint64_t>(round_ops ? round_ops : (1ull << 24), c->batch_ops);
-    L.merge_round = std::max<uint64_t>(std::min<uint64_t>(L.round_ops, 1ull << 22), c->batch_ops);
+    L.merge_round = std::max<uint64_t>(std::min<uint64_t>(L.round_ops, 1ull << 24), c->batch_ops);
     L.mkey = c->key_bytes == 4 ? sizeof(MKey<4, true>) : sizeof(MKey<13, true>);
     L.shared = round256(uint64_t(c->d) * L.round_ops * 4) + round256(uint64_t(c->d) * L.round_ops * 2) +
                round256(cells * c->z * 4) + round256(kRingTiles * sizeof(TileDesc)) +

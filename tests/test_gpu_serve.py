@@ -122,7 +122,7 @@ def test_pool_launch_with_more_requests_than_a_subround_holds():
     matches the oracle."""
     import torch
     cfg = sf.make_config(4, 64, 4, 4, 1, 1000)
-    pool = sf.SketchPool(cfg, max_slots=1700)
+    pool = sf.SketchPool(cfg, max_slots=1700, round_ops=1 << 20)   # sub-rounds of <= 1152 tiles
     rng = np.random.default_rng(5)
     slots = [pool.acquire() for _ in range(1700)]
     keys = [rng.integers(0, 500, int(rng.integers(50, 300))).astype(np.uint32) for _ in slots]
