@@ -606,6 +606,16 @@ def main():
         ceil = micro_ceilings(torch)
         result["random_access_ceilings_g_per_s"] = ceil
         log(f"[bench] ceilings {json.dumps(ceil)}")
+        # the dominant kernel against the measured rate of its own kind of access, at the
+        # footprint of the sketch's cell records (80 MiB: between the 64 and 256 MiB points)
+        probe = {"fat_add": ("atomic_add_u32", "u32 atomic adds"), "fat_sub": ("atomic_add_u32", "u32 atomic adds"),
+                 "snapshot": ("gather_u32", "random record reads"), "query": ("gather_u32", "random reads")}
+        if dom in probe and dk.get("g_accesses_s"):
+            key, what = probe[dom]
+            top = ceil["64MiB"][key]
+            result["roofline"]["random_access"] = {
+                "what": what, "achieved_g_per_s": dk["g_accesses_s"], "ceiling_g_per_s": top,
+                "frac": round(dk["g_accesses_s"] / top, 3), "ceiling": "measured by bench.py (libsf_micro), 64 MiB table"}
 
     if not args.no_cpu_baseline:
         import oracle
