@@ -231,7 +231,27 @@ def run_multi(args, torch, np, sf, sfgen):
     ops = torch.from_numpy(m.ops).to(dev)
     qk = torch.from_numpy(m.queries.view(np.int32)).to(dev)
     out = torch.empty(n_q, dtype=torch.int32, device=dev)
-    cfgs = [sf.make_config(m.d, int(m.w[i]), m.z, 4, 1, batch_for_width(int(m.w[i]))) for i in range(m.n)]
+    batch_of_w = {int(w): batch_for_width(int(w)) for w in np.unique(m.w)}
+    tuned = None
+    if not args.no_autotune:
+        # one tuning run per sketch width on that class's longest stream (at most 2M ops)
+        from paper_1701_04148_amd.tune import tune_batch
+        t_tune = time.time()
+        lens = np.diff(m.seg.astype(np.int64))
+        tuned = {}
+        for w in sorted(batch_of_w):
+            i = int(np.argmax(np.where(m.w == w, lens, -1)))
+            k_i, o_i, q_i = m.part(i)
+            n = min(k_i.shape[0], 1 << 21)
+            r = tune_batch(m.d, w, m.z, k_i[:n], o_i[:n], q_i)
+            batch_of_w[w] = r.b
+            tuned[str(w)] = {"b": r.b, "rule_b": batch_for_width(w), "ref_b": r.ref_b,
+                             "ref_are": round(r.ref_are, 5), "bound": round(r.bound, 5),
+                             "candidates": [[b, round(a, 5), round(ms, 2), ok] for b, a, ms, ok in r.table]}
+        log(f"[bench] autotuned batch per width in {time.time() - t_tune:.1f}s: "
+            f"{ {w: v['b'] for w, v in tuned.items()} } (rule min(16 w, 2^22): "
+            f"{ {w: v['rule_b'] for w, v in tuned.items()} })")
+    cfgs = [sf.make_config(m.d, int(m.w[i]), m.z, 4, 1, batch_of_w[int(m.w[i])]) for i in range(m.n)]
     G = sf.SketchGroup(cfgs)
     G.set_tile(args.tile)
     G.set_merge(args.merge == "batch")
@@ -315,9 +335,11 @@ def run_multi(args, torch, np, sf, sfgen):
         "config": {"workload": f"{m.n} SF-sketches, d=4, Fat 2^14..2^20 u32 log-uniform (z=4), "
                                "stream lengths lognormal median 200K in [10K, 4M], Zipf(1.1), 5% deletes; "
                                "one graph-captured group update, then query every stream's universe",
-                   "sketches": m.n, "ops": n_ops, "queries": n_q, "batch_ops": "min(16 w, 2^22) per sketch",
+                   "sketches": m.n, "ops": n_ops, "queries": n_q,
+                   "batch_ops": ("autotuned per width" if tuned else "min(16 w, 2^22) per sketch"),
                    "tile_ops": args.tile, "merge": args.merge, "launch_rounds": sub, "scale": args.scale},
         "merged_entries_per_step": {"insert": entries[0], "delete": entries[1]},
+        "autotune": tuned,
         "one_sketch_per_launch": {"value": round(lone_value, 2), "unit": "Mitems/s",
                                   "ms_per_step": round(el1 * 1e3, 3)},
         "group_vs_lone": round(value / lone_value, 2),
@@ -435,6 +457,8 @@ def main():
                          "--no-multi / --no-serve); multi: 1024 sketches in one group; serve: the "
                          "request loop alone")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="1024-sketch run: use the rule min(16 w, 2^22) instead of tuning b per width")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes generating the 1024-sketch streams (0: up to 16; 1 under a profiler)")
     ap.add_argument("--no-serve", action="store_true")
@@ -644,6 +668,8 @@ def main():
         multi = run_multi(args, torch, np, sf, sfgen)
         result["sketches_1024"] = {k: multi[k] for k in ("value", "unit", "ms_per_step", "config",
                                                          "one_sketch_per_launch", "group_vs_lone")}
+        if multi.get("autotune"):
+            result["sketches_1024"]["autotuned_b"] = {w: v["b"] for w, v in multi["autotune"].items()}
         if "cpu_baseline" in multi:
             result["sketches_1024"]["cpu_baseline"] = multi["cpu_baseline"]
         torch.cuda.empty_cache()

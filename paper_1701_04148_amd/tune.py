@@ -1,0 +1,131 @@
+"""Autotuner for the schedule batch size b of one sketch shape.
+
+The batch schedule trades accuracy for throughput: a larger b runs fewer,
+larger batches (fewer launches, more duplicate keys merged) but lets more
+inserts of a batch read the Slim state from before the batch.  For one
+sketch shape (d, w, z) and a sample stream, the tuner runs the GPU path at
+every candidate b, measures
+
+* the time of the update and the query of the sample (host clock around
+  the sketch's stream, synchronised), and
+* the ARE of the answers against the exact counts of the sample
+  (|q - f'| / f over queried keys with f > 0, f' = min(f, 65535)),
+
+takes the smallest candidate as the stand-in for sequential SF_F (b = 1 is
+far too slow to run), and picks the fastest b whose ARE stays within
+``rel * ARE_ref + abs_`` (default 1.10x + 1e-3).  Results are cached per
+shape and stream class.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Sketch
+
+SLIM_MAX = 65535
+
+
+def exact_counts(keys: np.ndarray, ops: np.ndarray | None, queries: np.ndarray) -> np.ndarray:
+    """Net count of every query key in the stream (inserts minus deletes), on the host.
+    keys / queries: uint32 [n] or uint8 [n, 13]."""
+    def as_rows(a):
+        return a if a.ndim == 1 else np.ascontiguousarray(a).view(np.dtype((np.void, a.shape[1]))).ravel()
+    k, q = as_rows(keys), as_rows(queries)
+    uniq, inv = np.unique(k, return_inverse=True)
+    sign = np.ones(k.shape[0], np.int64) if ops is None else np.where(ops == 1, -1, 1)
+    cnt = np.bincount(inv.ravel(), weights=sign, minlength=uniq.shape[0]).astype(np.int64)
+    pos = np.searchsorted(uniq, q)
+    pos[pos >= uniq.shape[0]] = 0
+    return np.where(uniq[pos] == q, cnt[pos], 0)
+
+
+def are(answers: np.ndarray, f: np.ndarray) -> float:
+    """Average relative error over keys with f > 0 (Slim saturation taken into account)."""
+    m = f > 0
+    if not m.any():
+        return 0.0
+    a = answers.astype(np.int64)[m]
+    fp = np.minimum(f[m], SLIM_MAX)
+    return float(np.mean(np.abs(a - fp) / f[m]))
+
+
+@dataclass
+class TuneResult:
+    b: int
+    ref_b: int
+    ref_are: float
+    bound: float
+    table: list = field(default_factory=list)   # (b, are, ms, feasible) per candidate
+
+
+def candidates_for(w: int, n_ops: int, cap: int = 1 << 22) -> list[int]:
+    """Every fourth power of two from w/16 up to min(64 w, cap), stopping at the
+    first one that holds the whole sample (larger ones behave the same on it)."""
+    lo = max(64, w // 16)
+    out, b = [], 1 << (lo - 1).bit_length()
+    while b <= min(64 * w, cap):
+        out.append(b)
+        if b >= n_ops:
+            break
+        b <<= 2
+    return out or [min(lo, cap)]
+
+
+def tune_batch(d: int, w: int, z: int, keys: np.ndarray, ops: np.ndarray | None, queries: np.ndarray,
+               key_bytes: int = 4, candidates=None, rel: float = 1.10, abs_: float = 1e-3,
+               reps: int = 2) -> TuneResult:
+    """Pick b for sketches of shape (d, w, z) fed streams like (keys, ops)."""
+    import torch
+    cands = sorted(candidates or candidates_for(w, keys.shape[0]))
+    f = exact_counts(keys, ops, queries)
+    dev = torch.device("cuda")
+    if key_bytes == 4:
+        dk = torch.from_numpy(np.ascontiguousarray(keys, np.uint32).view(np.int32)).to(dev)
+        dq = torch.from_numpy(np.ascontiguousarray(queries, np.uint32).view(np.int32)).to(dev)
+    else:
+        dk = torch.from_numpy(np.ascontiguousarray(keys).reshape(-1)).to(dev)
+        dq = torch.from_numpy(np.ascontiguousarray(queries).reshape(-1)).to(dev)
+    dops = None if ops is None else torch.from_numpy(np.ascontiguousarray(ops)).to(dev)
+    out = torch.empty(queries.shape[0], dtype=torch.int32, device=dev)
+    rows = []
+    for b in cands:
+        sk = Sketch(d, w, z, key_bytes=key_bytes, batch_ops=b)
+        best = float("inf")
+        for _ in range(reps):
+            sk.reset()
+            sk.sync()
+            t0 = time.perf_counter()
+            if dops is None:
+                sk.insert(dk)
+            else:
+                sk.update(dk, dops)
+            sk.query(dq, out)
+            sk.sync()
+            best = min(best, (time.perf_counter() - t0) * 1e3)
+        ans = out.cpu().numpy().view(np.uint32)
+        rows.append([b, are(ans, f), best])
+        sk.close()
+    ref_b, ref_are = rows[0][0], rows[0][1]
+    bound = rel * ref_are + abs_
+    for r in rows:
+        r.append(r[1] <= bound)
+    feasible = [r for r in rows if r[3]]
+    pick = min(feasible, key=lambda r: r[2])[0] if feasible else ref_b
+    return TuneResult(pick, ref_b, ref_are, bound, rows)
+
+
+class Autotuner:
+    """Per-shape cache of tune_batch results (key: d, w, z, key_bytes, stream class)."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+        self.cache: dict = {}
+
+    def batch_for(self, d, w, z, keys, ops, queries, key_bytes=4, stream_class="default") -> TuneResult:
+        k = (d, w, z, key_bytes, stream_class)
+        if k not in self.cache:
+            self.cache[k] = tune_batch(d, w, z, keys, ops, queries, key_bytes=key_bytes, **self.kw)
+        return self.cache[k]
