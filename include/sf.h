@@ -131,18 +131,18 @@ int sf_export_fat(sf_sketch *sk, uint32_t *out, uint64_t out_elems);
 /* Wait for all work enqueued on the sketch's stream. */
 int sf_sync(sf_sketch *sk);
 
-/* Launch shape of the duplicate-merging kernels: each workgroup groups the
- * keys of a tile of tile_ops consecutive ops (256, 1024 or 2048; default
- * 2048) and issues one atomic per distinct key.  Results do not depend on
- * it; throughput on skewed streams does. */
+/* Launch shape of the per-tile merging path (sf_set_merge(sk, 0)): each
+ * workgroup groups the keys of a tile of tile_ops consecutive ops (256, 1024
+ * or 2048; default 2048) and issues one atomic per distinct key.  Results do
+ * not depend on it; throughput on skewed streams does.  The batch-wide path
+ * ignores it. */
 int sf_set_tile(sf_sketch *sk, uint32_t tile_ops);
 
 /* Where duplicate keys are merged before they reach a counter: 1 = across
  * the whole batch (the default: keys are first partitioned into hash
- * buckets, then merged per bucket, and S1 is taken once per merged key),
- * 0 = per tile of consecutive ops.  Results are identical; the batch-wide
- * merge issues far fewer atomics and random reads (measured 1.5-1.7x faster
- * on Zipf 0.6 .. 1.4 streams). */
+ * buckets, then merged per bucket chunk, and S1..S5 run once per merged
+ * key), 0 = per tile of consecutive ops.  Results are identical; the
+ * batch-wide merge issues far fewer atomics and random reads. */
 int sf_set_merge(sf_sketch *sk, int batch_wide);
 
 /* Merged entries (distinct keys per bucket chunk) the batch-wide merge has
