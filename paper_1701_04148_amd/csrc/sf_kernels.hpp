@@ -339,14 +339,14 @@ template <int KB, bool G> __device__ __forceinline__ uint32_t mkey_hash(const MK
 }
 
 template <int KB, bool G> struct MergeShape {  // LDS table of the merging kernel
-    // Chunks of 8192 uint32 keys (16 waves) or 2048 13-byte keys (8 waves).
-    // A lone sketch's table has 12280 slots (load <= 2/3), so keys and slots
-    // take just under 80 KB and two groups share a CU; the others use 2x the
-    // chunk (pow2 slots: 128 KB with the sketch index, 57 KB for 13-byte keys).
+    // uint32 keys: chunks of 8192 keys and 12280 slots for a lone sketch,
+    // 6144 (key, sketch) pairs and 8190 slots in groups and pools -- either
+    // way keys and slots take just under 80 KB, so two groups of 16 waves
+    // share a CU.  13-byte keys: 2048 per chunk, 4096 slots (8 waves).
     static constexpr uint32_t kThreads = KB == 4 ? 1024 : 512;
-    static constexpr int J = KB == 4 ? 8 : 4;
+    static constexpr int J = KB == 4 ? (G ? 6 : 8) : 4;
     static constexpr uint32_t kChunk = kThreads * J;
-    static constexpr uint32_t kSlots = (KB == 4 && !G) ? 12280u : 2 * kChunk;
+    static constexpr uint32_t kSlots = KB == 4 ? (G ? 8190u : 12280u) : 2 * kChunk;
     static constexpr bool kPow2 = (kSlots & (kSlots - 1)) == 0;
 };
 constexpr uint32_t kMinChunk = 2048;  // smallest kChunk of any shape
