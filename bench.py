@@ -171,6 +171,31 @@ def summarize_stats(stats_csv: str) -> str:
     return "\n".join(lines)
 
 
+def summarize_trace(trace_csv: str) -> str:
+    """Per-kind kernel durations from a rocprofv3 kernel_trace.csv, with the Fat kernel's
+    insert (S2) and delete (S4) dispatches told apart by the kernel before them -- the
+    kinds and units bench.py's event timing reports."""
+    import csv
+    from collections import defaultdict
+    rows = []
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _kernel_base(r["Kernel_Name"])))
+    rows.sort()
+    dur, prev = defaultdict(list), None
+    for t0, t1, base in rows:
+        if base in ("k_fat_update", "k_entries_fat"):
+            kind = "fat_sub" if prev in ("k_raise", "k_entries_raise") else "fat_add"
+        else:
+            kind = KIND_OF_KERNEL.get(base, base)
+        dur[kind].append((t1 - t0) / 1e3)
+        prev = base
+    lines = [f"{'kind':16s} {'dispatches':>10s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s}"]
+    for kind, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{kind:16s} {len(v):10d} {sum(v) / len(v):8.1f} {min(v):8.1f} {max(v):8.1f}")
+    return "\n".join(lines)
+
+
 def workload_tag(args) -> str:
     """Name of the timed workload (sketch shape, stream, schedule, tile) for stored counters."""
     return (f"c2_d4_w{2**20 // args.scale}_z4_ops{32_000_000 // args.scale}_zipf{args.skew}_del10"
@@ -469,6 +494,8 @@ def main():
     ap.add_argument("--serve-launch-keys", type=int, default=1 << 24)
     ap.add_argument("--stats-summary", metavar="STATS_CSV",
                     help="print a rocprofv3 --stats kernel table and exit")
+    ap.add_argument("--trace-summary", metavar="TRACE_CSV",
+                    help="print per-kind durations from a rocprofv3 kernel trace and exit")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_traffic.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -477,6 +504,9 @@ def main():
 
     if args.stats_summary:
         print(summarize_stats(args.stats_summary))
+        return
+    if args.trace_summary:
+        print(summarize_trace(args.trace_summary))
         return
     if args.pmc_summary:
         rec = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], workload_tag(args),
@@ -622,6 +652,11 @@ def main():
                           "merged_entries_per_step": [units["ie"] // args.steps, units["de"] // args.steps]},
         "kernels": kernels,
         "kernels_note": "HIP-event durations from the same steps run once more with events on",
+        "phases_ms_per_step": {
+            "update": round(sum(v["ms_total"] for k, v in kernels.items() if k not in ("query", "export"))
+                            / args.steps, 3),
+            "export": round(kernels.get("export", {}).get("ms_total", 0.0) / args.steps, 3),
+            "query": round(kernels.get("query", {}).get("ms_total", 0.0) / args.steps, 3)},
         "profiled_ms_per_step": round(prof_ms_step, 3),
     }
 
