@@ -660,6 +660,17 @@ def main():
         "profiled_ms_per_step": round(prof_ms_step, 3),
     }
 
+    if not args.no_autotune:
+        # what the autotuner would pick for this workload (the run above uses the rule)
+        from paper_1701_04148_amd.tune import tune_batch
+        t_tune = time.time()
+        r = tune_batch(wl.d, wl.w, wl.z, wl.keys, wl.ops, wl.queries)
+        result["autotune_check"] = {"b": r.b, "rule_b": b, "ref_b": r.ref_b, "ref_are": round(r.ref_are, 5),
+                                    "bound": round(r.bound, 5),
+                                    "candidates": [[bb, round(a, 5), round(ms, 2), ok] for bb, a, ms, ok in r.table]}
+        log(f"[bench] autotuner on this workload ({time.time() - t_tune:.1f}s): b = {r.b} "
+            f"(rule {b}); table {result['autotune_check']['candidates']}")
+
     if not args.no_micro:
         log("[bench] random-access ceilings ...")
         ceil = micro_ceilings(torch)
