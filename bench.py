@@ -482,6 +482,7 @@ def main():
                          "--no-multi / --no-serve); multi: 1024 sketches in one group; serve: the "
                          "request loop alone")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-host-fed", action="store_true", help="skip the PCIe-inclusive host-fed steps")
     ap.add_argument("--no-autotune", action="store_true",
                     help="1024-sketch run: use the rule min(16 w, 2^22) instead of tuning b per width")
     ap.add_argument("--gen-workers", type=int, default=0,
@@ -600,6 +601,39 @@ def main():
     sk.profile(False)
     log(f"[bench] profiled steps: {prof_ms_step:.3f} ms/step")
 
+    # PCIe-inclusive variant (never `value`): keys and op codes from pinned host memory
+    # through sf_update_host (copies overlap the updates), query keys copied in and
+    # answers copied out every step
+    host_fed = None
+    if not args.no_host_fed:
+        hk = torch.from_numpy(wl.keys.view(np.int32)).pin_memory()
+        ho = torch.from_numpy(wl.ops).pin_memory()
+        hq = torch.from_numpy(wl.queries.view(np.int32)).pin_memory()
+        hout = torch.empty(wl.n_queries, dtype=torch.int32).pin_memory()
+
+        def host_step():
+            sk.reset()
+            sk.update_host(hk, ho, chunk_ops=b)
+            sf.sf_export_slim(sk._h, slim16)
+            qk.copy_(hq, non_blocking=True)
+            torch.cuda.current_stream().synchronize()
+            sk.query(qk, out)
+            sk.sync()
+            hout.copy_(out)
+
+        host_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            host_step()
+        torch.cuda.synchronize()
+        hel = time.perf_counter() - t0
+        host_fed = {"value": round(items / hel / 1e6, 2), "unit": "Mitems/s",
+                    "ms_per_step": round(hel * 1e3 / args.steps, 3),
+                    "note": "keys + op codes + query keys H2D from pinned memory and answers D2H "
+                            "each step (sf_update_host, copy chunks of b ops overlapping the updates)"}
+        log(f"[bench] host-fed (PCIe-inclusive): {host_fed['ms_per_step']} ms/step, {host_fed['value']} M items/s")
+
     # sanity on the device result: Fat row sums = net stream weight (Section 3.4 CM property)
     fat = sk.export_fat()
     rows = fat.reshape(wl.d, -1).astype(np.int64).sum(axis=1)
@@ -652,6 +686,7 @@ def main():
                           "merged_entries_per_step": [units["ie"] // args.steps, units["de"] // args.steps]},
         "kernels": kernels,
         "kernels_note": "HIP-event durations from the same steps run once more with events on",
+        "host_fed": host_fed,
         "phases_ms_per_step": {
             "update": round(sum(v["ms_total"] for k, v in kernels.items() if k not in ("query", "export"))
                             / args.steps, 3),

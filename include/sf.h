@@ -106,6 +106,18 @@ int sf_delete(sf_sketch *sk, const void *keys, uint64_t n);
 /* Mixed stream of n ops: ops[t] = 0 inserts keys[t], 1 deletes it (device). */
 int sf_update(sf_sketch *sk, const void *keys, const uint8_t *ops, uint64_t n);
 
+/* Host-fed updates: n ops whose keys (and op codes, or NULL for all
+ * inserts) are in PINNED host memory (hipHostMalloc).  They are copied in
+ * chunks of chunk_ops ops (a positive multiple of batch_ops, so the batches
+ * are exactly those of one sf_update call on device buffers) into two device
+ * buffers the sketch keeps, on a copy stream of its own: the copy of chunk
+ * c+1 overlaps the updates of chunk c.  Returns once every copy from the
+ * host buffers has completed (the caller may reuse them); the updates may
+ * still run on the sketch's stream.  SF_EINVAL for pageable host memory or a
+ * bad chunk size. */
+int sf_update_host(sf_sketch *sk, const void *host_keys, const uint8_t *host_ops, uint64_t n,
+                   uint64_t chunk_ops);
+
 /* Point query (Section 3.1 query rule, unchanged in SF_F): out[t] = the
  * smallest of the d Slim counters of keys[t], as uint32 (device pointer).
  * Between an sf_export_slim and the next update or reset, the query reads

@@ -63,6 +63,7 @@ SIGNATURES = {
     "sf_sync": (_I, [_P]),
     "sf_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_set_merge": (_I, [_P, _I]),
+    "sf_update_host": (_I, [_P, _P, _P, _U64, _U64]),
     "sf_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_profile": (_I, [_P, _I]),
     "sf_profile_read": (_I, [_P, ctypes.POINTER(sf_kernel_stats), _I]),
@@ -286,6 +287,22 @@ class Sketch:
 
     def update(self, keys, ops):
         sf_update(self._h, keys, ops, self.key_bytes)
+
+    def update_host(self, keys, ops=None, chunk_ops: int = 0):
+        """Updates from PINNED host tensors (torch ... pin_memory=True): keys (int32 / uint8
+        rows of 13 bytes), ops (uint8, None = all inserts).  chunk_ops: ops per copy chunk,
+        a multiple of batch_ops (0: 4 batches).  Returns once the host buffers are free."""
+        import torch
+        for t, what in ((keys, "keys"), (ops, "ops")):
+            if t is not None and (not isinstance(t, torch.Tensor) or t.is_cuda or not t.is_pinned()
+                                  or not t.is_contiguous()):
+                raise TypeError(f"{what} must be a contiguous pinned host tensor")
+        n = keys.numel() * keys.element_size() // self.key_bytes
+        if ops is not None and ops.numel() != n:
+            raise ValueError("ops must hold one code per key")
+        chunk = chunk_ops or 4 * self.cfg.batch_ops
+        _check(lib().sf_update_host(self._h, keys.data_ptr(), ops.data_ptr() if ops is not None else None,
+                                    n, chunk), "sf_update_host")
 
     def query(self, keys, out=None):
         import torch

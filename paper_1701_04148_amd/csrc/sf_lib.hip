@@ -18,6 +18,7 @@
 // stream, over tiles of 256 * tile_j consecutive ops (UniformPlan).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <unordered_set>
@@ -57,6 +58,14 @@ struct sf_sketch {
     MergeChunk* chunks;//             key range of every merge chunk
     MergeMeta* meta;
     Profiler prof;
+    // host-fed updates (sf_update_host): two device chunk buffers (keys, then
+    // op codes), their events and a copy stream, made on first use
+    hipStream_t copy_stream = nullptr;
+    uint8_t* feed[2] = {nullptr, nullptr};
+    uint64_t feed_ops = 0;
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    hipEvent_t consumed[2] = {nullptr, nullptr};
+    bool feed_busy[2] = {false, false};
 };
 
 namespace {
@@ -249,6 +258,13 @@ int sf_destroy(sf_sketch* s) {
         if (!s || !g_live.erase(s)) return fail(SF_ESTATE, "sketch handle is not live");
     }
     hipError_t e = hipStreamSynchronize(s->stream);
+    if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
+    for (int i = 0; i < 2; i++) {
+        if (s->feed[i]) (void)hipFree(s->feed[i]);
+        if (s->copied[i]) (void)hipEventDestroy(s->copied[i]);
+        if (s->consumed[i]) (void)hipEventDestroy(s->consumed[i]);
+    }
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
     hipError_t e2 = hipFree(s->fat);
     delete s;
     if (e != hipSuccess) return device_fail(e, "sf_destroy sync");
@@ -278,6 +294,78 @@ int sf_delete(sf_sketch* s, const void* keys, uint64_t n) { return run_updates(s
 
 int sf_update(sf_sketch* s, const void* keys, const uint8_t* ops, uint64_t n) {
     return run_updates(s, keys, ops, n, kMixed);
+}
+
+int sf_update_host(sf_sketch* s, const void* host_keys, const uint8_t* host_ops, uint64_t n, uint64_t chunk_ops) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    if (n == 0) return SF_OK;
+    const uint64_t b = s->cfg.batch_ops;
+    if (chunk_ops == 0 || chunk_ops % b) return fail(SF_EINVAL, "chunk_ops must be a positive multiple of batch_ops");
+    auto pinned = [](const void* p) {
+        hipPointerAttribute_t at{};
+        if (!p || hipPointerGetAttributes(&at, p) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return at.type == hipMemoryTypeHost;
+    };
+    if (!pinned(host_keys)) return fail(SF_EINVAL, "host_keys must be pinned host memory (hipHostMalloc)");
+    if (host_ops && !pinned(host_ops)) return fail(SF_EINVAL, "host_ops must be pinned host memory (hipHostMalloc)");
+    const uint32_t kb = s->cfg.key_bytes;
+    const uint64_t chunk = std::min<uint64_t>(chunk_ops, n);
+    hipError_t e = hipSuccess;
+    if (!s->copy_stream) {
+        e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);  // default priority
+        for (int i = 0; i < 2 && e == hipSuccess; i++) {
+            e = hipEventCreateWithFlags(&s->copied[i], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->consumed[i], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) return device_fail(e, "sf_update_host setup");
+    }
+    if (s->feed_ops < chunk) {  // (re)allocate the chunk buffers once no launch reads them
+        if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return device_fail(e, "sf_update_host sync");
+        for (int i = 0; i < 2; i++) {
+            if (s->feed[i]) (void)hipFree(s->feed[i]);
+            s->feed[i] = nullptr;
+            s->feed_busy[i] = false;
+        }
+        s->feed_ops = 0;
+        for (int i = 0; i < 2; i++) {
+            e = hipMalloc(reinterpret_cast<void**>(&s->feed[i]), chunk * (kb + 1));
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return e == hipErrorOutOfMemory ? fail(SF_ENOMEM, "sf_update_host chunk buffers")
+                                                : device_fail(e, "sf_update_host chunk buffers");
+            }
+        }
+        s->feed_ops = chunk;
+    }
+    const uint8_t* hk = static_cast<const uint8_t*>(host_keys);
+    int last = 0;
+    for (uint64_t lo = 0, c = 0; lo < n; lo += chunk, c++) {
+        const int slot = int(c & 1);
+        const uint64_t cnt = std::min(chunk, n - lo);
+        uint8_t* dk = s->feed[slot];
+        uint8_t* dop = s->feed[slot] + s->feed_ops * kb;
+        // the copy into a buffer waits for the updates that read it before
+        if (s->feed_busy[slot] && (e = hipStreamWaitEvent(s->copy_stream, s->consumed[slot], 0)) != hipSuccess)
+            return device_fail(e, "sf_update_host wait");
+        e = hipMemcpyAsync(dk, hk + lo * kb, cnt * kb, hipMemcpyHostToDevice, s->copy_stream);
+        if (e == hipSuccess && host_ops)
+            e = hipMemcpyAsync(dop, host_ops + lo, cnt, hipMemcpyHostToDevice, s->copy_stream);
+        if (e == hipSuccess) e = hipEventRecord(s->copied[slot], s->copy_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->copied[slot], 0);
+        if (e != hipSuccess) return device_fail(e, "sf_update_host copy");
+        const int rc = run_updates(s, dk, host_ops ? dop : nullptr, cnt, host_ops ? kMixed : kInsert);
+        if (rc) return rc;
+        if ((e = hipEventRecord(s->consumed[slot], s->stream)) != hipSuccess)
+            return device_fail(e, "sf_update_host record");
+        s->feed_busy[slot] = true;
+        last = slot;
+    }
+    // every byte has left the host buffers once the last copy is done
+    e = hipEventSynchronize(s->copied[last]);
+    return e == hipSuccess ? SF_OK : device_fail(e, "sf_update_host copies");
 }
 
 int sf_query(sf_sketch* s, const void* keys, uint64_t n, uint32_t* out) {

@@ -269,3 +269,41 @@ def test_flow_config_full_size_properties():
     assert (ans.astype(np.int64) <= np.minimum(U, 65535)).all()
     q_or = oracle.query_slim(slim, wl.d, wl.w, wl.z, wl.queries[:200_000], key_bytes=13)
     assert_same(ans[:200_000], q_or, "answers vs oracle query on the exported Slim")
+
+
+def test_host_fed_updates_equal_device_updates():
+    """sf_update_host (pinned host keys, chunked copies overlapping the updates)
+    reaches exactly the state of sf_update on device buffers; two calls in a row
+    reuse the chunk buffers; pageable memory and bad chunk sizes are refused."""
+    import torch
+    wl = sfgen.config_main(1.0, scale=64)                     # 500K ops, w = 2^14
+    b = 1 << 14
+    n = wl.keys.shape[0]
+    ref = sf.Sketch(wl.d, wl.w, wl.z, batch_ops=b)
+    ref.update(dev_keys(wl.keys), torch.from_numpy(wl.ops).cuda())
+    ref.sync()
+    say(f"[case] host-fed updates n={n} b={b}")
+    hk = torch.from_numpy(wl.keys.view(np.int32)).pin_memory()
+    ho = torch.from_numpy(wl.ops).pin_memory()
+    sk = sf.Sketch(wl.d, wl.w, wl.z, batch_ops=b)
+    half = (n // 2) // b * b                                  # split at a batch boundary
+    sk.update_host(hk[:half], ho[:half], chunk_ops=3 * b)
+    sk.update_host(hk[half:], ho[half:], chunk_ops=3 * b)
+    sk.sync()
+    assert_same(sk.export_fat(), ref.export_fat(), "fat")
+    assert_same(sk.export_slim(), ref.export_slim(), "slim")
+    q = dev_keys(wl.queries)
+    assert_same(sk.query(q).cpu().numpy(), ref.query(q).cpu().numpy(), "queries")
+    ins = sf.Sketch(wl.d, wl.w, wl.z, batch_ops=b)             # insert-only form (ops = None)
+    ins.update_host(hk[:half], None, chunk_ops=b)
+    ref2 = sf.Sketch(wl.d, wl.w, wl.z, batch_ops=b)
+    ref2.insert(dev_keys(wl.keys[:half]))
+    ins.sync()
+    ref2.sync()
+    assert_same(ins.export_fat(), ref2.export_fat(), "fat, inserts")
+    rc = sf.lib().sf_update_host(sk._h, wl.keys.ctypes.data, None, 1000, b)   # pageable numpy memory
+    assert rc == sf.SF_EINVAL
+    rc = sf.lib().sf_update_host(sk._h, hk.data_ptr(), None, 1000, b + 1)     # not a multiple of b
+    assert rc == sf.SF_EINVAL
+    for s_ in (sk, ref, ins, ref2):
+        s_.close()
