@@ -488,23 +488,48 @@ constexpr uint32_t kScanBuckets = 4, kScanSegs = 64;
 template <typename T>
 __global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan(
     T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
+    constexpr uint32_t kRowsReg = 16;             // a segment's rows kept in registers when it has few
     __shared__ T seg_sum[kScanSegs][kScanBuckets];
     const uint32_t lb = threadIdx.x % kScanBuckets, sg = threadIdx.x / kScanBuckets;
     const uint32_t b = blockIdx.x * kScanBuckets + lb;
     const uint32_t rows = (groups + kScanSegs - 1) / kScanSegs;
     const uint32_t g0 = sg * rows, g1 = min(groups, g0 + rows);
+    const bool in_reg = rows <= kRowsReg;
+    T v[kRowsReg];
     T sum = 0;
-    if (b < nbt)
-        for (uint32_t g = g0; g < g1; g++) sum += hist[size_t(g) * nbt + b];
+    if (b < nbt) {
+        if (in_reg) {
+#pragma unroll
+            for (uint32_t r = 0; r < kRowsReg; r++) {
+                v[r] = g0 + r < g1 ? hist[size_t(g0 + r) * nbt + b] : T(0);
+                sum += v[r];
+            }
+        } else {
+            for (uint32_t g = g0; g < g1; g++) sum += hist[size_t(g) * nbt + b];
+        }
+    }
     seg_sum[sg][lb] = sum;
     __syncthreads();
-    T run = 0;                                    // keys of this bucket in earlier segments
-    for (uint32_t s2 = 0; s2 < sg; s2++) run += seg_sum[s2][lb];
+    for (uint32_t off = 1; off < kScanSegs; off <<= 1) {  // inclusive scan over the segments
+        const T x = sg >= off ? seg_sum[sg - off][lb] : T(0);
+        __syncthreads();
+        seg_sum[sg][lb] += x;
+        __syncthreads();
+    }
+    T run = seg_sum[sg][lb] - sum;                // keys of this bucket in earlier segments
     if (b < nbt) {
-        for (uint32_t g = g0; g < g1; g++) {
-            const T v = hist[size_t(g) * nbt + b];
-            hist[size_t(g) * nbt + b] = run;
-            run += v;
+        if (in_reg) {
+#pragma unroll
+            for (uint32_t r = 0; r < kRowsReg; r++) {
+                if (g0 + r < g1) hist[size_t(g0 + r) * nbt + b] = run;
+                run += v[r];
+            }
+        } else {
+            for (uint32_t g = g0; g < g1; g++) {
+                const T x = hist[size_t(g) * nbt + b];
+                hist[size_t(g) * nbt + b] = run;
+                run += x;
+            }
         }
         if (sg == kScanSegs - 1) meta->total[b] = run;
     }
