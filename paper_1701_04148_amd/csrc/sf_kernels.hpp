@@ -459,10 +459,22 @@ struct MergeMeta {                    // device-side bookkeeping of one batch
 // column into the groups' offsets inside the bucket (and the bucket total);
 // k_part_start lays the buckets out; k_part_scatter adds the two.
 
-// Bucket of a key: top log2(nb) bits of its hash (the LDS table uses low bits).
+// Bucket of a key.  A lone sketch buckets by the key's row-0 cell (nb equal
+// cell ranges), so the entries one merge chunk emits -- processed side by
+// side by the entry kernels -- share a narrow range of row-0 cell records
+// that stays in cache.  With a sketch table it is the top log2(nb) bits of
+// the key's hash.  (The merge table's slot comes from a different hash.)
 template <int KB, bool G>
-__device__ __forceinline__ uint32_t bucket_of(const MKey<KB, G>& k, bool del, uint32_t nb_log2) {
-    return (mkey_hash<KB, G>(k) >> (32u - nb_log2)) + (del ? (1u << nb_log2) : 0u);
+__device__ __forceinline__ uint32_t bucket_of(const MKey<KB, G>& k, bool del, uint32_t nb_log2, const Geom& g) {
+    uint32_t b;
+    if constexpr (G) {
+        b = mkey_hash<KB, G>(k) >> (32u - nb_log2);
+    } else {
+        uint32_t h, f;
+        split(g, Mixed<KB>(k.k).row(g.seed_base), h, f);
+        b = uint32_t((uint64_t(h) << nb_log2) / g.w);
+    }
+    return b + (del ? (1u << nb_log2) : 0u);
 }
 
 // Counts the ops of every bucket in each group's tile.
@@ -476,7 +488,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* _
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < w.count; t += kPartThreads) {
         const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
-        atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2)], 1u);
+        atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2, w.g)], 1u);
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist_out[size_t(blockIdx.x) * nbt + b] = hist[b];
@@ -594,7 +606,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
         rank[r] = 0;
         if (t < w.count) {
             k[r] = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
-            bk[r] = bucket_of<KB, G>(k[r], is_delete(w.ops, t, w.mode), nb_log2);
+            bk[r] = bucket_of<KB, G>(k[r], is_delete(w.ops, t, w.mode), nb_log2, w.g);
             rank[r] = atomicAdd(&hist[bk[r]], 1u);   // place among the group's keys of the bucket
         }
     }
