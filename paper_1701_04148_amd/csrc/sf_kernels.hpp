@@ -4,14 +4,24 @@
 //   ListPlan     a device table of tiles over many sketches (sketch groups)
 // The step each kernel implements is the same in both cases.
 //
-// One schedule batch (the sf.h update schedule):
-//   k_snapshot   S1  insert ops: Slim and Fat counters before the batch
-//   k_fat_update S2  insert ops: Fat += count, one atomic per distinct key of the tile
-//   k_raise      S3  insert ops: T = min(m0 + delta, max(m0, Bmin), 65535),
-//                    atomic max into the Slim where T exceeds the snapshot
-//   k_fat_update S4  delete ops: Fat -= count
-//   k_clamp      S5  delete ops: atomic min of the Slim with the bucket max
-// Kernel boundaries are the schedule's grid-wide barriers.
+// One schedule batch (the sf.h update schedule), S1..S5:
+//   S1  insert keys: Slim and Fat counters before the batch
+//   S2  insert keys: Fat += count
+//   S3  insert keys: T = min(m0 + delta, max(m0, Bmin), 65535), atomic max
+//       into the Slim where T exceeds it
+//   S4  delete keys: Fat -= count
+//   S5  delete keys: atomic min of the Slim with the bucket max
+// Two ways to get there, with identical results:
+//   batch-wide merging (default): k_part_count / k_part_colscan /
+//     k_part_start / k_part_scatter partition the batch's keys into hash
+//     buckets, k_merge turns each bucket chunk into entries (key, count), and
+//     k_entries_snapshot / _fat / _raise / _fat / _clamp run S1..S5 once per
+//     entry;
+//   per-tile merging: k_snapshot, k_fat_update, k_raise, k_fat_update,
+//     k_clamp each group the duplicate keys of their tile in LDS first.
+// Kernel boundaries are the schedule's grid-wide barriers.  A cell of the
+// sketch is one record of z+1 uint32 words: its Fat bucket, then its Slim
+// working copy (Geom::rs words apart from the next cell's).
 #pragma once
 
 #include "sf_device.hpp"
@@ -406,21 +416,17 @@ template <class T> __device__ __forceinline__ T read_lane(const T& x, int lane) 
     return r;
 }
 
-// Skewed streams put many copies of one key (or bucket) in one wavefront, and
-// LDS atomics on one address serialise.  K rounds of "peeling": the first
+// Skewed streams put many copies of one key in one wavefront, and LDS
+// atomics on one address serialise.  K rounds of "peeling": the first
 // unclaimed lane leads, every lane holding the leader's value joins it, and
 // the leader alone carries the group.  Returns this lane's weight: the group
-// size for a leader, 0 for a follower (or an invalid lane), 1 for a lane
-// left unclaimed.  *leader_of / *rank (optional) say which lane leads this
-// lane's group and this lane's place in it.  Call with the whole wavefront.
+// size for a leader, 0 for a follower (or an invalid lane), 1 for a lane left
+// unclaimed.  Call with the whole wavefront.
 template <int K, class T, class Eq>
-__device__ __forceinline__ uint32_t wave_peel(const T& v, bool valid, Eq eq, int* leader_of = nullptr,
-                                              uint32_t* rank = nullptr) {
+__device__ __forceinline__ uint32_t wave_peel(const T& v, bool valid, Eq eq) {
     bool claimed = !valid;
     uint32_t w = valid ? 1u : 0u;
     const int lane = int(lane_id());
-    if (leader_of) *leader_of = lane;
-    if (rank) *rank = 0;
 #pragma unroll
     for (int r = 0; r < K; r++) {
         const unsigned long long act = __ballot(!claimed);
@@ -432,8 +438,6 @@ __device__ __forceinline__ uint32_t wave_peel(const T& v, bool valid, Eq eq, int
         if (same) {
             claimed = true;
             w = lane == leader ? uint32_t(__popcll(m)) : 0u;
-            if (leader_of) *leader_of = leader;
-            if (rank) *rank = uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
         }
     }
     return w;
