@@ -461,6 +461,47 @@ def run_serve(args, torch, np, sf, sfgen, shape_name, w=None):
             "peak_resident_sketches": res.peak_resident, "slots": slots}
 
 
+def run_collector(np, sk, step, queries, answers, snapshots=20):
+    """The Slim hand-off to a collector process (paper Sections 1 and 3): one
+    snapshot after every update step (a reporting interval of one step), then
+    back-to-back snapshots for the streaming rate, then the step's queries
+    answered by the collector, which must equal the sketch's own answers."""
+    from paper_1701_04148_amd.collector import Collector
+    t_start = time.perf_counter()
+    with Collector(max_cells=sk.d * sk.w, frames=4) as col:
+        t_ready = time.perf_counter() - t_start
+        col.publish(0, sk)                      # warm-up: the collector's first device copy
+        col.drain()
+        col.clear_latencies()
+        for _ in range(snapshots):
+            step()
+            col.publish(0, sk)
+        col.drain()
+        lat = col.latencies()
+        t0 = time.perf_counter()
+        for _ in range(snapshots):
+            col.publish(0, sk)
+        col.drain()
+        el = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        got, seq = col.query(0, queries)
+        q_el = time.perf_counter() - t1
+    if not np.array_equal(got, answers):
+        raise SystemExit("collector answers differ from the sketch's own")
+    slim_bytes = 2 * sk.d * sk.w
+    e2e, exp = lat["end_to_end_ms"], lat["export_ms"]
+    return {"slim_bytes": slim_bytes, "frames": 4, "snapshots": int(lat["snapshots"]),
+            "export_ms_p50": round(float(np.percentile(exp, 50)), 3),
+            "to_collector_gpu_ms_p50": round(float(np.percentile(e2e, 50)), 3),
+            "to_collector_gpu_ms_p99": round(float(np.percentile(e2e, 99)), 3),
+            "stream_snapshots_per_s": round(snapshots / el, 1),
+            "stream_gb_s": round(snapshots * slim_bytes / el / 1e9, 2),
+            "query_keys": int(queries.shape[0]), "query_round_trip_ms": round(q_el * 1e3, 2),
+            "answers_equal_sketch": True, "collector_start_s": round(t_ready, 1),
+            "note": "sf_export_slim into a shared-memory frame (D2H), message over a pipe, the "
+                    "collector process copies it to its GPU; query keys and answers travel over the pipe"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -483,6 +524,8 @@ def main():
                          "request loop alone")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-host-fed", action="store_true", help="skip the PCIe-inclusive host-fed steps")
+    ap.add_argument("--no-collector", action="store_true",
+                    help="skip streaming the Slim to a collector process")
     ap.add_argument("--no-autotune", action="store_true",
                     help="1024-sketch run: use the rule min(16 w, 2^22) instead of tuning b per width")
     ap.add_argument("--gen-workers", type=int, default=0,
@@ -641,6 +684,11 @@ def main():
         raise SystemExit(f"Fat row sums {rows} != net weight {n_ins - n_del}")
     gpu_answers = out.cpu().numpy().view(np.uint32).copy()
 
+    collector = None
+    if not args.no_collector:
+        collector = run_collector(np, sk, step, wl.queries, gpu_answers)
+        log(f"[bench] collector: {json.dumps(collector)}")
+
     # per-kernel accounting from the events on the sketch's stream
     kernels = {}
     units = dict(ins=n_ins * args.steps, dels=n_del * args.steps, ops=wl.n_ops * args.steps,
@@ -687,6 +735,7 @@ def main():
         "kernels": kernels,
         "kernels_note": "HIP-event durations from the same steps run once more with events on",
         "host_fed": host_fed,
+        "collector": collector,
         "phases_ms_per_step": {
             "update": round(sum(v["ms_total"] for k, v in kernels.items() if k not in ("query", "export"))
                             / args.steps, 3),
