@@ -150,7 +150,10 @@ def collector_main(conn, shm_name: str, frames: int, fbytes: int, device: int) -
 
 class Collector:
     """Producer-side handle of a collector process for Slims of at most
-    max_cells = d*w counters, with `frames` shared-memory frames in flight."""
+    max_cells = d*w counters, with `frames` shared-memory frames in flight.
+    publish() takes a Sketch (anything with d, w, cfg and export_slim(out))."""
+
+    KEEP_TIMES = 1 << 16                          # snapshots whose times latencies() reports, at most
 
     def __init__(self, max_cells: int, frames: int = 4, device: int = 0, timeout: float = 300.0):
         import multiprocessing as mp
@@ -223,6 +226,8 @@ class Collector:
         c = sk.cfg
         write_header(self.shm.buf, off, sketch_id, seq, (c.d, c.w, c.z, c.key_bytes, c.seed_base))
         self.times[seq] = [t0, t1, None]
+        if len(self.times) > self.KEEP_TIMES:
+            self.clear_latencies()
         self.conn.send(("slim", frame, seq, sketch_id))
         return seq
 
@@ -252,20 +257,32 @@ class Collector:
         return {"snapshots": len(done), "export_ms": exp, "end_to_end_ms": e2e}
 
     def close(self) -> None:
-        if getattr(self, "proc", None) is None:
-            return
+        """Stop the collector process and remove the shared memory (idempotent)."""
+        proc, self.proc = getattr(self, "proc", None), None
+        conn, self.conn = getattr(self, "conn", None), None
+        shm, self.shm = getattr(self, "shm", None), None
         try:
-            if self.proc.is_alive():
-                self.conn.send(("stop",))
-                self.proc.join(60)
+            if proc is not None and proc.is_alive():
+                try:
+                    conn.send(("stop",))
+                except OSError:
+                    pass
+                proc.join(60)
         finally:
-            if self.proc.is_alive():
-                self.proc.terminate()
-                self.proc.join(10)
-            self.proc = None
-            self.conn.close()
-            self.shm.close()
-            self.shm.unlink()
+            if proc is not None and proc.is_alive():
+                proc.terminate()
+                proc.join(10)
+            if conn is not None:
+                conn.close()
+            if shm is not None:
+                shm.close()
+                shm.unlink()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 -- interpreter shutdown
+            pass
 
     def __enter__(self):
         return self

@@ -11,8 +11,8 @@ every candidate b, measures
 * the ARE of the answers against the exact counts of the sample
   (|q - f'| / f over queried keys with f > 0, f' = min(f, 65535)),
 
-takes the smallest candidate as the stand-in for sequential SF_F (b = 1 is
-far too slow to run), and picks the fastest b whose ARE stays within
+takes the smallest candidate (w/16) as the stand-in for sequential SF_F
+(b = 1 is far too slow to run), and picks the fastest b whose ARE stays within
 ``rel * ARE_ref + abs_`` (default 1.10x + 1e-3).  Results are cached per
 shape and stream class.
 """
@@ -61,16 +61,16 @@ class TuneResult:
     table: list = field(default_factory=list)   # (b, are, ms, feasible) per candidate
 
 
-def candidates_for(w: int, n_ops: int, cap: int = 1 << 22) -> list[int]:
-    """Every fourth power of two from w/16 up to min(64 w, cap), stopping at the
-    first one that holds the whole sample (larger ones behave the same on it)."""
+def candidates_for(w: int, n_ops: int, cap: int = 1 << 23) -> list[int]:
+    """Every power of two from w/16 up to min(64 w, cap), stopping at the first
+    one that holds the whole sample (larger ones behave the same on it)."""
     lo = max(64, w // 16)
     out, b = [], 1 << (lo - 1).bit_length()
     while b <= min(64 * w, cap):
         out.append(b)
         if b >= n_ops:
             break
-        b <<= 2
+        b <<= 1
     return out or [min(lo, cap)]
 
 

@@ -118,10 +118,10 @@ def test_main_config_scaled(skew, merge):
 
 def test_main_config_full_size_as_benchmarked():
     """The 32M-op configuration at full size (w=2^20, Zipf 1.0, 10% deletes) with
-    the benchmark's schedule batch 2^22 and launch settings: Fat, Slim and all
+    the benchmark's schedule batch 2^23 and launch settings: Fat, Slim and all
     2M answers bit-exact against the oracle."""
     wl = sfgen.config_main(1.0)
-    check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, 1 << 22, tag="c2 full", merge=True)
+    check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, 1 << 23, tag="c2 full", merge=True)
 
 
 @pytest.mark.parametrize("merge", [False, True])

@@ -30,9 +30,10 @@ def test_are_and_saturation():
 
 
 def test_candidates():
-    assert candidates_for(4096, 10**6) == [256, 1024, 4096, 16384, 65536, 262144]
-    assert candidates_for(1 << 20, 1 << 20) == [65536, 262144, 1048576]
-    assert candidates_for(1 << 17, 700_000) == [8192, 32768, 131072, 524288, 2097152]
+    assert candidates_for(4096, 10**6) == [256 << i for i in range(11)]          # up to 64 w
+    assert candidates_for(1 << 20, 1 << 20) == [65536, 131072, 262144, 524288, 1048576]
+    assert candidates_for(1 << 20, 10**9) == [65536 << i for i in range(8)]      # up to the cap 2^23
+    assert candidates_for(1 << 17, 700_000) == [8192, 16384, 32768, 65536, 131072, 262144, 524288, 1048576]
     assert candidates_for(1 << 12, 100) == [256]
 
 
