@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_pack16(const T* __restrict__ in, uin
 // =====================================================================
 namespace sfk {
 
-constexpr uint32_t kMaxBuckets = 512;          // per op type; the runtime nb is a power of two <= this
+constexpr uint32_t kMaxBuckets = 1024;         // per op type; the runtime nb is a power of two <= this
 constexpr uint32_t kPartOps = 8192;            // ops per partitioning workgroup
 constexpr uint32_t kPartThreads = 1024;        // its threads (16 waves)
 // Partitioning groups one batch (or merged sub-round) of cap ops may use:
@@ -357,7 +357,7 @@ template <int KB, bool G> struct MergeShape {  // LDS table of the merging kerne
     static constexpr int J = KB == 4 ? (G ? 6 : 8) : 4;
     static constexpr uint32_t kChunk = kThreads * J;
     static constexpr uint32_t kSlots = KB == 4 ? (G ? 8190u : 12280u) : 2 * kChunk;
-    static constexpr bool kPow2 = (kSlots & (kSlots - 1)) == 0;
+    static_assert(kSlots > kChunk, "a chunk's keys always fit the table");
 };
 constexpr uint32_t kMinChunk = 2048;  // smallest kChunk of any shape
 
@@ -367,13 +367,18 @@ struct MergeChunk {
 };
 // Chunks one batch (or merged sub-round) of cap ops can have: full chunks
 // plus one partial chunk per bucket.
-__host__ __device__ constexpr uint64_t merge_chunks_max(uint64_t cap) { return cap / kMinChunk + 2 * 1024 + 1; }
+__host__ __device__ constexpr uint64_t merge_chunks_max(uint64_t cap) { return cap / kMinChunk + 2 * kMaxBuckets + 1; }
 
 // Bucket count for a batch of cnt ops: about one chunk of ops per bucket, so
-// that few keys are split between two chunks (each part becomes an entry).
+// that few keys are split between two chunks (each part becomes an entry).  A
+// sketch table stops at half the limit: there a batch holds many sketches'
+// short per-sketch batches, whose duplicates already meet in a bucket of two
+// or three chunks, and the wider histogram matrix would cost more than it
+// saves.
 template <int KB, bool G> __host__ __device__ inline uint32_t buckets_for(uint64_t cnt) {
+    constexpr uint32_t kLimit = G ? kMaxBuckets / 2 : kMaxBuckets;
     uint32_t nb = 16;
-    while (nb < kMaxBuckets && uint64_t(nb) * MergeShape<KB, G>::kChunk < cnt) nb <<= 1;
+    while (nb < kLimit && uint64_t(nb) * MergeShape<KB, G>::kChunk < cnt) nb <<= 1;
     return nb;
 }
 
@@ -384,23 +389,24 @@ template <int KB, bool G> struct MergeLDS {
     uint32_t slot[MergeShape<KB, G>::kSlots];
 };
 
-// Adds cnt copies of key k (local index idx) to the table.  Returns the slot
-// if this call created it (the key was new), else kEmpty.
+// Adds cnt copies of key k (local index idx) to the first `slots` slots of
+// the table.  Returns the slot if this call created it (the key was new),
+// else kEmpty.
 template <int KB, bool G>
 __device__ __forceinline__ uint32_t merge_insert(MergeLDS<KB, G>& L, const MKey<KB, G>& k, uint32_t idx,
-                                                 uint32_t cnt) {
-    constexpr uint32_t kSlots = MergeShape<KB, G>::kSlots;
+                                                 uint32_t cnt, uint32_t slots) {
     const uint32_t h = mkey_hash<KB, G>(k);
-    // the bucket came from the hash's top bits, so the slot takes the low ones
-    uint32_t s = MergeShape<KB, G>::kPow2 ? (h & (kSlots - 1)) : __umulhi(__builtin_rotateleft32(h, 16), kSlots);
-    for (uint32_t probe = 0; probe < kSlots; probe++) {
+    // a sketch table's bucket came from the hash's top bits, so the slot
+    // starts from the low ones
+    uint32_t s = __umulhi(__builtin_rotateleft32(h, 16), slots);
+    for (uint32_t probe = 0; probe < slots; probe++) {
         const uint32_t prev = atomicCAS(&L.slot[s], kEmpty, (idx << 16) | cnt);
         if (prev == kEmpty) return s;
         if (mkey_eq<KB, G>(L.key[prev >> 16], k)) {
             atomicAdd(&L.slot[s], cnt);  // counts stay < 2^16: never carry into the owner
             return kEmpty;
         }
-        s = s + 1 == kSlots ? 0u : s + 1;
+        s = s + 1 == slots ? 0u : s + 1;
     }
     return kEmpty;
 }
@@ -551,32 +557,49 @@ __global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan(
     }
 }
 
-// One workgroup of 2*nb threads: bucket starts, the chunk prefix and every
-// chunk's key range; clears the entry counters for the next batch.
+// One workgroup of nbt/2 threads (thread t owns buckets 2t and 2t+1): bucket
+// starts, the chunk prefix and every chunk's key range; clears the entry
+// counters for the next batch.
+constexpr uint32_t kStartPer = 2;
+static_assert(2 * kMaxBuckets / kStartPer <= 1024, "k_part_start is one workgroup");
+static_assert((2 * kMaxBuckets) % kPartThreads == 0, "k_part_scatter gives each thread whole buckets");
 template <int KB, bool G>
-__global__ __launch_bounds__(2 * kMaxBuckets) void k_part_start(MergeMeta* __restrict__ meta,
-                                                                MergeChunk* __restrict__ chunks) {
+__global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(MergeMeta* __restrict__ meta,
+                                                                            MergeChunk* __restrict__ chunks) {
     constexpr uint32_t chunk = MergeShape<KB, G>::kChunk;
-    __shared__ uint32_t a[2 * kMaxBuckets], c[2 * kMaxBuckets];
-    const uint32_t b = threadIdx.x, nbt = blockDim.x;
-    const uint32_t sz = meta->total[b];
-    a[b] = sz;
-    c[b] = (sz + chunk - 1) / chunk;
+    __shared__ uint32_t a[2 * kMaxBuckets / kStartPer], c[2 * kMaxBuckets / kStartPer];
+    const uint32_t t = threadIdx.x, nt = blockDim.x, nbt = kStartPer * nt;
+    uint32_t sz[kStartPer], nc[kStartPer], sa = 0, sc = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kStartPer; e++) {
+        sz[e] = meta->total[t * kStartPer + e];
+        nc[e] = (sz[e] + chunk - 1) / chunk;
+        sa += sz[e];
+        sc += nc[e];
+    }
+    a[t] = sa;
+    c[t] = sc;
     __syncthreads();
-    for (uint32_t off = 1; off < nbt; off <<= 1) {  // inclusive scans
-        const uint32_t va = b >= off ? a[b - off] : 0u, vc = b >= off ? c[b - off] : 0u;
+    for (uint32_t off = 1; off < nt; off <<= 1) {  // inclusive scans over the threads
+        const uint32_t va = t >= off ? a[t - off] : 0u, vc = t >= off ? c[t - off] : 0u;
         __syncthreads();
-        a[b] += va;
-        c[b] += vc;
+        a[t] += va;
+        c[t] += vc;
         __syncthreads();
     }
-    meta->size[b] = sz;
-    meta->start[b] = a[b] - sz;
-    meta->chunk0[b + 1] = c[b];
-    const uint32_t c0 = c[b] - (sz + chunk - 1) / chunk;  // this bucket's first chunk
-    for (uint32_t q = 0; q * chunk < sz; q++)
-        chunks[c0 + q] = MergeChunk{a[b] - sz + q * chunk, min(chunk, sz - q * chunk), b >= nbt / 2 ? 1u : 0u};
-    if (b == 0) {
+    uint32_t first = a[t] - sa, c0 = c[t] - sc;  // the first bucket's key start and first chunk
+#pragma unroll
+    for (uint32_t e = 0; e < kStartPer; e++) {
+        const uint32_t b = t * kStartPer + e;
+        meta->size[b] = sz[e];
+        meta->start[b] = first;
+        meta->chunk0[b + 1] = c0 + nc[e];
+        for (uint32_t q = 0; q < nc[e]; q++)
+            chunks[c0 + q] = MergeChunk{first + q * chunk, min(chunk, sz[e] - q * chunk), b >= nbt / 2 ? 1u : 0u};
+        first += sz[e];
+        c0 += nc[e];
+    }
+    if (t == 0) {
         meta->chunk0[0] = 0;
         meta->n_ins = 0;
         meta->n_del = 0;
@@ -616,20 +639,32 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
     }
     __syncthreads();
     if constexpr (kStage) {
-        const uint32_t b = threadIdx.x;             // kPartThreads == 2 * kMaxBuckets >= nbt
-        const uint32_t v = b < nbt ? hist[b] : 0u;
-        lstart[b] = v;
+        // exclusive prefix of the local counts: thread t owns buckets kPer*t ..
+        constexpr uint32_t kPer = 2 * kMaxBuckets / kPartThreads;
+        const uint32_t t = threadIdx.x;
+        uint32_t v[kPer], sum = 0;
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; e++) {
+            const uint32_t b = t * kPer + e;
+            v[e] = b < nbt ? hist[b] : 0u;
+            sum += v[e];
+        }
+        lstart[t] = sum;
         __syncthreads();
-        for (uint32_t off = 1; off < nbt; off <<= 1) {  // inclusive scan
-            const uint32_t x = b >= off ? lstart[b - off] : 0u;
+        for (uint32_t off = 1; off < kPartThreads; off <<= 1) {  // inclusive scan over the threads
+            const uint32_t x = t >= off ? lstart[t - off] : 0u;
             __syncthreads();
-            lstart[b] += x;
+            lstart[t] += x;
             __syncthreads();
         }
-        const uint32_t excl = lstart[b] - v;
+        uint32_t run = lstart[t] - sum;
         __syncthreads();
-        lstart[b] = excl;
-        if (b < nbt) hist[b] = meta->start[b] + offs[size_t(blockIdx.x) * nbt + b];
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; e++) {
+            lstart[t * kPer + e] = run;
+            run += v[e];
+        }
+        for (uint32_t b = t; b < nbt; b += kPartThreads) hist[b] = meta->start[b] + offs[size_t(blockIdx.x) * nbt + b];
         __syncthreads();
 #pragma unroll
         for (uint32_t r = 0; r < R; r++) {
@@ -678,7 +713,10 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
     const MergeChunk ck = chunks[c];
     const bool del = ck.del != 0;
     const uint32_t first = ck.first, n = ck.n;
-    for (uint32_t i = threadIdx.x; i < kSlots; i += kThreads) L.slot[i] = kEmpty;
+    // about two slots per key (at least one per thread): a small chunk clears
+    // and probes a small table
+    const uint32_t slots = min(kSlots, max(kThreads, 2 * n));
+    for (uint32_t i = threadIdx.x; i < slots; i += kThreads) L.slot[i] = kEmpty;
     if (threadIdx.x == 0) nloc = 0;
     __syncthreads();
     MKey<KB, G> k[J];
@@ -699,7 +737,7 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
         const uint32_t wgt = wave_peel<kPeel>(k[j], idx < n, [](const MKey<KB, G>& a, const MKey<KB, G>& b) {
             return mkey_eq<KB, G>(a, b);
         });
-        made[j] = wgt ? merge_insert<KB, G>(L, k[j], idx, wgt) : kEmpty;
+        made[j] = wgt ? merge_insert<KB, G>(L, k[j], idx, wgt, slots) : kEmpty;
         mine += made[j] != kEmpty;
     }
     // The creator of a slot emits its entry: a wavefront prefix sum of the

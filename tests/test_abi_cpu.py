@@ -54,10 +54,12 @@ def test_footprint_and_budget():
     merge = b * 4 + b * 4 + b * 4          # partitioned keys, entry keys, entry counts
     # cell records (z Fat counters + Slim), export staging (dense Fat), dense uint16 Slim
     # copy for queries, snapshots, merge buffers
-    hist = (b // 8192 + 1) * 1024 * 4      # per-partition-group bucket histograms
-    need = cells * 5 * 4 + cells * 4 * 4 + cells * 2 + 4 * b * 6 + merge + hist
+    hist = (b // 8192 + 1) * 2048 * 4      # per-partition-group bucket histograms (2 x 1024 buckets)
+    chunks = (b // 2048 + 2 * 1024 + 1) * 12   # every merge chunk's key range
+    meta = 4 * (2 * 1024 + 1) * 4 + 3 * 256     # per-bucket totals, starts, sizes, chunk prefix; counters
+    need = cells * 5 * 4 + cells * 4 * 4 + cells * 2 + 4 * b * 6 + merge + hist + chunks
     assert fp >= need
-    assert fp < need + (64 << 10)          # plus small bookkeeping and 256-B rounding
+    assert fp < need + meta + (8 << 10)          # plus 256-B rounding
     h = ctypes.c_void_p()
     rc = sf.lib().sf_create(ctypes.byref(c), fp - 1, None, ctypes.byref(h))
     assert rc == sf.SF_ENOMEM and not h.value
