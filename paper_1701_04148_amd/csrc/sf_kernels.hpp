@@ -455,7 +455,7 @@ struct MergeMeta {                    // device-side bookkeeping of one batch
     uint32_t total[2 * kMaxBuckets];  // keys per bucket (written by k_part_colscan)
     uint32_t start[2 * kMaxBuckets];  // first position of each bucket in the partitioned keys
     uint32_t size[2 * kMaxBuckets];
-    uint32_t chunk0[2 * kMaxBuckets + 1];  // first chunk of each bucket (prefix)
+    uint32_t chunk0[2 * kMaxBuckets + 1];  // chunks of the buckets before each bucket (prefix; [nbt] = all)
     // Entries emitted.  Every merging workgroup bumps one of these once, so
     // each sits on its own 256-byte line (atomics on one line serialise).
     alignas(256) uint32_t n_ins;
@@ -558,46 +558,99 @@ __global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan(
 }
 
 // One workgroup of nbt/2 threads (thread t owns buckets 2t and 2t+1): bucket
-// starts, the chunk prefix and every chunk's key range; clears the entry
-// counters for the next batch.
+// starts, then the merge chunks, then clears the entry counters for the next
+// batch.  A bucket of more than half a chunk of keys gets ceil(size / chunk)
+// chunks of its own.  Smaller buckets are packed: consecutive small buckets
+// of one op type whose starts fall in the same half-chunk window of the
+// partitioned keys share one chunk.  Such a chunk spans less than half a
+// chunk of starts plus a last bucket of at most half a chunk, so never more
+// than a chunk.  Equal keys share a bucket, so packing never splits a key's
+// copies between chunks.
 constexpr uint32_t kStartPer = 2;
 static_assert(2 * kMaxBuckets / kStartPer <= 1024, "k_part_start is one workgroup");
 static_assert((2 * kMaxBuckets) % kPartThreads == 0, "k_part_scatter gives each thread whole buckets");
 template <int KB, bool G>
 __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(MergeMeta* __restrict__ meta,
                                                                             MergeChunk* __restrict__ chunks) {
-    constexpr uint32_t chunk = MergeShape<KB, G>::kChunk;
-    __shared__ uint32_t a[2 * kMaxBuckets / kStartPer], c[2 * kMaxBuckets / kStartPer];
-    const uint32_t t = threadIdx.x, nt = blockDim.x, nbt = kStartPer * nt;
-    uint32_t sz[kStartPer], nc[kStartPer], sa = 0, sc = 0;
+    constexpr uint32_t K = MergeShape<KB, G>::kChunk, H = K / 2, P = kStartPer;
+    static_assert(P == 2, "the group-end lookup below assumes two buckets per thread");
+    __shared__ uint32_t sc[2 * kMaxBuckets / P];   // per-thread scans
+    __shared__ uint32_t st[2 * kMaxBuckets + 1];   // bucket starts, then the end of the keys
+    const uint32_t t = threadIdx.x, nt = blockDim.x, nbt = P * nt, half = nbt / 2;
+    uint32_t sz[P], sum = 0;
 #pragma unroll
-    for (uint32_t e = 0; e < kStartPer; e++) {
-        sz[e] = meta->total[t * kStartPer + e];
-        nc[e] = (sz[e] + chunk - 1) / chunk;
-        sa += sz[e];
-        sc += nc[e];
+    for (uint32_t e = 0; e < P; e++) {
+        sz[e] = meta->total[t * P + e];
+        sum += sz[e];
     }
-    a[t] = sa;
-    c[t] = sc;
+    // bucket starts
+    sc[t] = sum;
     __syncthreads();
-    for (uint32_t off = 1; off < nt; off <<= 1) {  // inclusive scans over the threads
-        const uint32_t va = t >= off ? a[t - off] : 0u, vc = t >= off ? c[t - off] : 0u;
+    for (uint32_t off = 1; off < nt; off <<= 1) {
+        const uint32_t x = t >= off ? sc[t - off] : 0u;
         __syncthreads();
-        a[t] += va;
-        c[t] += vc;
+        sc[t] += x;
         __syncthreads();
     }
-    uint32_t first = a[t] - sa, c0 = c[t] - sc;  // the first bucket's key start and first chunk
+    uint32_t first = sc[t] - sum;
 #pragma unroll
-    for (uint32_t e = 0; e < kStartPer; e++) {
-        const uint32_t b = t * kStartPer + e;
+    for (uint32_t e = 0; e < P; e++) {
+        const uint32_t b = t * P + e;
+        st[b] = first;
         meta->size[b] = sz[e];
         meta->start[b] = first;
-        meta->chunk0[b + 1] = c0 + nc[e];
-        for (uint32_t q = 0; q < nc[e]; q++)
-            chunks[c0 + q] = MergeChunk{first + q * chunk, min(chunk, sz[e] - q * chunk), b >= nbt / 2 ? 1u : 0u};
         first += sz[e];
+    }
+    if (t == nt - 1) st[nbt] = first;
+    __syncthreads();
+    // where packed groups start: op type boundary, next to a big bucket, new window
+    bool gs[P];
+    uint32_t lo = nbt;  // this thread's first group start (nbt: none)
+#pragma unroll
+    for (uint32_t e = 0; e < P; e++) {
+        const uint32_t b = t * P + e, pb = b ? b - 1 : 0u;
+        gs[e] = b == 0 || b == half || sz[e] > H || st[b] - st[pb] > H || st[b] / H != st[pb] / H;
+        if (gs[e] && lo == nbt) lo = b;
+    }
+    __syncthreads();
+    sc[t] = lo;
+    __syncthreads();
+    for (uint32_t off = 1; off < nt; off <<= 1) {  // suffix minimum: first group start at or after thread t
+        const uint32_t x = t + off < nt ? sc[t + off] : nbt;
+        __syncthreads();
+        sc[t] = min(sc[t], x);
+        __syncthreads();
+    }
+    const uint32_t after = t + 1 < nt ? sc[t + 1] : nbt;  // first group start past this thread's buckets
+    const uint32_t nxt[P] = {gs[1] ? t * P + 1 : after, after};
+    uint32_t nc[P], csum = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < P; e++) {
+        const uint32_t b = t * P + e;
+        nc[e] = sz[e] > H ? (sz[e] + K - 1) / K : (gs[e] && st[nxt[e]] > st[b] ? 1u : 0u);
+        csum += nc[e];
+    }
+    __syncthreads();                               // every thread has read sc
+    sc[t] = csum;
+    __syncthreads();
+    for (uint32_t off = 1; off < nt; off <<= 1) {  // chunk prefix
+        const uint32_t x = t >= off ? sc[t - off] : 0u;
+        __syncthreads();
+        sc[t] += x;
+        __syncthreads();
+    }
+    uint32_t c0 = sc[t] - csum;
+#pragma unroll
+    for (uint32_t e = 0; e < P; e++) {
+        const uint32_t b = t * P + e, del = b >= half ? 1u : 0u;
+        if (sz[e] > H) {
+            for (uint32_t q = 0; q < nc[e]; q++)
+                chunks[c0 + q] = MergeChunk{st[b] + q * K, min(K, sz[e] - q * K), del};
+        } else if (nc[e]) {
+            chunks[c0] = MergeChunk{st[b], st[nxt[e]] - st[b], del};
+        }
         c0 += nc[e];
+        meta->chunk0[b + 1] = c0;
     }
     if (t == 0) {
         meta->chunk0[0] = 0;
