@@ -487,6 +487,40 @@ __device__ __forceinline__ uint32_t bucket_of(const MKey<KB, G>& k, bool del, ui
     return b + (del ? (1u << nb_log2) : 0u);
 }
 
+// Inclusive scan under op over the workgroup's threads in thread order
+// (blockDim.x <= 1024): a shuffle scan inside each wavefront, then one over
+// the wavefront totals.  tmp: 16 words of LDS.  Call with the whole workgroup.
+template <class Op>
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, Op op, uint32_t identity, uint32_t* tmp) {
+    const uint32_t lane = lane_id(), wv = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t x = __shfl_up(v, off);
+        if (lane >= uint32_t(off)) v = op(v, x);
+    }
+    if (lane == 63u || threadIdx.x == blockDim.x - 1) tmp[wv] = v;  // the wavefront's total
+    __syncthreads();
+    if (wv == 0) {
+        uint32_t t = lane < nw ? tmp[lane] : identity;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t x = __shfl_up(t, off);
+            if (lane >= uint32_t(off)) t = op(t, x);
+        }
+        if (lane < nw) tmp[lane] = t;
+    }
+    __syncthreads();
+    v = wv ? op(tmp[wv - 1], v) : v;
+    __syncthreads();  // tmp is free again
+    return v;
+}
+struct AddOp {
+    __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; }
+};
+struct MinOp {
+    __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a < b ? a : b; }
+};
+
 // Counts the ops of every bucket in each group's tile.
 template <int KB, bool G, class P>
 __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* __restrict__ hist_out,
@@ -574,7 +608,8 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
                                                                             MergeChunk* __restrict__ chunks) {
     constexpr uint32_t K = MergeShape<KB, G>::kChunk, H = K / 2, P = kStartPer;
     static_assert(P == 2, "the group-end lookup below assumes two buckets per thread");
-    __shared__ uint32_t sc[2 * kMaxBuckets / P];   // per-thread scans
+    __shared__ uint32_t tmp[16];
+    __shared__ uint32_t rev[2 * kMaxBuckets / P];  // per-thread values in reverse thread order
     __shared__ uint32_t st[2 * kMaxBuckets + 1];   // bucket starts, then the end of the keys
     const uint32_t t = threadIdx.x, nt = blockDim.x, nbt = P * nt, half = nbt / 2;
     uint32_t sz[P], sum = 0;
@@ -584,15 +619,7 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
         sum += sz[e];
     }
     // bucket starts
-    sc[t] = sum;
-    __syncthreads();
-    for (uint32_t off = 1; off < nt; off <<= 1) {
-        const uint32_t x = t >= off ? sc[t - off] : 0u;
-        __syncthreads();
-        sc[t] += x;
-        __syncthreads();
-    }
-    uint32_t first = sc[t] - sum;
+    uint32_t first = block_scan(sum, AddOp{}, 0u, tmp) - sum;
 #pragma unroll
     for (uint32_t e = 0; e < P; e++) {
         const uint32_t b = t * P + e;
@@ -612,16 +639,14 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
         gs[e] = b == 0 || b == half || sz[e] > H || st[b] - st[pb] > H || st[b] / H != st[pb] / H;
         if (gs[e] && lo == nbt) lo = b;
     }
+    // first group start at or after each thread's buckets: a minimum scan in
+    // reverse thread order
+    rev[nt - 1 - t] = lo;
     __syncthreads();
-    sc[t] = lo;
+    const uint32_t suf = block_scan(rev[t], MinOp{}, nbt, tmp);  // for thread nt-1-t
+    rev[t] = suf;  // block_scan synchronised after every read of rev above
     __syncthreads();
-    for (uint32_t off = 1; off < nt; off <<= 1) {  // suffix minimum: first group start at or after thread t
-        const uint32_t x = t + off < nt ? sc[t + off] : nbt;
-        __syncthreads();
-        sc[t] = min(sc[t], x);
-        __syncthreads();
-    }
-    const uint32_t after = t + 1 < nt ? sc[t + 1] : nbt;  // first group start past this thread's buckets
+    const uint32_t after = t + 1 < nt ? rev[nt - 2 - t] : nbt;  // first group start past this thread's buckets
     const uint32_t nxt[P] = {gs[1] ? t * P + 1 : after, after};
     uint32_t nc[P], csum = 0;
 #pragma unroll
@@ -630,16 +655,7 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
         nc[e] = sz[e] > H ? (sz[e] + K - 1) / K : (gs[e] && st[nxt[e]] > st[b] ? 1u : 0u);
         csum += nc[e];
     }
-    __syncthreads();                               // every thread has read sc
-    sc[t] = csum;
-    __syncthreads();
-    for (uint32_t off = 1; off < nt; off <<= 1) {  // chunk prefix
-        const uint32_t x = t >= off ? sc[t - off] : 0u;
-        __syncthreads();
-        sc[t] += x;
-        __syncthreads();
-    }
-    uint32_t c0 = sc[t] - csum;
+    uint32_t c0 = block_scan(csum, AddOp{}, 0u, tmp) - csum;  // chunk prefix
 #pragma unroll
     for (uint32_t e = 0; e < P; e++) {
         const uint32_t b = t * P + e, del = b >= half ? 1u : 0u;
@@ -671,6 +687,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
     constexpr bool kStage = sizeof(MKey<KB, G>) <= 8;
     __shared__ uint32_t hist[2 * kMaxBuckets];       // local counts, then the group's first global slot
     __shared__ uint32_t lstart[2 * kMaxBuckets];     // exclusive prefix of the local counts
+    __shared__ uint32_t tmp[16];
     __shared__ MKey<KB, G> stage[kStage ? kPartOps : 1];
     __shared__ uint16_t sbk[kStage ? kPartOps : 1];
     const uint32_t nbt = 2u << nb_log2;
@@ -702,16 +719,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
             v[e] = b < nbt ? hist[b] : 0u;
             sum += v[e];
         }
-        lstart[t] = sum;
-        __syncthreads();
-        for (uint32_t off = 1; off < kPartThreads; off <<= 1) {  // inclusive scan over the threads
-            const uint32_t x = t >= off ? lstart[t - off] : 0u;
-            __syncthreads();
-            lstart[t] += x;
-            __syncthreads();
-        }
-        uint32_t run = lstart[t] - sum;
-        __syncthreads();
+        uint32_t run = block_scan(sum, AddOp{}, 0u, tmp) - sum;
 #pragma unroll
         for (uint32_t e = 0; e < kPer; e++) {
             lstart[t * kPer + e] = run;
