@@ -228,8 +228,12 @@ struct MergeRun {
         {
             Timed tm(prof, st, SF_K_PARTITION, cnt);
             k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, nb_log2);
-            k_part_colscan<uint32_t><<<blocks_for(2 * nb, kScanBuckets), kScanBuckets * kScanSegs, 0, st>>>(
-                hist, part_groups, 2 * nb, meta);
+            if (part_groups <= kScanWaves * kScanRowsReg)
+                k_part_colscan<uint32_t><<<blocks_for(2 * nb, kScanCols), kScanCols * kScanWaves, 0, st>>>(
+                    hist, part_groups, 2 * nb, meta);
+            else
+                k_part_colscan_tall<uint32_t><<<blocks_for(2 * nb, kScanBuckets), kScanBuckets * kScanSegs, 0, st>>>(
+                    hist, part_groups, 2 * nb, meta);
             k_part_start<KB, G><<<1, 2 * nb / kStartPer, 0, st>>>(meta, chunks);
             k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, meta, part, nb_log2);
         }

@@ -538,11 +538,71 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* _
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist_out[size_t(blockIdx.x) * nbt + b] = hist[b];
 }
 
-// Column scans of hist: 4 buckets per workgroup, the groups split into 64
-// segments.  hist[g][b] becomes the number of bucket-b keys of groups < g.
+// Column scans of hist: 64 buckets per workgroup, one per lane, so that a
+// wavefront reads 256 contiguous bytes of a row; the 16 wavefronts split the
+// groups into segments.  hist[g][b] becomes the number of bucket-b keys of
+// groups < g.  A segment of at most 64 rows stays in registers between the
+// sum and the prefix pass; longer ones are read twice.
+constexpr uint32_t kScanCols = 64, kScanWaves = 16, kScanRowsReg = 64;
+template <typename T>
+__global__ __launch_bounds__(kScanCols * kScanWaves) void k_part_colscan(
+    T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
+    __shared__ T seg_sum[kScanWaves][kScanCols];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / 64;
+    const uint32_t b = blockIdx.x * kScanCols + lane;
+    const uint32_t rows = (groups + kScanWaves - 1) / kScanWaves;
+    const uint32_t g0 = wv * rows, g1 = min(groups, g0 + rows);
+    const bool in_reg = rows <= kScanRowsReg;
+    T v[kScanRowsReg];
+    T sum = 0;
+    if (b < nbt) {
+        if (in_reg) {
+#pragma unroll
+            for (uint32_t r = 0; r < kScanRowsReg; r++) {
+                v[r] = g0 + r < g1 ? hist[size_t(g0 + r) * nbt + b] : T(0);
+                sum += v[r];
+            }
+        } else {
+            for (uint32_t g = g0; g < g1; g++) sum += hist[size_t(g) * nbt + b];
+        }
+    }
+    seg_sum[wv][lane] = sum;
+    __syncthreads();
+    if (wv == 0) {                                // exclusive prefix over the segments, per column
+        T run = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kScanWaves; w++) {
+            const T x = seg_sum[w][lane];
+            seg_sum[w][lane] = run;
+            run += x;
+        }
+        if (b < nbt) meta->total[b] = run;
+    }
+    __syncthreads();
+    T run = seg_sum[wv][lane];                    // keys of this bucket in earlier segments
+    if (b < nbt) {
+        if (in_reg) {
+#pragma unroll
+            for (uint32_t r = 0; r < kScanRowsReg; r++) {
+                if (g0 + r < g1) hist[size_t(g0 + r) * nbt + b] = run;
+                run += v[r];
+            }
+        } else {
+            for (uint32_t g = g0; g < g1; g++) {
+                const T x = hist[size_t(g) * nbt + b];
+                hist[size_t(g) * nbt + b] = run;
+                run += x;
+            }
+        }
+    }
+}
+
+// The same for a tall matrix (more than kScanWaves * kScanRowsReg groups, as
+// in sketch groups and pools): 4 buckets per workgroup and the groups split
+// into 64 segments, so that many workgroups share the rows.
 constexpr uint32_t kScanBuckets = 4, kScanSegs = 64;
 template <typename T>
-__global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan(
+__global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan_tall(
     T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
     constexpr uint32_t kRowsReg = 16;             // a segment's rows kept in registers when it has few
     __shared__ T seg_sum[kScanSegs][kScanBuckets];
