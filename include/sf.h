@@ -152,12 +152,13 @@ int sf_set_tile(sf_sketch *sk, uint32_t tile_ops);
 
 /* Where duplicate keys are merged before they reach a counter: 1 = across
  * the whole batch (the default: keys are first partitioned into hash
- * buckets, then merged per bucket chunk, and S1..S5 run once per merged
- * key), 0 = per tile of consecutive ops.  Results are identical; the
- * batch-wide merge issues far fewer atomics and random reads. */
+ * buckets, then merged per chunk of whole buckets -- a large bucket spans
+ * several chunks -- and S1..S5 run once per merged key), 0 = per tile of
+ * consecutive ops.  Results are identical; the batch-wide merge issues far
+ * fewer atomics and random reads. */
 int sf_set_merge(sf_sketch *sk, int batch_wide);
 
-/* Merged entries (distinct keys per bucket chunk) the batch-wide merge has
+/* Merged entries (distinct keys per merge chunk) the batch-wide merge has
  * emitted since sf_create, for inserts and deletes; waits for the stream. */
 int sf_merge_stats(sf_sketch *sk, uint64_t *insert_entries, uint64_t *delete_entries);
 
@@ -175,7 +176,7 @@ enum sf_kernel_kind {
     SF_K_CLAMP = 4,    /* S5 */
     SF_K_QUERY = 5,
     SF_K_EXPORT = 6,
-    SF_K_MERGE = 7,    /* batch-wide merge: merge per bucket chunk (+ S1) */
+    SF_K_MERGE = 7,    /* batch-wide merge: merge per chunk of bucketed keys */
     SF_K_PARTITION = 8,/* batch-wide merge: bucket counts, starts, scatter */
     SF_K_COUNT = 10
 };
