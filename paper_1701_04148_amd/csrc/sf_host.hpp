@@ -228,7 +228,9 @@ struct MergeRun {
         {
             Timed tm(prof, st, SF_K_PARTITION, cnt);
             k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, nb_log2);
-            if (part_groups <= kScanWaves * kScanRowsReg)
+            // one lane per bucket pays off for 512..1024 rows; fewer rows (small
+            // batches) or more (sketch tables) spread better over segments
+            if (part_groups >= kScanWaves * kScanRowsReg / 2 && part_groups <= kScanWaves * kScanRowsReg)
                 k_part_colscan<uint32_t><<<blocks_for(2 * nb, kScanCols), kScanCols * kScanWaves, 0, st>>>(
                     hist, part_groups, 2 * nb, meta);
             else

@@ -597,9 +597,10 @@ __global__ __launch_bounds__(kScanCols * kScanWaves) void k_part_colscan(
     }
 }
 
-// The same for a tall matrix (more than kScanWaves * kScanRowsReg groups, as
-// in sketch groups and pools): 4 buckets per workgroup and the groups split
-// into 64 segments, so that many workgroups share the rows.
+// The same for other shapes -- a tall matrix (more than kScanWaves *
+// kScanRowsReg groups, as in sketch groups and pools) or a short one (a small
+// batch): 4 buckets per workgroup and the groups split into 64 segments, so
+// that many workgroups share the rows.
 constexpr uint32_t kScanBuckets = 4, kScanSegs = 64;
 template <typename T>
 __global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan_tall(

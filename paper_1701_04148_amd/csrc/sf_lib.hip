@@ -54,7 +54,7 @@ struct sf_sketch {
     void* part;       // batch merge: keys partitioned by bucket      [b] keys
     void* ent_key;    // batch merge: one key per merged entry        [b] keys
     uint32_t* ent_cnt;//              its op count                    [b]
-    uint32_t* hist;   //              per-group bucket histograms     [b/8192+1][1024]
+    uint32_t* hist;   //              per-group bucket histograms     [b/8192+1][2048]
     MergeChunk* chunks;//             key range of every merge chunk
     MergeMeta* meta;
     Profiler prof;
