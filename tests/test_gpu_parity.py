@@ -142,6 +142,49 @@ def test_batch_merge_with_one_hot_key():
     check(4, 1 << 14, 4, 4, keys, ops, q, n, tag="hot", merge=True)
 
 
+@pytest.mark.parametrize("kb", [4, 13])
+def test_merge_chunk_packing_shapes(kb):
+    """One batch whose bucket sizes are built around the rule that packs small
+    buckets into shared merge chunks: empty, tiny, exactly half a chunk, one
+    key over half, one chunk, several chunks, runs of small buckets across
+    half-chunk windows and next to big ones, in both op types.  Keys are
+    picked by their row-0 column, which decides a lone sketch's bucket."""
+    K = 8192 if kb == 4 else 2048                 # keys per merge chunk of a lone sketch
+    d, w, z, nb = 4, 1 << 14, 4, 32
+    H = K // 2
+    ins = [0, 3, H, H + 1, 5, 5 * H, 7, 0, K // 4, K // 4, K // 4, K // 4 + 3, 1, 1, 1, 6 * H,
+           H, H, 0, 0, 10, K - 1, K, K + 1, 2, 0, K // 3, K // 3, K // 3, 4, 0, 100]
+    dels = [0, 3, 1, H, 0, H + 1, 7, 0, 2, 0, K // 4, 1, 1, 0, 1, 3 * H,
+            0, H, 0, 0, 10, 5, K, 9, 2, 0, 1, 0, K // 3, 4, 0, 100]
+    n = sum(ins) + sum(dels)
+    assert nb // 2 * K < n <= nb * K               # so that the batch gets exactly nb buckets per op type
+    rng = np.random.default_rng(70 + kb)
+    if kb == 4:
+        cand = rng.choice(2**32, size=160_000, replace=False).astype(np.uint32)
+    else:
+        cand = rng.integers(0, 256, size=(160_000, 13), dtype=np.uint8)
+    h, _ = oracle.Sketch(d, w, z, kb).indices(cand)
+    bucket = h[:, 0].astype(np.int64) * nb // w
+    ins_keys, del_keys = [], []
+    for j in range(nb):
+        pool = cand[bucket == j]
+        if ins[j] == 0:
+            continue
+        distinct = pool[: max(1, ins[j] // 3)]
+        occ = distinct[rng.integers(0, distinct.shape[0], ins[j]) % distinct.shape[0]]
+        ins_keys.append(occ)
+        if dels[j]:
+            del_keys.append(occ[rng.permutation(ins[j])[: dels[j]]])   # deletes of inserted copies
+    ki = np.concatenate(ins_keys)
+    kd = np.concatenate(del_keys)
+    ki = ki[rng.permutation(ki.shape[0])]
+    kd = kd[rng.permutation(kd.shape[0])]
+    keys = np.concatenate([ki, kd])
+    ops = np.concatenate([np.zeros(ki.shape[0], np.uint8), np.ones(kd.shape[0], np.uint8)])
+    q = np.concatenate([np.unique(ki, axis=0), cand[-1000:]])
+    check(d, w, z, kb, keys, ops, q, 1 << 20, tag="packing", merge=True)
+
+
 def test_query_exported_slim_collector():
     """The collector answers from the exported uint16 Slim alone (sf_query_slim)."""
     import torch
