@@ -274,6 +274,38 @@ __global__ __launch_bounds__(kBlock) void k_query(P plan) {
 }
 
 // The Fat-subsketch in its dense [d][w][z] form, out of the cell records.
+// Point query over a dense uint16 Slim [d][w], one row per XCD.  The
+// dispatcher deals workgroups to the 8 XCDs round-robin, so workgroup b runs
+// on XCD b % 8.  With d dividing 8, XCD x reads only row x % d (2 MiB at
+// w = 2^20, which its 4 MB L2 holds) and takes every (8/d)-th run of kBlock
+// keys.  part[r][t] receives row r's counter of key t; k_query_min takes the
+// minimum over the rows.  Placement only decides cache hits: any other
+// dispatch order gives the same answers.  gridDim.x is a multiple of 8.
+constexpr uint32_t kXcds = 8;
+template <int KB>
+__global__ __launch_bounds__(kBlock) void k_query_rows(const uint8_t* __restrict__ keys, uint32_t n,
+                                                       const uint16_t* __restrict__ view, Geom g, uint32_t d,
+                                                       uint16_t* __restrict__ part) {
+    const uint32_t x = blockIdx.x % kXcds, r = x % d, nsub = kXcds / d;
+    const uint32_t slot = (blockIdx.x / kXcds) * nsub + x / d, nslots = (gridDim.x / kXcds) * nsub;
+    const uint16_t* row = view + size_t(r) * g.w;
+    for (uint32_t t = slot * kBlock + threadIdx.x; t < n; t += nslots * kBlock) {
+        uint32_t h, f;
+        split(g, Mixed<KB>(load_key<KB>(keys, t)).row(g.seed_base + r), h, f);
+        part[size_t(r) * n + t] = row[h];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_query_min(const T* __restrict__ part, uint32_t n, uint32_t d,
+                                                      uint32_t* __restrict__ out) {
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
+        uint32_t m = part[t];
+        for (uint32_t r = 1; r < d; r++) m = min(m, uint32_t(part[size_t(r) * n + t]));
+        out[t] = m;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_unpack_fat(const T* __restrict__ rec, T* __restrict__ out,
                                                        size_t cells, uint32_t z) {

@@ -44,6 +44,7 @@ struct sf_sketch {
     uint32_t* fat;
     uint32_t* slim;
     uint16_t* stage;
+    uint64_t stage_bytes;  // also the per-row query scratch (stream-ordered like the exports)
     uint16_t* view;   // dense uint16 Slim as of the last export (queries read it while fresh)
     bool view_fresh;  // no update or reset since view was packed
     uint32_t* bpre;
@@ -161,6 +162,35 @@ void query_launch(const sf_config* c, const Geom& g, const void* slim, const uin
     launch_query_rows<KB, UniformPlan<KB>, S>(c->d, plan, blocks_for(cnt, kBlock), st);
 }
 
+// The one-row-per-XCD query over a dense uint16 Slim, with part (part_bytes
+// of device scratch) holding the per-row counters of a run of keys.
+int query_by_rows(Profiler* prof, const sf_config* c, const Geom& g, const uint16_t* view, const uint8_t* k8,
+                  uint64_t n, uint32_t* out, uint16_t* part, uint64_t part_bytes, hipStream_t st) {
+    const uint32_t kb = c->key_bytes, d = c->d;
+    const uint64_t run = part_bytes / (2ull * d) < kMaxLaunch ? part_bytes / (2ull * d) : kMaxLaunch;
+    for (uint64_t lo = 0; lo < n; lo += run) {
+        const uint32_t cnt = uint32_t(n - lo < run ? n - lo : run);
+        const uint32_t per_xcd = blocks_for(blocks_for(cnt, kBlock), kXcds / d);
+        const unsigned grid = kXcds * (per_xcd < 1024u ? per_xcd : 1024u);
+        const unsigned mgrid = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
+        Timed tm(prof, st, SF_K_QUERY, cnt);
+        if (kb == 4) k_query_rows<4><<<grid, kBlock, 0, st>>>(k8 + lo * kb, cnt, view, g, d, part);
+        else k_query_rows<13><<<grid, kBlock, 0, st>>>(k8 + lo * kb, cnt, view, g, d, part);
+        k_query_min<uint16_t><<<mgrid, kBlock, 0, st>>>(part, cnt, d, out + lo);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SF_OK : device_fail(e, "query launch");
+}
+
+int query_checks(const sf_config* c, const void* keys, uint64_t n, uint32_t* out) {
+    if (c->key_bytes == 4 && (reinterpret_cast<uintptr_t>(keys) & 3u))
+        return fail(SF_EINVAL, "uint32 keys must be 4-byte aligned");
+    if (reinterpret_cast<uintptr_t>(out) & 3u) return fail(SF_EINVAL, "out must be 4-byte aligned");
+    int rc = check_gpu_ptr(keys, n * c->key_bytes, "keys");
+    if (rc) return rc;
+    return check_gpu_ptr(out, n * 4, "out");
+}
+
 int query_common(Profiler* prof, const sf_config* c, const Geom& g, const void* slim, bool slim16,
                  const void* keys, uint64_t n, uint32_t* out, hipStream_t st) {
     if (n == 0) return SF_OK;
@@ -225,6 +255,7 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     s->fat = reinterpret_cast<uint32_t*>(base);
     s->slim = reinterpret_cast<uint32_t*>(base) + cfg->z;
     s->stage = reinterpret_cast<uint16_t*>(base + sz.fat + sz.slim);
+    s->stage_bytes = sz.stage;
     s->view = reinterpret_cast<uint16_t*>(base + sz.fat + sz.slim + sz.stage);
     s->view_fresh = false;
     s->bpre = reinterpret_cast<uint32_t*>(base + sz.fat + sz.slim + sz.stage + sz.view);
@@ -370,6 +401,15 @@ int sf_update_host(sf_sketch* s, const void* host_keys, const uint8_t* host_ops,
 
 int sf_query(sf_sketch* s, const void* keys, uint64_t n, uint32_t* out) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    // the dense uint16 Slim, one row per XCD, once the whole copy outgrows an
+    // XCD's 4 MB L2
+    if (s->view_fresh && kXcds % s->cfg.d == 0 && uint64_t(s->cfg.d) * s->cfg.w * 2 > (4ull << 20)) {
+        if (n == 0) return SF_OK;
+        int rc = query_checks(&s->cfg, keys, n, out);
+        if (rc) return rc;
+        return query_by_rows(&s->prof, &s->cfg, s->g, s->view, static_cast<const uint8_t*>(keys), n, out,
+                             reinterpret_cast<uint16_t*>(s->stage), s->stage_bytes, s->stream);
+    }
     if (s->view_fresh)  // the dense uint16 Slim: a fifth of the records' footprint
         return query_common(&s->prof, &s->cfg, s->g, s->view, true, keys, n, out, s->stream);
     return query_common(&s->prof, &s->cfg, s->g, s->slim, false, keys, n, out, s->stream);

@@ -204,6 +204,35 @@ def test_query_exported_slim_collector():
         sk.close()
 
 
+@pytest.mark.parametrize("d,w,z,kb,nq", [(4, 1 << 20, 4, 4, 300_000), (8, 1 << 19, 1, 4, 2_500_000),
+                                         (2, 1 << 21, 2, 13, 200_000)])
+def test_query_one_row_per_xcd(d, w, z, kb, nq):
+    """After an export a Slim larger than 4 MiB is queried one row per XCD (per-row
+    counters in scratch, then a minimum pass), in runs that fit the scratch
+    (three runs for the d=8, z=1 case).  Answers equal the records path's and
+    the oracle's query on the exported Slim."""
+    import torch
+    rng = np.random.default_rng(d * 31 + kb)
+    keys, ops, uni = random_turnstile(rng, 400_000, 60_000, 0.1, key_bytes=kb)
+    if kb == 4:
+        extra = rng.integers(0, 2**32, nq - uni.shape[0], dtype=np.uint64).astype(np.uint32)
+    else:
+        extra = rng.integers(0, 256, size=(nq - uni.shape[0], 13), dtype=np.uint8)
+    q = np.concatenate([uni, extra])
+    say(f"[case] row-per-XCD query d={d} w={w} z={z} kb={kb} q={nq}")
+    sk = sf.Sketch(d, w, z, key_bytes=kb, batch_ops=1 << 18)
+    sk.update(dev_keys(keys), torch.from_numpy(ops).cuda())
+    dq = dev_keys(q)
+    before = sk.query(dq).cpu().numpy().view(np.uint32).copy()      # records path
+    slim = sk.export_slim()
+    after = sk.query(dq).cpu().numpy().view(np.uint32)               # dense copy, one row per XCD
+    sk.close()
+    assert_same(after, before, "row-per-XCD query vs records query")
+    sample = np.concatenate([np.arange(min(nq, 150_000)), rng.integers(0, nq, 20_000)])
+    exp = oracle.query_slim(slim, d, w, z, q[sample], key_bytes=kb)
+    assert_same(after[sample], exp, "row-per-XCD query vs oracle on the exported Slim")
+
+
 def test_query_reads_exported_copy_only_while_fresh():
     """sf_query answers from the sketch's dense copy made by sf_export_slim until
     the next update or reset: before export, after export, after more updates
