@@ -122,7 +122,11 @@ int sf_update_host(sf_sketch *sk, const void *host_keys, const uint8_t *host_ops
  * smallest of the d Slim counters of keys[t], as uint32 (device pointer).
  * Between an sf_export_slim and the next update or reset, the query reads
  * the dense uint16 copy that export made (same values, a fifth of the
- * memory footprint); otherwise it reads the Slim words of the sketch. */
+ * memory footprint); otherwise it reads the Slim words of the sketch.  A
+ * dense copy larger than 4 MiB with d dividing 8 is read one row per XCD:
+ * per-row counters go to the sketch's export staging buffer (like every
+ * call, ordered on the sketch's stream), then a second pass takes the
+ * minimum. */
 int sf_query(sf_sketch *sk, const void *keys, uint64_t n, uint32_t *out);
 
 /* Collector-side point query over an exported Slim (slim: device pointer to
