@@ -97,7 +97,7 @@ def stored_traffic(kernel_kind: str, workload: str):
 
 KIND_OF_KERNEL = {"k_snapshot": "snapshot", "k_raise": "raise", "k_clamp": "clamp",
                   "k_query": "query", "k_query_rows": "query", "k_query_min": "query", "k_pack16": "export", "k_merge": "merge",
-                  "k_entries_snapshot": "snapshot", "k_entries_snapshot_rows": "snapshot", "k_entries_clamp_rows": "clamp",
+                  "k_entries_snapshot": "snapshot", "k_entries_snapshot_rows": "snapshot",
                   "k_entries_raise": "raise", "k_entries_clamp": "clamp",
                   "k_part_count": "part_count", "k_part_colscan": "part_colscan", "k_part_colscan_tall": "part_colscan", "k_part_start": "part_start",
                   "k_unpack_fat": "fat_export",

@@ -225,8 +225,8 @@ struct MergeRun {
         const uint32_t nb = buckets_for<KB, G>(cnt);
         const uint32_t nb_log2 = uint32_t(__builtin_ctz(nb));
         const unsigned eg = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
-        // S1 and S5 one row per XCD when the row count divides the XCD count:
-        // the same threads per row as eg per entry, in a multiple of 8 workgroups
+        // S1 one row per XCD when the row count divides the XCD count: the same
+        // threads per row as eg per entry, in a multiple of 8 workgroups
         constexpr bool kRowsPerXcd = D > 0 && kXcds % D == 0;
         const unsigned xg = kXcds * (blocks_for(uint64_t(eg) * (D > 0 ? D : 1), kXcds) < 1024u
                                          ? blocks_for(uint64_t(eg) * (D > 0 ? D : 1), kXcds)
@@ -275,10 +275,7 @@ struct MergeRun {
             }
             {
                 Timed tm(prof, st, SF_K_CLAMP, cnt);
-                if constexpr (kRowsPerXcd)
-                    k_entries_clamp_rows<KB, D, G, SR><<<xg, kBlock, 0, st>>>(meta, ent_key, cap, sr);
-                else
-                    k_entries_clamp<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, cap, sr);
+                k_entries_clamp<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, cap, sr);
             }
         }
     }

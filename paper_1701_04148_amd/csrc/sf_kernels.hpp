@@ -1060,12 +1060,13 @@ __global__ __launch_bounds__(kBlock) void k_entries_clamp(const MergeMeta* __res
     }
 }
 
-// S1 and S5 one row per XCD.  Their rows are independent (S1 stores per-row
-// values, S5 updates each row on its own), so with D dividing 8 workgroup b
-// handles row (b mod 8) mod D for its share of the entries, and an XCD's
-// random reads stay within one row of records (a quarter of the footprint at
-// D = 4, so more of them hit its L2).  As with the query, the dispatch order
-// only decides cache hits.  gridDim.x is a multiple of 8.
+// S1 one row per XCD.  Its rows are independent (it stores per-row values),
+// so with D dividing 8 workgroup b handles row (b mod 8) mod D for its share
+// of the entries, and an XCD's random reads stay within one row of records (a
+// quarter of the footprint at D = 4, so more of them hit its L2).  As with the
+// query, the dispatch order only decides cache hits.  gridDim.x is a multiple
+// of 8.  (S5 gains nothing from this: a batch has few delete entries, and the
+// wider grid costs more than the cache hits save.)
 struct XcdRow {
     uint32_t r, slot, nslots;
     template <int D> __device__ __forceinline__ static XcdRow of() {
@@ -1092,23 +1093,6 @@ __global__ __launch_bounds__(kBlock) void k_entries_snapshot_rows(const MergeMet
         const uint32_t b = sd.fat[cell * sd.g.rs + f];
         asnap[size_t(xr.r) * stride + e] = uint16_t(a);
         bpre[size_t(xr.r) * stride + e] = b;
-    }
-}
-
-template <int KB, int D, bool G, class SR>
-__global__ __launch_bounds__(kBlock) void k_entries_clamp_rows(const MergeMeta* __restrict__ meta,
-                                                               const MKey<KB, G>* __restrict__ ent_key, uint32_t cap,
-                                                               SR sr) {
-    const XcdRow xr = XcdRow::of<D>();
-    const uint32_t n = meta->n_del;
-    for (uint32_t e = xr.slot * kBlock + threadIdx.x; e < n; e += xr.nslots * kBlock) {
-        const MKey<KB, G> m = ent_key[cap - 1 - e];
-        const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
-        uint32_t h, f;
-        split(sd.g, Mixed<KB>(m.k).row(sd.g.seed_base + xr.r), h, f);
-        const size_t cell = size_t(xr.r) * sd.g.w + h;
-        const uint32_t mval = bucket_max(sd.fat, cell, sd.g);
-        if (sd.slim[cell * sd.g.rs] > mval) atomic_min_u32(&sd.slim[cell * sd.g.rs], mval);
     }
 }
 
