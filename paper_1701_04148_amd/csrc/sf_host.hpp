@@ -247,17 +247,18 @@ struct MergeRun {
         }
         {
             Timed tm(prof, st, SF_K_MERGE, cnt);
-            k_merge<KB, G><<<blocks_for(cnt, MergeShape<KB, G>::kChunk) + 2 * nb, MergeShape<KB, G>::kThreads, 0, st>>>(
-                part, meta, chunks, ent_key, ent_cnt, cap, nb_log2);
+            k_merge<KB, G, SR><<<blocks_for(cnt, MergeShape<KB, G>::kChunk) + 2 * nb, MergeShape<KB, G>::kThreads, 0,
+                                 st>>>(part, meta, chunks, ent_key, ent_cnt, cap, nb_log2, sr, bpre, asnap);
         }
         if (ins) {
             {
                 Timed tm(prof, st, SF_K_SNAPSHOT, cnt);
                 if constexpr (kRowsPerXcd)
-                    k_entries_snapshot_rows<KB, D, G, SR><<<xg, kBlock, 0, st>>>(meta, ent_key, sr, bpre, asnap,
-                                                                                 stride);
+                    k_entries_snapshot_rows<KB, D, G, SR><<<xg, kBlock, 0, st>>>(meta, ent_key, ent_cnt, sr, bpre,
+                                                                                 asnap, stride);
                 else
-                    k_entries_snapshot<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, sr, bpre, asnap, stride);
+                    k_entries_snapshot<KB, D, G, SR><<<eg, kBlock, 0, st>>>(meta, ent_key, ent_cnt, sr, bpre, asnap,
+                                                                            stride);
             }
             {
                 Timed tm(prof, st, SF_K_FAT_ADD, cnt);

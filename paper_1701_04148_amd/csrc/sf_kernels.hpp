@@ -393,10 +393,14 @@ template <int KB, bool G> struct MergeShape {  // LDS table of the merging kerne
 };
 constexpr uint32_t kMinChunk = 2048;  // smallest kChunk of any shape
 
-// One merge chunk: a range of the partitioned keys inside one bucket.
+// One merge chunk: a range of the partitioned keys, and the buckets
+// [b_lo, b_hi) it holds whole (empty for a piece of a split bucket).
 struct MergeChunk {
-    uint32_t first, n, del;
+    uint32_t first, n, del, b_lo, b_hi;
 };
+// An insert entry whose row-0 S1 and S2 the merge took in place carries this
+// bit in its count (counts stay below 2^16).
+constexpr uint32_t kRow0Done = 0x80000000u;
 // Chunks one batch (or merged sub-round) of cap ops can have: full chunks
 // plus one partial chunk per bucket.
 __host__ __device__ constexpr uint64_t merge_chunks_max(uint64_t cap) { return cap / kMinChunk + 2 * kMaxBuckets + 1; }
@@ -753,10 +757,11 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
     for (uint32_t e = 0; e < P; e++) {
         const uint32_t b = t * P + e, del = b >= half ? 1u : 0u;
         if (sz[e] > H) {
+            const uint32_t whole = nc[e] == 1 ? b + 1 : b;  // a bucket split over chunks is held whole by none
             for (uint32_t q = 0; q < nc[e]; q++)
-                chunks[c0 + q] = MergeChunk{st[b] + q * K, min(K, sz[e] - q * K), del};
+                chunks[c0 + q] = MergeChunk{st[b] + q * K, min(K, sz[e] - q * K), del, b, whole};
         } else if (nc[e]) {
-            chunks[c0] = MergeChunk{st[b], st[nxt[e]] - st[b], del};
+            chunks[c0] = MergeChunk{st[b], st[nxt[e]] - st[b], del, b, nxt[e]};
         }
         c0 += nc[e];
         meta->chunk0[b + 1] = c0;
@@ -847,15 +852,25 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
     }
 }
 
-// Merges one chunk of one bucket and emits its entries (key, count).
-// cap = entry capacity (insert entries at [0, n_ins), delete entries at
-// [cap - n_del, cap)).
-template <int KB, bool G>
+// Merges one chunk and emits its entries (key, count).  cap = entry capacity
+// (insert entries at [0, n_ins), delete entries at [cap - n_del, cap)).
+//
+// A lone sketch's bucket is a range of row-0 cells, so an insert chunk that
+// holds its buckets whole is the only workgroup of the batch touching their
+// row-0 records.  If their Fat counters fit the LDS table and its entries
+// are at least one per 8 of those counters, the chunk takes row 0's S1
+// (snapshot) and S2 (Fat +) in place: it reads the snapshot of
+// its entries, then, after a barrier, sums their counts per counter in LDS
+// and adds the sums with plain stores.  Its entries carry kRow0Done, and the
+// entry kernels skip row 0 for them.
+template <int KB, bool G, class SR>
 __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const MKey<KB, G>* __restrict__ part,
                                                   MergeMeta* __restrict__ meta,
                                                   const MergeChunk* __restrict__ chunks,
                                                   MKey<KB, G>* __restrict__ ent_key,
-                                                  uint32_t* __restrict__ ent_cnt, uint32_t cap, uint32_t nb_log2) {
+                                                  uint32_t* __restrict__ ent_cnt, uint32_t cap, uint32_t nb_log2,
+                                                  SR sr, uint32_t* __restrict__ bpre,
+                                                  uint16_t* __restrict__ asnap) {
     constexpr int J = MergeShape<KB, G>::J;
     constexpr uint32_t kThreads = MergeShape<KB, G>::kThreads;
     constexpr uint32_t kSlots = MergeShape<KB, G>::kSlots;
@@ -867,6 +882,17 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
     const MergeChunk ck = chunks[c];
     const bool del = ck.del != 0;
     const uint32_t first = ck.first, n = ck.n;
+    bool inplace = false;                         // row 0's S1 and S2 taken here (same for the workgroup)
+    uint32_t lo = 0, ncnt = 0;                    // first row-0 cell of the chunk's buckets, their Fat counters
+    SketchDesc sd{};
+    if constexpr (!G) {
+        sd = sr.of(0u);
+        const uint64_t w = sd.g.w, round = (1ull << nb_log2) - 1;
+        lo = uint32_t((uint64_t(ck.b_lo) * w + round) >> nb_log2);  // bucket b: cells with h * nb / w = b
+        const uint32_t hi = uint32_t((uint64_t(ck.b_hi) * w + round) >> nb_log2);
+        ncnt = (hi - lo) * sd.g.z;
+        inplace = !del && ck.b_hi > ck.b_lo && uint64_t(hi - lo) * sd.g.z <= kSlots;
+    }
     // about two slots per key (at least one per thread): a small chunk clears
     // and probes a small table
     const uint32_t slots = min(kSlots, max(kThreads, 2 * n));
@@ -907,15 +933,44 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
     wbase = __shfl(wbase, 63);
     __syncthreads();                              // every count final, nloc complete
     if (threadIdx.x == 0) base = atomicAdd(del ? &meta->n_del : &meta->n_ins, nloc);
+    // in place only where the entries are dense enough to repay clearing and
+    // scanning the per-counter table (at least one per 8 counters)
+    inplace = inplace && uint64_t(nloc) * 8 >= ncnt;
     __syncthreads();
     uint32_t rank = base + wbase + incl - mine;
+    uint32_t eid[J], ecnt[J];
 #pragma unroll
     for (int j = 0; j < J; j++) {
         if (made[j] == kEmpty) continue;
         const uint32_t id = del ? cap - 1 - rank : rank;
         rank++;
+        eid[j] = id;
+        ecnt[j] = L.slot[made[j]] & 0xffffu;
         ent_key[id] = k[j];
-        ent_cnt[id] = L.slot[made[j]] & 0xffffu;
+        ent_cnt[id] = ecnt[j] | (inplace ? kRow0Done : 0u);
+    }
+    if constexpr (!G) {
+        if (inplace) {
+            const uint32_t z = sd.g.z;
+            __syncthreads();                      // every count has been read from the table
+            for (uint32_t i = threadIdx.x; i < ncnt; i += kThreads) L.slot[i] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; j++) {
+                if (made[j] == kEmpty) continue;
+                uint32_t h, f;
+                split(sd.g, Mixed<KB>(k[j].k).row(sd.g.seed_base), h, f);
+                const uint32_t* rec = sd.fat + size_t(h) * sd.g.rs;  // row 0
+                asnap[eid[j]] = uint16_t(rec[z]);
+                bpre[eid[j]] = rec[f];
+                atomicAdd(&L.slot[(h - lo) * z + f], ecnt[j]);
+            }
+            __syncthreads();                      // every snapshot read before a counter moves
+            for (uint32_t i = threadIdx.x; i < ncnt; i += kThreads) {
+                const uint32_t v = L.slot[i];
+                if (v) sd.fat[size_t(lo + i / z) * sd.g.rs + i % z] += v;
+            }
+        }
     }
 }
 
@@ -934,7 +989,8 @@ struct SketchTable {
 // S1 over merged insert entries: Slim and Fat counters before the batch.
 template <int KB, int D, bool G, class SR>
 __global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __restrict__ meta,
-                                                             const MKey<KB, G>* __restrict__ ent_key, SR sr,
+                                                             const MKey<KB, G>* __restrict__ ent_key,
+                                                             const uint32_t* __restrict__ ent_cnt, SR sr,
                                                              uint32_t* __restrict__ bpre,
                                                              uint16_t* __restrict__ asnap, uint32_t stride) {
     constexpr int R = D ? D : kMaxD;
@@ -943,11 +999,12 @@ __global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __
         const MKey<KB, G> m = ent_key[e];
         const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
         const uint32_t d = SF_ROWS(D, sd.g);
+        const uint32_t i0 = ent_cnt[e] & kRow0Done ? 1u : 0u;  // row 0 taken by the merge
         const Mixed<KB> mx(m.k);
         uint32_t av[R], bv[R];
 #pragma unroll
         for (int i = 0; i < R; i++) {
-            if (uint32_t(i) < d) {
+            if (uint32_t(i) < d && uint32_t(i) >= i0) {
                 uint32_t h, f;
                 split(sd.g, mx.row(sd.g.seed_base + i), h, f);
                 const size_t cell = size_t(i) * sd.g.w + h;
@@ -957,7 +1014,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __
         }
 #pragma unroll
         for (int i = 0; i < R; i++) {
-            if (uint32_t(i) < d) {
+            if (uint32_t(i) < d && uint32_t(i) >= i0) {
                 asnap[size_t(i) * stride + e] = uint16_t(av[i]);
                 bpre[size_t(i) * stride + e] = bv[i];
             }
@@ -975,14 +1032,16 @@ __global__ __launch_bounds__(kBlock) void k_entries_fat(MergeMeta* __restrict__ 
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(del ? &meta->acc_del : &meta->acc_ins, (unsigned long long)n);
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
         const uint32_t id = del ? cap - 1 - e : e;
-        const uint32_t v = del ? 0u - ent_cnt[id] : ent_cnt[id];
+        const uint32_t raw = ent_cnt[id], cnt = raw & ~kRow0Done;
+        const uint32_t v = del ? 0u - cnt : cnt;
+        const uint32_t i0 = raw & kRow0Done ? 1u : 0u;  // row 0 added by the merge
         const MKey<KB, G> m = ent_key[id];
         const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
         const uint32_t d = SF_ROWS(D, sd.g);
         const Mixed<KB> mx(m.k);
 #pragma unroll
         for (uint32_t i = 0; i < uint32_t(D ? D : kMaxD); i++) {
-            if (i < d) {
+            if (i < d && i >= i0) {
                 uint32_t h, f;
                 split(sd.g, mx.row(sd.g.seed_base + i), h, f);
                 atomic_add_u32(&sd.fat[(size_t(i) * sd.g.w + h) * sd.g.rs + f], v);
@@ -1078,12 +1137,14 @@ struct XcdRow {
 
 template <int KB, int D, bool G, class SR>
 __global__ __launch_bounds__(kBlock) void k_entries_snapshot_rows(const MergeMeta* __restrict__ meta,
-                                                                  const MKey<KB, G>* __restrict__ ent_key, SR sr,
+                                                                  const MKey<KB, G>* __restrict__ ent_key,
+                                                                  const uint32_t* __restrict__ ent_cnt, SR sr,
                                                                   uint32_t* __restrict__ bpre,
                                                                   uint16_t* __restrict__ asnap, uint32_t stride) {
     const XcdRow xr = XcdRow::of<D>();
     const uint32_t n = meta->n_ins;
     for (uint32_t e = xr.slot * kBlock + threadIdx.x; e < n; e += xr.nslots * kBlock) {
+        if (xr.r == 0 && (ent_cnt[e] & kRow0Done)) continue;  // row 0 taken by the merge
         const MKey<KB, G> m = ent_key[e];
         const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
         uint32_t h, f;

@@ -55,7 +55,7 @@ def test_footprint_and_budget():
     # cell records (z Fat counters + Slim), export staging (dense Fat), dense uint16 Slim
     # copy for queries, snapshots, merge buffers
     hist = (b // 8192 + 1) * 2048 * 4      # per-partition-group bucket histograms (2 x 1024 buckets)
-    chunks = (b // 2048 + 2 * 1024 + 1) * 12   # every merge chunk's key range
+    chunks = (b // 2048 + 2 * 1024 + 1) * 20   # every merge chunk: key range, whole buckets
     meta = 4 * (2 * 1024 + 1) * 4 + 3 * 256     # per-bucket totals, starts, sizes, chunk prefix; counters
     need = cells * 5 * 4 + cells * 4 * 4 + cells * 2 + 4 * b * 6 + merge + hist + chunks
     assert fp >= need
