@@ -31,6 +31,8 @@ METRIC = "Minsert+query items/s per GPU (1 vs 1024 sketches); p50/p99 served lat
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
+from paper_1701_04148_amd.tune import batch_for_width  # noqa: E402  (the b rule, shared with the tests)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -229,19 +231,6 @@ def micro_ceilings(torch, sizes_mib=(1, 16, 64, 256, 4096), n=1 << 26):
         del t
         torch.cuda.empty_cache()
     return out
-
-
-BATCH_CAP = 1 << 23
-
-
-def batch_for_width(w: int) -> int:
-    """Schedule batch size per sketch width: b = min(16 w, 2^23).  The oracle measurements
-    behind it (ARE vs truth of the batch schedule against sequential SF_F), with the
-    tolerance ARE <= 1.10 x seq + 1e-3: on the 1M-insert workload (w = 2^14) b = 16 w drifts
-    3.8% (within) and b = 64 w 17% (outside); on the 32M-op workload (w = 2^20) b = 2^23
-    drifts 7.4% / 2.1% / 10% of a tiny ARE at Zipf 0.6 / 1.0 / 1.4, while b = 2^24 drifts 13%
-    at Zipf 0.6 (within only through the absolute term), hence the cap 2^23."""
-    return int(min(16 * w, BATCH_CAP))
 
 
 def run_multi(args, torch, np, sf, sfgen):

@@ -26,6 +26,18 @@ import numpy as np
 from . import Sketch
 
 SLIM_MAX = 65535
+BATCH_CAP = 1 << 23
+
+
+def batch_for_width(w: int) -> int:
+    """Default schedule batch size for a sketch of Slim width w: b = min(16 w, 2^23).
+    It comes from the oracle's ARE of the batch schedule against sequential SF_F on
+    the benchmark workloads under the tolerance ARE <= 1.10 x ARE_seq + 1e-3
+    (``python -m oracle.accuracy`` prints the table): on the 1M-insert workload
+    (w = 2^14) b = 16 w is within it and 64 w is not; on the 32M-op workload
+    (w = 2^20) 2^23 is within it at every skew, 2^24 at Zipf 0.6 only through the
+    absolute term, hence the cap."""
+    return int(min(16 * w, BATCH_CAP))
 
 
 def exact_counts(keys: np.ndarray, ops: np.ndarray | None, queries: np.ndarray) -> np.ndarray:
