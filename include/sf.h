@@ -129,10 +129,34 @@ int sf_update_host(sf_sketch *sk, const void *host_keys, const uint8_t *host_ops
  * minimum. */
 int sf_query(sf_sketch *sk, const void *keys, uint64_t n, uint32_t *out);
 
-/* Collector-side point query over an exported Slim (slim: device pointer to
- * [d][w] uint16, row-major) without a sketch; runs on hip_stream. */
+/* Collector-side point query (Section 3.1 query rule) over an exported Slim
+ * (Sections 1 and 3: the collector holds only the Slim): slim is a device
+ * pointer to [d][w] uint16, row-major; keys and out as in sf_query; runs on
+ * hip_stream (NULL = the null stream).  cfg.batch_ops is ignored.  A Slim
+ * larger than 4 MiB with d dividing 8 is read one row per XCD, as sf_query
+ * does after an export: per-row counters of runs of keys go to scratch the
+ * call allocates stream-ordered (hipMallocAsync / hipFreeAsync on
+ * hip_stream); smaller Slims take one pass with no scratch.  Errors:
+ * SF_EINVAL (bad config or pointers, buffers too small), SF_ENOMEM (no
+ * scratch), SF_EDEVICE. */
 int sf_query_slim(const uint16_t *slim, const sf_config *cfg, const void *keys, uint64_t n,
                   uint32_t *out, void *hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): sf_query_slim
+ * with the same kernels and the same answers, but the per-row counters live
+ * in a static device array of SF_NOALLOC_QUERY_COUNTERS uint16 (16 MiB) that
+ * every GPU the library runs on holds until the process ends; the call makes
+ * no allocation of any kind.  Limit: n * d <= SF_NOALLOC_QUERY_COUNTERS
+ * (e.g. 2M keys at d = 4), whichever path the Slim takes; larger n is
+ * rejected with SF_EINVAL before any device work -- split the keys over
+ * several calls.  All calls on one GPU share the array: calls that overlap
+ * on one GPU (two streams, or two host threads) race and may return wrong
+ * answers; calls ordered on one stream are safe.  Other errors as
+ * sf_query_slim. */
+#define SF_NOALLOC_QUERY_COUNTERS (1u << 23)
+int sf_query_slim_noalloc(const uint16_t *slim, const sf_config *cfg, const void *keys, uint64_t n,
+                          uint32_t *out, void *hip_stream);
 
 /* Slim export, the structure sent to the collector (Sections 1 and 3): d*w
  * uint16 counters, row-major [d][w].  out may be host or device memory with

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libsf.so")
 
 SF_OK, SF_EINVAL, SF_ENOMEM, SF_EDEVICE, SF_ESTATE, SF_EUNDERFLOW = 0, -1, -2, -3, -4, -5
 SLIM_MAX = 65535
+NOALLOC_QUERY_COUNTERS = 1 << 23  # SF_NOALLOC_QUERY_COUNTERS of sf.h
 
 _lib = None
 
@@ -58,6 +59,7 @@ SIGNATURES = {
     "sf_update": (_I, [_P, _P, _P, _U64]),
     "sf_query": (_I, [_P, _P, _U64, _P]),
     "sf_query_slim": (_I, [_P, _CFG, _P, _U64, _P, _P]),
+    "sf_query_slim_noalloc": (_I, [_P, _CFG, _P, _U64, _P, _P]),
     "sf_export_slim": (_I, [_P, _P, _U64]),
     "sf_export_fat": (_I, [_P, _P, _U64]),
     "sf_sync": (_I, [_P]),
@@ -216,6 +218,16 @@ def sf_query_slim(slim, cfg: sf_config, keys, out, stream=None):
         raise ValueError("out must be a GPU 4-byte tensor with one element per key")
     _check(lib().sf_query_slim(slim.data_ptr(), ctypes.byref(cfg), p, n, out.data_ptr(),
                                _stream_handle(stream)), "sf_query_slim")
+
+
+def sf_query_slim_noalloc(slim, cfg: sf_config, keys, out, stream=None):
+    """sf_query_slim without any allocation: per-row counters in the library's
+    static device array (n * d <= NOALLOC_QUERY_COUNTERS)."""
+    p, n = _keys_ptr(keys, cfg.key_bytes)
+    if out.numel() < n or out.element_size() != 4 or not out.is_cuda:
+        raise ValueError("out must be a GPU 4-byte tensor with one element per key")
+    _check(lib().sf_query_slim_noalloc(slim.data_ptr(), ctypes.byref(cfg), p, n, out.data_ptr(),
+                                       _stream_handle(stream)), "sf_query_slim_noalloc")
 
 
 def sf_export_slim(h, out):

@@ -22,6 +22,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_set>
+#include <vector>
 
 #include "sf.h"
 #include "sf_host.hpp"
@@ -215,6 +216,53 @@ int query_common(Profiler* prof, const sf_config* c, const Geom& g, const void* 
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SF_OK : device_fail(e, "query launch");
+}
+
+// Collector-side queries read a dense uint16 Slim one row per XCD (as
+// sf_query does after an export) once it outgrows an XCD's 4 MB L2.
+bool slim_by_rows(const sf_config& c) { return kXcds % c.d == 0 && uint64_t(c.d) * c.w * 2 > (4ull << 20); }
+
+// Per-row counters one sf_query_slim run keeps in its stream-ordered scratch.
+constexpr uint64_t kSlimQueryRunBytes = 32ull << 20;
+
+int slim_query_checks(const uint16_t* slim, const sf_config* cfg, const void* keys, uint64_t n, uint32_t* out,
+                      sf_config* c) {
+    if (!cfg) return fail(SF_EINVAL, "null config");
+    *c = *cfg;
+    c->batch_ops = 1;  // not used by queries
+    int rc = validate(c);
+    if (rc || n == 0) return rc;
+    if ((rc = check_gpu_ptr(slim, uint64_t(c->d) * c->w * 2, "slim"))) return rc;
+    return query_checks(c, keys, n, out);
+}
+
+// Scratch of sf_query_slim_noalloc: the per-row counters of its one-row-per-
+// XCD query.  Every GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` only names the symbol; kernels get
+// the device address that hipGetSymbolAddress returns for the current
+// device, looked up once per device and kept in g_scratch.
+__device__ __align__(256) uint16_t scratch[SF_NOALLOC_QUERY_COUNTERS];
+
+std::mutex g_scratch_mu;
+std::vector<uint16_t*> g_scratch;  // per device ordinal; null until looked up
+
+int noalloc_scratch(uint16_t** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "sf_query_slim_noalloc device");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch.size() <= size_t(dev)) g_scratch.resize(size_t(dev) + 1, nullptr);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return device_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "sf_query_slim_noalloc scratch address");
+        }
+        g_scratch[dev] = static_cast<uint16_t*>(p);
+    }
+    *out = g_scratch[dev];
+    return SF_OK;
 }
 
 }  // namespace
@@ -417,13 +465,41 @@ int sf_query(sf_sketch* s, const void* keys, uint64_t n, uint32_t* out) {
 
 int sf_query_slim(const uint16_t* slim, const sf_config* cfg, const void* keys, uint64_t n, uint32_t* out,
                   void* hip_stream) {
-    sf_config c = cfg ? *cfg : sf_config{};
-    if (cfg) c.batch_ops = 1;  // not used by queries
-    int rc = validate(cfg ? &c : nullptr);
+    sf_config c{};
+    int rc = slim_query_checks(slim, cfg, keys, n, out, &c);
+    if (rc || n == 0) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (!slim_by_rows(c)) return query_common(nullptr, &c, geom_of(&c), slim, true, keys, n, out, st);
+    // per-row counters of a run of keys, in stream-ordered scratch freed behind the run
+    const uint64_t run = std::min<uint64_t>(n, kSlimQueryRunBytes / (2ull * c.d));
+    void* part = nullptr;
+    hipError_t e = hipMallocAsync(&part, run * c.d * 2, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? fail(SF_ENOMEM, "sf_query_slim scratch") : device_fail(e, "sf_query_slim scratch");
+    }
+    rc = query_by_rows(nullptr, &c, geom_of(&c), slim, static_cast<const uint8_t*>(keys), n, out,
+                       static_cast<uint16_t*>(part), run * c.d * 2, st);
+    e = hipFreeAsync(part, st);
     if (rc) return rc;
-    if (n && (rc = check_gpu_ptr(slim, uint64_t(c.d) * c.w * 2, "slim"))) return rc;
-    return query_common(nullptr, &c, geom_of(&c), slim, true, keys, n, out,
-                        static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? SF_OK : device_fail(e, "sf_query_slim scratch free");
+}
+
+int sf_query_slim_noalloc(const uint16_t* slim, const sf_config* cfg, const void* keys, uint64_t n, uint32_t* out,
+                          void* hip_stream) {
+    sf_config c{};
+    int rc = slim_query_checks(slim, cfg, keys, n, out, &c);
+    if (rc || n == 0) return rc;
+    if (n * c.d > SF_NOALLOC_QUERY_COUNTERS)
+        return fail(SF_EINVAL, "sf_query_slim_noalloc: n * d = " + std::to_string(n * c.d) +
+                                   " per-row counters exceed its static scratch of " +
+                                   std::to_string(SF_NOALLOC_QUERY_COUNTERS) + "; split the keys over several calls");
+    uint16_t* part = nullptr;
+    if ((rc = noalloc_scratch(&part))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (!slim_by_rows(c)) return query_common(nullptr, &c, geom_of(&c), slim, true, keys, n, out, st);
+    return query_by_rows(nullptr, &c, geom_of(&c), slim, static_cast<const uint8_t*>(keys), n, out, part,
+                         uint64_t(SF_NOALLOC_QUERY_COUNTERS) * 2, st);
 }
 
 int sf_export_slim(sf_sketch* s, uint16_t* out, uint64_t out_elems) {
