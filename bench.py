@@ -217,7 +217,8 @@ def micro_ceilings(torch, sizes_mib=(1, 16, 64, 256, 4096), n=1 << 26):
                          ("atomic_add_u32", lambda s: micro.atomic_add_u32(t, n, s)),
                          ("gather_16b", lambda s: micro.gather_16b(t, n, s, sink)),
                          ("pair_same_line", lambda s: micro.gather_pair(t, n, s, True, sink)),
-                         ("pair_two_lines", lambda s: micro.gather_pair(t, n, s, False, sink))):
+                         ("pair_two_lines", lambda s: micro.gather_pair(t, n, s, False, sink)),
+                         ("scatter_u64", lambda s: micro.scatter_u64(t.view(torch.int64), n, s))):
             fn(1)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -178,13 +178,24 @@ int sf_sync(sf_sketch *sk);
  * ignores it. */
 int sf_set_tile(sf_sketch *sk, uint32_t tile_ops);
 
-/* Where duplicate keys are merged before they reach a counter: 1 = across
- * the whole batch (the default: keys are first partitioned into hash
- * buckets, then merged per chunk of whole buckets -- a large bucket spans
- * several chunks -- and S1..S5 run once per merged key), 0 = per tile of
- * consecutive ops.  Results are identical; the batch-wide merge issues far
- * fewer atomics and random reads. */
+/* Where duplicate keys are merged before they reach a counter, and how the
+ * merged keys reach the counters.  1 (the default) and 2 merge across the
+ * whole batch: keys are first partitioned into hash buckets, then merged per
+ * chunk of whole buckets (a large bucket spans several chunks), and S1..S5
+ * run once per merged key.  With 1, where the shape allows it (a range of
+ * 2^k >= 16 cells, at most 1024 ranges per row and at most 8192 / d, holds
+ * at most 8192 Fat counters), each (row, cell range) has one owning
+ * workgroup per step that applies S1..S5 to its records with LDS sums and
+ * plain stores; other shapes, and mode 2, use one device-scope atomic per
+ * merged key and row.  0 merges per tile of consecutive ops.  Results are
+ * identical in every mode (Section 3.4 insertion and Section 3.5 deletion
+ * are sums, maxima and minima per counter).  SF_EINVAL for other values. */
 int sf_set_merge(sf_sketch *sk, int batch_wide);
+
+/* The path sf_update takes now: 0 per-tile merging, 1 batch-wide merge with
+ * owner-computes S1..S5, 2 batch-wide merge with atomic S1..S5; negative on
+ * error. */
+int sf_merge_path(sf_sketch *sk);
 
 /* Merged entries (distinct keys per merge chunk) the batch-wide merge has
  * emitted since sf_create, for inserts and deletes; waits for the stream. */
@@ -206,7 +217,11 @@ enum sf_kernel_kind {
     SF_K_EXPORT = 6,
     SF_K_MERGE = 7,    /* batch-wide merge: merge per chunk of bucketed keys */
     SF_K_PARTITION = 8,/* batch-wide merge: bucket counts, starts, scatter */
-    SF_K_COUNT = 10
+    SF_K_PAIRS = 9,    /* owner path: (entry, row) pairs partitioned by (row, cell range) */
+    SF_K_OWN_STEP = 10,/* owner path: per (row, cell range), S3..S5 of the previous batch, S1 + S2 of this one */
+    SF_K_LEVEL = 11,   /* owner path: S3's level T per inserted key */
+    SF_K_OWN_FINAL = 12,  /* owner path: S3..S5 of an update call's last batch */
+    SF_K_COUNT = 16
 };
 
 typedef struct sf_kernel_stats {

@@ -47,6 +47,10 @@ int micro_atomic_add_xcd(uint32_t *table, uint64_t elems, uint64_t n, uint32_t s
 int micro_gather_pair(const uint32_t *table, uint64_t elems, uint64_t n, uint32_t seed,
                       uint32_t same_line, uint32_t *sink, void *hip_stream);
 
+/* n random 8-byte stores into table[0 .. elems) (elems a power of two,
+ * counted in uint64): the rate of writing items out in another order. */
+int micro_scatter_u64(uint64_t *table, uint64_t elems, uint64_t n, uint32_t seed, void *hip_stream);
+
 /* XCDs (XCCs) of the current device, or -3 on error. */
 int micro_num_xcc(void);
 

@@ -36,8 +36,8 @@ class sf_config(ctypes.Structure):
 
 
 KERNEL_KINDS = ("snapshot", "fat_add", "raise", "fat_sub", "clamp", "query", "export", "merge",
-                "partition")
-SF_K_COUNT = 10
+                "partition", "pairs", "own_step", "level", "own_final")
+SF_K_COUNT = 16
 
 
 class sf_kernel_stats(ctypes.Structure):
@@ -65,6 +65,7 @@ SIGNATURES = {
     "sf_sync": (_I, [_P]),
     "sf_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_set_merge": (_I, [_P, _I]),
+    "sf_merge_path": (_I, [_P]),
     "sf_update_host": (_I, [_P, _P, _P, _U64, _U64]),
     "sf_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_profile": (_I, [_P, _I]),
@@ -350,9 +351,19 @@ class Sketch:
         _check(lib().sf_merge_stats(self._h, ctypes.byref(a), ctypes.byref(b)), "sf_merge_stats")
         return int(a.value), int(b.value)
 
-    def set_merge(self, batch_wide: bool):
-        """Merge duplicate keys across the whole batch (True, the default) or per tile (False)."""
-        _check(lib().sf_set_merge(self._h, int(bool(batch_wide))), "sf_set_merge")
+    def set_merge(self, batch_wide):
+        """Merge duplicate keys across the whole batch (True / 1, the default: owner-computes
+        S1..S5 where the shape allows), per tile (False / 0), or across the batch with atomic
+        S1..S5 (2)."""
+        mode = int(batch_wide) if not isinstance(batch_wide, bool) else int(batch_wide)
+        _check(lib().sf_set_merge(self._h, mode), "sf_set_merge")
+
+    def merge_path(self) -> int:
+        """0 per-tile merging, 1 batch-wide merge + owner-computes S1..S5, 2 batch-wide + atomics."""
+        rc = lib().sf_merge_path(self._h)
+        if rc < 0:
+            _check(rc, "sf_merge_path")
+        return rc
 
     def profile(self, enable: bool = True):
         sf_profile(self._h, enable)

@@ -5,11 +5,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
 #include "sf.h"
-#include "sf_kernels.hpp"
+#include "sf_owner.hpp"
 
 namespace sfh {
 
@@ -200,6 +201,59 @@ void launch_steps(const P& plan, unsigned tiles, bool ins, bool del, uint32_t* b
     }
 }
 
+// Layout of the owner-computes path for a sketch shape: ranges of 2^cr_shift
+// cells (at least 16) so that a row has at most kMaxRanges of them and the
+// columns of both op types fit kMaxCols; the shape qualifies when a range's
+// Fat counters fit the owners' LDS and a pair's 16-bit local code.
+inline bool owner_geom(const sf_config* c, OwnerGeom* og) {
+    const uint32_t rmax = std::min<uint32_t>(kMaxRanges, kMaxCols / (2 * c->d));
+    uint32_t zbits = 0;
+    while ((1ull << zbits) < c->z) zbits++;
+    uint32_t sh = 4;
+    while (((uint64_t(c->w) + (1ull << sh) - 1) >> sh) > rmax) sh++;
+    const uint64_t cr = 1ull << sh;
+    if (cr * c->z > kOwnCounters || (cr << zbits) > 65536) return false;
+    og->R = uint32_t((uint64_t(c->w) + cr - 1) >> sh);
+    og->cr_shift = sh;
+    og->zbits = zbits;
+    og->ncol = 2 * c->d * og->R;
+    og->xcd = (kXcds % c->d == 0 && (c->d * og->R) % kXcds == 0) ? 1u : 0u;
+    return true;
+}
+
+// Device buffers of the owner-computes path (cap = entry capacity = b).  A
+// batch's S3..S5 run in the owner step of the next batch of the same update
+// call (or in a closing step), so the pairs and column starts of two batches
+// are alive at once: set `cur` takes the next batch, set cur ^ 1 holds the
+// batch whose S3..S5 are pending.
+struct OwnerBufs {
+    OwnerGeom og;
+    uint64_t* pairs[2];  // [d * cap] pairs, in column order
+    PairMeta* pm[2];
+    uint32_t* pos;       // [d][cap] position of each insert entry's pair per row
+    uint64_t* res;       // [d * cap] per insert pair: Slim before, growth, Fat after (16 bits each)
+    uint16_t* level;     // [cap] T of each insert entry
+    uint32_t* hmat;      // [pair_tiles_max(cap)][ncol] per-tile column counts, then offsets
+    uint32_t cur = 0;
+    bool pending = false;
+};
+
+// LDS of one owner step: the range's records.
+inline size_t own_step_lds(const Geom& g, const OwnerGeom& og) {
+    return (size_t(1) << og.cr_shift) * g.rs * 4;
+}
+
+// The closing owner step of an update call: S3..S5 of its last batch.
+template <int D>
+void owner_close(OwnerBufs* own, const Geom& g, uint32_t* fat, hipStream_t st, Profiler* prof) {
+    if (!own->pending) return;
+    const uint32_t prev = own->cur ^ 1u;
+    Timed tm(prof, st, SF_K_OWN_FINAL, 0);
+    k_own_step<D><<<g.d * own->og.R, kOwnThreads, own_step_lds(g, own->og), st>>>(
+        g, own->og, fat, own->pm[prev], own->pairs[prev], own->level, nullptr, nullptr, own->res);
+    own->pending = false;
+}
+
 // Dispatch of (key width, rows, tile) to kernel instantiations.
 // The batch-merge path of one schedule batch (or round): partition the ops
 // into hash buckets, merge each bucket chunk in LDS into entries, then S1..S5
@@ -216,6 +270,10 @@ struct MergeRun {
     uint32_t* bpre;        // [d][stride] S1 snapshot of Fat counters, per insert entry
     uint16_t* asnap;       // [d][stride] S1 snapshot of Slim counters, per insert entry
     uint32_t stride;
+    OwnerBufs* own = nullptr;  // lone sketch: S1..S5 by (row, cell range) owners
+
+    template <int D, class SR>
+    void launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st, Profiler* prof) const;
 
     // part_groups: workgroups of the partition kernels (plan tiles of at most
     // kPartOps ops); cnt: ops in the batch (<= cap).
@@ -248,7 +306,14 @@ struct MergeRun {
         {
             Timed tm(prof, st, SF_K_MERGE, cnt);
             k_merge<KB, G, SR><<<blocks_for(cnt, MergeShape<KB, G>::kChunk) + 2 * nb, MergeShape<KB, G>::kThreads, 0,
-                                 st>>>(part, meta, chunks, ent_key, ent_cnt, cap, nb_log2, sr, bpre, asnap);
+                                 st>>>(part, meta, chunks, ent_key, ent_cnt, cap, nb_log2, sr, bpre, asnap,
+                                       own ? 0u : 1u);
+        }
+        if constexpr (!G) {
+            if (own) {
+                launch_owner<D>(cnt, sr, ins, del, st, prof);
+                return;
+            }
         }
         if (ins) {
             {
@@ -281,6 +346,38 @@ struct MergeRun {
         }
     }
 };
+
+template <int KB, bool G>
+template <int D, class SR>
+void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st,
+                                   Profiler* prof) const {
+    const OwnerGeom& og = own->og;
+    const unsigned tiles = pair_tiles_max(cnt);
+    const unsigned owners = sr.g.d * og.R;
+    const uint32_t set = own->cur, prev = set ^ 1u;
+    {
+        Timed tm(prof, st, SF_K_PAIRS, cnt);
+        k_pair_count<KB, D><<<dim3(tiles, sr.g.d), kCountThreads, 0, st>>>(meta, ent_key, cap, sr.g, og, own->hmat);
+        k_pair_colscan<><<<blocks_for(og.ncol, kScanCols), kScanCols * kScanWaves, 0, st>>>(own->hmat, meta,
+                                                                                          own->pm[set], og.ncol);
+        k_pair_start<><<<1, 1024, 0, st>>>(own->pm[set], og.ncol, meta);
+        k_pair_scatter<KB, D><<<dim3(tiles, sr.g.d), kPairThreads, 0, st>>>(
+            meta, ent_key, ent_cnt, cap, sr.g, og, own->hmat, own->pm[set], own->pairs[set], own->pos, cap);
+    }
+    {
+        Timed tm(prof, st, SF_K_OWN_STEP, cnt);
+        k_own_step<D><<<owners, kOwnThreads, own_step_lds(sr.g, og), st>>>(
+            sr.g, og, sr.fat, own->pending ? own->pm[prev] : nullptr, own->pending ? own->pairs[prev] : nullptr,
+            own->level, ins ? own->pm[set] : nullptr, ins ? own->pairs[set] : nullptr, own->res);
+    }
+    if (ins) {
+        Timed tm(prof, st, SF_K_LEVEL, cnt);
+        k_level<D><<<tiles, kPairThreads, 0, st>>>(meta, own->pos, cap, own->res, sr.g.d, own->level);
+    }
+    own->pending = true;  // this batch's S3..S5 (raise, deletes, clamp) come next
+    own->cur = prev;
+    (void)del;
+}
 
 template <template <int> class PT>
 struct Steps {

@@ -581,8 +581,8 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* _
 // sum and the prefix pass; longer ones are read twice.
 constexpr uint32_t kScanCols = 64, kScanWaves = 16, kScanRowsReg = 64;
 template <typename T>
-__global__ __launch_bounds__(kScanCols * kScanWaves) void k_part_colscan(
-    T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
+__device__ __forceinline__ void colscan_wide(T* __restrict__ hist, uint32_t groups, uint32_t nbt,
+                                             uint32_t* __restrict__ totals) {
     __shared__ T seg_sum[kScanWaves][kScanCols];
     const uint32_t lane = lane_id(), wv = threadIdx.x / 64;
     const uint32_t b = blockIdx.x * kScanCols + lane;
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(kScanCols * kScanWaves) void k_part_colscan(
             seg_sum[w][lane] = run;
             run += x;
         }
-        if (b < nbt) meta->total[b] = run;
+        if (b < nbt) totals[b] = run;
     }
     __syncthreads();
     T run = seg_sum[wv][lane];                    // keys of this bucket in earlier segments
@@ -633,14 +633,20 @@ __global__ __launch_bounds__(kScanCols * kScanWaves) void k_part_colscan(
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kScanCols * kScanWaves) void k_part_colscan(
+    T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
+    colscan_wide<T>(hist, groups, nbt, meta->total);
+}
+
 // The same for other shapes -- a tall matrix (more than kScanWaves *
 // kScanRowsReg groups, as in sketch groups and pools) or a short one (a small
 // batch): 4 buckets per workgroup and the groups split into 64 segments, so
 // that many workgroups share the rows.
 constexpr uint32_t kScanBuckets = 4, kScanSegs = 64;
 template <typename T>
-__global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan_tall(
-    T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
+__device__ __forceinline__ void colscan_tall(T* __restrict__ hist, uint32_t groups, uint32_t nbt,
+                                             uint32_t* __restrict__ totals) {
     constexpr uint32_t kRowsReg = 16;             // a segment's rows kept in registers when it has few
     __shared__ T seg_sum[kScanSegs][kScanBuckets];
     const uint32_t lb = threadIdx.x % kScanBuckets, sg = threadIdx.x / kScanBuckets;
@@ -684,8 +690,13 @@ __global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan_tall(
                 run += x;
             }
         }
-        if (sg == kScanSegs - 1) meta->total[b] = run;
+        if (sg == kScanSegs - 1) totals[b] = run;
     }
+}
+template <typename T>
+__global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan_tall(
+    T* __restrict__ hist, uint32_t groups, uint32_t nbt, MergeMeta* __restrict__ meta) {
+    colscan_tall<T>(hist, groups, nbt, meta->total);
 }
 
 // One workgroup of nbt/2 threads (thread t owns buckets 2t and 2t+1): bucket
@@ -870,7 +881,7 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
                                                   MKey<KB, G>* __restrict__ ent_key,
                                                   uint32_t* __restrict__ ent_cnt, uint32_t cap, uint32_t nb_log2,
                                                   SR sr, uint32_t* __restrict__ bpre,
-                                                  uint16_t* __restrict__ asnap) {
+                                                  uint16_t* __restrict__ asnap, uint32_t row0) {
     constexpr int J = MergeShape<KB, G>::J;
     constexpr uint32_t kThreads = MergeShape<KB, G>::kThreads;
     constexpr uint32_t kSlots = MergeShape<KB, G>::kSlots;
@@ -891,7 +902,7 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
         lo = uint32_t((uint64_t(ck.b_lo) * w + round) >> nb_log2);  // bucket b: cells with h * nb / w = b
         const uint32_t hi = uint32_t((uint64_t(ck.b_hi) * w + round) >> nb_log2);
         ncnt = (hi - lo) * sd.g.z;
-        inplace = !del && ck.b_hi > ck.b_lo && uint64_t(hi - lo) * sd.g.z <= kSlots;
+        inplace = row0 && !del && ck.b_hi > ck.b_lo && uint64_t(hi - lo) * sd.g.z <= kSlots;
     }
     // about two slots per key (at least one per thread): a small chunk clears
     // and probes a small table

@@ -59,6 +59,9 @@ struct sf_sketch {
     uint32_t* hist;   //              per-group bucket histograms     [b/8192+1][2048]
     MergeChunk* chunks;//             key range of every merge chunk
     MergeMeta* meta;
+    bool owner_ok;    // the shape fits the owner-computes path (buffers allocated)
+    bool owner_on;    // S1..S5 by (row, cell range) owners (else the entry kernels)
+    OwnerBufs own;
     Profiler prof;
     // host-fed updates (sf_update_host): two device chunk buffers (keys, then
     // op codes), their events and a copy stream, made on first use
@@ -82,8 +85,10 @@ bool live(const sf_sketch* s) {
 
 struct Sizes {
     uint64_t fat, slim, stage, view, bpre, asnap, part, ent_key, ent_cnt, meta, hist, chunks;
+    uint64_t pairs = 0, pos = 0, res = 0, level = 0, hmat = 0, pmeta = 0;  // owner path
     uint64_t total() const {
-        return fat + slim + stage + view + bpre + asnap + part + ent_key + ent_cnt + meta + hist + chunks;
+        return fat + slim + stage + view + bpre + asnap + part + ent_key + ent_cnt + meta + hist + chunks + pairs +
+               pos + res + level + hmat + pmeta;
     }
 };
 
@@ -103,6 +108,16 @@ Sizes sizes_of(const sf_config* c) {
     s.meta = round256(sizeof(MergeMeta));
     s.hist = round256(part_groups_max(c->batch_ops, 1) * 2 * kMaxBuckets * 4);
     s.chunks = round256(merge_chunks_max(c->batch_ops) * sizeof(MergeChunk));
+    OwnerGeom og;
+    if (owner_geom(c, &og)) {
+        const uint64_t b = c->batch_ops, d = c->d;
+        s.pairs = 2 * round256(d * b * 8);
+        s.pos = round256(d * b * 4);
+        s.res = round256(d * b * 8);
+        s.level = round256(b * 2);
+        s.hmat = round256(uint64_t(pair_tiles_max(uint32_t(b))) * og.ncol * 4);
+        s.pmeta = 2 * round256(sizeof(PairMeta));
+    }
     return s;
 }
 
@@ -110,7 +125,8 @@ Sizes sizes_of(const sf_config* c) {
 template <int KB, int D>
 void launch_merged(sf_sketch* s, const UniformPlan<KB>& plan, uint32_t cnt, bool ins, bool del) {
     MergeRun<KB, false> run{static_cast<MKey<KB, false>*>(s->part), static_cast<MKey<KB, false>*>(s->ent_key),
-                            s->ent_cnt, s->meta, s->hist, s->chunks, s->stride, s->bpre, s->asnap, s->stride};
+                            s->ent_cnt, s->meta, s->hist, s->chunks, s->stride, s->bpre, s->asnap, s->stride,
+                            s->owner_on ? &s->own : nullptr};
     run.template launch<D>(plan, blocks_for(cnt, kPartOps), cnt, OneSketch{s->g, s->fat, s->slim}, ins, del,
                            s->stream, &s->prof);
 }
@@ -151,6 +167,11 @@ int run_updates(sf_sketch* s, const void* keys, const uint8_t* ops, uint64_t n, 
         const uint8_t* op = kind == kMixed ? ops + lo : nullptr;
         if (kb == 4) launch_batch<4>(s, kp, op, mode, cnt, kind != kDelete, kind != kInsert);
         else launch_batch<13>(s, kp, op, mode, cnt, kind != kDelete, kind != kInsert);
+    }
+    if (s->own.pending) {  // the call's last batch: its S3..S5
+        if (s->cfg.d == 4) owner_close<4>(&s->own, s->g, s->fat, s->stream, &s->prof);
+        else if (s->cfg.d == 8) owner_close<8>(&s->own, s->g, s->fat, s->stream, &s->prof);
+        else owner_close<0>(&s->own, s->g, s->fat, s->stream, &s->prof);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SF_OK : device_fail(e, "update launch");
@@ -315,6 +336,20 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     s->meta = reinterpret_cast<MergeMeta*>(mq + sz.part + sz.ent_key + sz.ent_cnt);
     s->hist = reinterpret_cast<uint32_t*>(mq + sz.part + sz.ent_key + sz.ent_cnt + sz.meta);
     s->chunks = reinterpret_cast<MergeChunk*>(mq + sz.part + sz.ent_key + sz.ent_cnt + sz.meta + sz.hist);
+    s->owner_ok = owner_geom(cfg, &s->own.og);
+    s->owner_on = s->owner_ok;
+    if (s->owner_ok) {
+        char* ob = mq + sz.part + sz.ent_key + sz.ent_cnt + sz.meta + sz.hist + sz.chunks;
+        s->own.pairs[0] = reinterpret_cast<uint64_t*>(ob);
+        s->own.pairs[1] = reinterpret_cast<uint64_t*>(ob + sz.pairs / 2);
+        s->own.pos = reinterpret_cast<uint32_t*>(ob + sz.pairs);
+        s->own.res = reinterpret_cast<uint64_t*>(ob + sz.pairs + sz.pos);
+        s->own.level = reinterpret_cast<uint16_t*>(ob + sz.pairs + sz.pos + sz.res);
+        s->own.hmat = reinterpret_cast<uint32_t*>(ob + sz.pairs + sz.pos + sz.res + sz.level);
+        s->own.pm[0] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat);
+        s->own.pm[1] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat +
+                                                   sz.pmeta / 2);
+    }
     e = hipMemsetAsync(s->meta, 0, sizeof(MergeMeta), s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(base, 0, sz.fat + sz.slim, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -564,8 +599,15 @@ int sf_set_tile(sf_sketch* s, uint32_t tile_ops) {
 
 int sf_set_merge(sf_sketch* s, int batch_wide) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    if (batch_wide < 0 || batch_wide > 2) return fail(SF_EINVAL, "merge mode must be 0, 1 or 2");
     s->merge_batch = batch_wide != 0;
+    s->owner_on = batch_wide == 1 && s->owner_ok;
     return SF_OK;
+}
+
+int sf_merge_path(sf_sketch* s) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    return !s->merge_batch ? 0 : s->owner_on ? 1 : 2;
 }
 
 int sf_merge_stats(sf_sketch* s, uint64_t* insert_entries, uint64_t* delete_entries) {

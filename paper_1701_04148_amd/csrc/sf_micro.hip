@@ -110,6 +110,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_pair(const uint32_t* __restri
     if (acc == 0x9e3779b9u) sink[0] = acc;
 }
 
+// Random 8-byte stores (no read of the old value): the write half of a
+// transposition between two orders of the same items.
+__global__ __launch_bounds__(kBlock) void k_scatter64(uint64_t* __restrict__ t, uint64_t mask, uint64_t n,
+                                                      uint32_t seed) {
+    const uint64_t base = (uint64_t(blockIdx.x) * kBlock + threadIdx.x) * kPerThread;
+#pragma unroll
+    for (int j = 0; j < kPerThread; j++) {
+        const uint64_t a = base + j;
+        if (a < n) t[rand_index(a, seed, mask)] = a;
+    }
+}
+
 bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
 unsigned grid_of(uint64_t n) {
@@ -166,6 +178,12 @@ int micro_gather_pair(const uint32_t* t, uint64_t elems, uint64_t n, uint32_t se
     if (!t || !sink || !pow2(elems) || elems < 32 || n >= (uint64_t(1) << 40)) return -1;
     k_gather_pair<<<grid_of(n), kBlock, 0, static_cast<hipStream_t>(st)>>>(t, elems - 1, n, seed, same_line,
                                                                            sink);
+    return done();
+}
+
+int micro_scatter_u64(uint64_t* t, uint64_t elems, uint64_t n, uint32_t seed, void* st) {
+    if (!t || !pow2(elems) || n >= (uint64_t(1) << 40)) return -1;
+    k_scatter64<<<grid_of(n), kBlock, 0, static_cast<hipStream_t>(st)>>>(t, elems - 1, n, seed);
     return done();
 }
 

@@ -1,0 +1,392 @@
+// Owner-computes S1..S5 for a lone sketch on the batch-wide merge path.
+//
+// After the merge each entry (a distinct key of a merge chunk, with its
+// count) touches one cell in each of the d rows.  Instead of d random record
+// reads and d device-scope atomics per entry and step, the (entry, row) pairs
+// are partitioned by (op type, row, cell range).  Each range of 2^cr_shift
+// consecutive cells of a row has one owning workgroup per step, which is then
+// the only one reading or writing those records: it stages the range's Fat
+// buckets and Slim words in LDS, applies the step there with LDS atomics and
+// writes the range back with coalesced stores.
+//
+//   k_pair_count    per tile of entries and row: pairs per column in LDS
+//   k_pair_colscan  each tile's offset inside every column; column totals
+//   k_pair_start    column starts
+//   k_pair_scatter  per tile and row: counting sort in LDS, pairs written in
+//                   runs; for insert entries the position of the pair of
+//                   each row goes to pos[row][entry]
+//   k_own_step      per (row, range), its records staged in LDS: S3 + S4 +
+//                   S5 of the previous batch, then S1 + S2 of this one; every
+//                   insert pair gets, in pair order, its Slim counter before
+//                   the batch, its Fat counter's growth over the batch and
+//                   the counter after it
+//   k_level         per insert entry: T = min(m0 + delta, max(m0, Bmin),
+//                   65535) from its d pairs, gathered through pos (the pairs
+//                   of one tile sit in short runs, so one fetched line serves
+//                   several of the tile's entries)
+// The last batch of an update call ends with a k_own_step that has no next
+// batch.
+//
+// Same results as the entry kernels of sf_kernels.hpp, bit for bit: S2 and S4
+// are sums, S3 a maximum and S5 a minimum per cell, and every pair of a key
+// sees the same snapshot.
+#pragma once
+
+#include "sf_kernels.hpp"
+
+namespace sfk {
+
+// Entries per partitioning tile: about kPairTiles tiles per batch, between
+// kPairTileMin and kPairTileMax entries each, so that few entries still spread
+// over many workgroups and many entries still write runs of several pairs.
+constexpr uint32_t kPairTileMin = 512, kPairTileMax = 4096, kPairTiles = 256;
+constexpr uint32_t kPairThreads = 512;   // threads of the per-tile kernels
+constexpr uint32_t kCountThreads = 256;  // threads of k_pair_count
+constexpr uint32_t kMaxCols = 16384;     // columns: 2 op types x d rows x R ranges
+constexpr uint32_t kMaxRanges = 1024;    // ranges per row
+constexpr uint32_t kOwnCounters = 8192;  // Fat counters of one range (its records fit 64 KiB of LDS)
+constexpr uint32_t kOwnThreads = 256;
+
+__host__ __device__ constexpr uint32_t pair_tile(uint32_t nv) {
+    const uint32_t per = (nv + kPairTiles - 1) / kPairTiles;
+    const uint32_t t = (per + kPairTileMin - 1) / kPairTileMin * kPairTileMin;
+    return t < kPairTileMin ? kPairTileMin : t > kPairTileMax ? kPairTileMax : t;
+}
+// Tiles (grid width) that cover every entry count up to cap.
+__host__ __device__ constexpr uint32_t pair_tiles_max(uint32_t cap) {
+    const uint32_t big = (cap + kPairTileMax - 1) / kPairTileMax;
+    return big > kPairTiles ? big : kPairTiles;
+}
+
+struct OwnerGeom {
+    uint32_t R;         // cell ranges per row
+    uint32_t cr_shift;  // log2(cells per range)
+    uint32_t zbits;     // bits of the slot in a pair's local code (2^zbits >= z)
+    uint32_t ncol;      // 2 * d * R: insert columns (row-major), then delete columns
+    uint32_t xcd;       // owner workgroup b takes row (b % 8) % d
+};
+
+struct PairMeta {
+    uint32_t total[kMaxCols];      // pairs per column
+    uint32_t start[kMaxCols + 1];  // first pair of each column; [ncol] = all pairs
+};
+
+// A pair: entry index (low word); local code (cell in range << zbits | slot)
+// and the entry's count in the high word.  Counts fit 16 bits: an entry
+// merges the copies of a key inside one merge chunk, which holds at most
+// MergeShape::kChunk keys.
+static_assert(MergeShape<4, false>::kChunk < 65536 && MergeShape<13, false>::kChunk < 65536,
+              "an entry's count must fit a pair's 16-bit count field");
+__device__ __forceinline__ uint64_t make_pair(uint32_t e, uint32_t code, uint32_t count) {
+    return uint64_t(e) | (uint64_t(code | (count << 16)) << 32);
+}
+
+// The (row, range) an owner workgroup takes.  With xcd, workgroup b runs on
+// XCD b % 8 (round-robin dispatch), so each XCD's L2 sees one row's records
+// only; placement decides cache hits, never results.
+__device__ __forceinline__ void owner_of(const OwnerGeom& og, uint32_t d, uint32_t& row, uint32_t& range) {
+    const uint32_t b = blockIdx.x;
+    if (og.xcd) {
+        const uint32_t x = b % kXcds;
+        row = x % d;
+        range = (b / kXcds) * (kXcds / d) + x / d;
+    } else {
+        row = b / og.R;
+        range = b % og.R;
+    }
+}
+
+// Entry of virtual index v: inserts are entries [0, ni), deletes sit at
+// cap-1, cap-2, ... (the merge fills them from the end).
+__device__ __forceinline__ uint32_t entry_of(uint32_t v, uint32_t ni, uint32_t cap) {
+    return v < ni ? v : cap - 1 - (v - ni);
+}
+
+// Pairs of one row of one tile per column (blockIdx.y = row).
+template <int KB, int D>
+__global__ __launch_bounds__(kCountThreads) void k_pair_count(const MergeMeta* __restrict__ meta,
+                                                              const MKey<KB, false>* __restrict__ ent_key,
+                                                              uint32_t cap, Geom g, OwnerGeom og,
+                                                              uint32_t* __restrict__ hmat) {
+    __shared__ uint32_t hist[2 * kMaxRanges];
+    const uint32_t ni = meta->n_ins, nv = ni + meta->n_del, T = pair_tile(nv);
+    const uint32_t lo = blockIdx.x * T;
+    if (lo >= nv) return;
+    const uint32_t hi = min(nv, lo + T), i = blockIdx.y, R = og.R, d = SF_ROWS(D, g);
+    for (uint32_t c = threadIdx.x; c < 2 * R; c += kCountThreads) hist[c] = 0;
+    __syncthreads();
+    for (uint32_t v = lo + threadIdx.x; v < hi; v += kCountThreads) {
+        uint32_t h, f;
+        split(g, Mixed<KB>(ent_key[entry_of(v, ni, cap)].k).row(g.seed_base + i), h, f);
+        atomicAdd(&hist[(v < ni ? 0u : R) + (h >> og.cr_shift)], 1u);
+    }
+    __syncthreads();
+    uint32_t* out = hmat + size_t(blockIdx.x) * og.ncol + i * R;
+    for (uint32_t c = threadIdx.x; c < 2 * R; c += kCountThreads) out[c < R ? c : d * R + c - R] = hist[c];
+}
+
+// Column scans of the histogram matrix over the tiles that hold entries: 64
+// columns per workgroup, a wavefront reading 256 contiguous bytes of a row.
+// (Taking the column starts in the workgroup that finishes last costs more
+// than a launch: making the totals visible across XCDs writes back the L2.)
+template <int = 0>
+__global__ __launch_bounds__(kScanCols * kScanWaves) void k_pair_colscan(uint32_t* __restrict__ hmat,
+                                                                         const MergeMeta* __restrict__ meta,
+                                                                         PairMeta* __restrict__ pm, uint32_t ncol) {
+    const uint32_t nv = meta->n_ins + meta->n_del, T = pair_tile(nv);
+    colscan_wide<uint32_t>(hmat, (nv + T - 1) / T, ncol, pm->total);
+}
+
+// Column starts: one workgroup, thread t owns columns kPer*t ...  Also adds
+// the batch's entries to the merge statistics.
+template <int = 0>
+__global__ __launch_bounds__(1024) void k_pair_start(PairMeta* __restrict__ pm, uint32_t ncol,
+                                                     MergeMeta* __restrict__ meta) {
+    constexpr uint32_t kPer = kMaxCols / 1024;
+    __shared__ uint32_t tmp[16];
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; e++) {
+        const uint32_t c = threadIdx.x * kPer + e;
+        v[e] = c < ncol ? pm->total[c] : 0u;
+        sum += v[e];
+    }
+    uint32_t run = block_scan(sum, AddOp{}, 0u, tmp) - sum;
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; e++) {
+        const uint32_t c = threadIdx.x * kPer + e;
+        if (c < ncol) pm->start[c] = run;
+        run += v[e];
+    }
+    if (threadIdx.x == 1023) pm->start[ncol] = run;
+    if (threadIdx.x == 0) {
+        meta->acc_ins += meta->n_ins;
+        meta->acc_del += meta->n_del;
+    }
+}
+
+// Writes the pairs of one row (blockIdx.y) of one tile into their columns:
+// counted per (op type, range) in LDS, staged in column order, written out as
+// one run per column.  For insert entries, the position of the pair goes to
+// pos[row][entry].
+template <int KB, int D>
+__global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* __restrict__ meta,
+                                                               const MKey<KB, false>* __restrict__ ent_key,
+                                                               const uint32_t* __restrict__ ent_cnt,
+                                                               uint32_t cap, Geom g, OwnerGeom og,
+                                                               const uint32_t* __restrict__ hmat,
+                                                               const PairMeta* __restrict__ pm,
+                                                               uint64_t* __restrict__ pairs,
+                                                               uint32_t* __restrict__ pos, uint32_t pos_stride) {
+    constexpr uint32_t E = kPairTileMax / kPairThreads;
+    constexpr uint32_t kPer = 2 * kMaxRanges / kPairThreads;  // columns per thread in the scan
+    __shared__ uint64_t stage[kPairTileMax];
+    __shared__ uint16_t scol[kPairTileMax];   // column (op type * R + range) of each staged pair
+    __shared__ uint32_t cnt[2 * kMaxRanges];  // the tile's pairs per column
+    __shared__ uint32_t lst[2 * kMaxRanges];  // their first staging slot
+    __shared__ uint32_t gb[2 * kMaxRanges];   // their first position in pairs
+    __shared__ uint32_t tmp[16];
+    const uint32_t ni = meta->n_ins, nv = ni + meta->n_del, T = pair_tile(nv);
+    const uint32_t lo = blockIdx.x * T;
+    if (lo >= nv) return;
+    const uint32_t n = min(nv - lo, T), i = blockIdx.y;
+    const uint32_t d = SF_ROWS(D, g), R = og.R, nc = 2 * R;
+    const uint32_t cmask = (1u << og.cr_shift) - 1;
+    for (uint32_t c = threadIdx.x; c < nc; c += kPairThreads) cnt[c] = 0;
+    __syncthreads();
+    uint32_t eid[E], c16[E], col[E], code[E], rank[E];
+#pragma unroll
+    for (uint32_t j = 0; j < E; j++) {
+        const uint32_t t = j * kPairThreads + threadIdx.x;
+        eid[j] = 0;
+        c16[j] = col[j] = code[j] = rank[j] = 0;
+        if (t < n) {
+            eid[j] = entry_of(lo + t, ni, cap);
+            c16[j] = ent_cnt[eid[j]] & ~kRow0Done;
+            uint32_t h, f;
+            split(g, Mixed<KB>(ent_key[eid[j]].k).row(g.seed_base + i), h, f);
+            col[j] = (lo + t >= ni ? R : 0u) + (h >> og.cr_shift);
+            code[j] = ((h & cmask) << og.zbits) | f;
+            rank[j] = atomicAdd(&cnt[col[j]], 1u);
+        }
+    }
+    __syncthreads();
+    {  // exclusive scan of the counts; thread t owns columns kPer*t ...
+        uint32_t v[kPer], sum = 0;
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; e++) {
+            const uint32_t c = threadIdx.x * kPer + e;
+            v[e] = c < nc ? cnt[c] : 0u;
+            sum += v[e];
+        }
+        uint32_t run = block_scan(sum, AddOp{}, 0u, tmp) - sum;
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; e++) {
+            const uint32_t c = threadIdx.x * kPer + e;
+            if (c < nc) lst[c] = run;
+            run += v[e];
+        }
+    }
+    for (uint32_t c = threadIdx.x; c < nc; c += kPairThreads) {
+        const uint32_t gcol = (c < R ? 0u : d * R) + i * R + (c < R ? c : c - R);
+        gb[c] = pm->start[gcol] + hmat[size_t(blockIdx.x) * og.ncol + gcol];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < E; j++) {
+        const uint32_t t = j * kPairThreads + threadIdx.x;
+        if (t >= n) continue;
+        const uint32_t s = lst[col[j]] + rank[j];
+        stage[s] = make_pair(eid[j], code[j], c16[j]);
+        scol[s] = uint16_t(col[j]);
+        if (lo + t < ni) pos[size_t(i) * pos_stride + eid[j]] = gb[col[j]] + rank[j];
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < n; s += kPairThreads) {
+        const uint32_t c = scol[s];
+        pairs[gb[c] + (s - lst[c])] = stage[s];
+    }
+}
+
+// T of every insert entry from its d pairs.  One workgroup per tile of the
+// pair partition, so the runs its pairs were written in serve its entries.
+template <int D>
+__global__ __launch_bounds__(kPairThreads) void k_level(const MergeMeta* __restrict__ meta,
+                                                        const uint32_t* __restrict__ pos, uint32_t pos_stride,
+                                                        const uint64_t* __restrict__ res, uint32_t d_rt,
+                                                        uint16_t* __restrict__ level) {
+    constexpr uint32_t E = kPairTileMax / kPairThreads;
+    const uint32_t ni = meta->n_ins, T = pair_tile(ni + meta->n_del);
+    const uint32_t lo = blockIdx.x * T;
+    if (lo >= ni) return;
+    const uint32_t hi = min(ni, lo + T), d = D ? uint32_t(D) : d_rt;
+    uint32_t m0[E], dl[E], bm[E];
+#pragma unroll
+    for (uint32_t j = 0; j < E; j++) m0[j] = dl[j] = bm[j] = kSlimMax;
+    for (uint32_t i = 0; i < d; i++) {  // d is a constant when D is
+        uint32_t ps[E];
+#pragma unroll
+        for (uint32_t j = 0; j < E; j++) {
+            const uint32_t e = lo + j * kPairThreads + threadIdx.x;
+            ps[j] = e < hi ? pos[size_t(i) * pos_stride + e] : 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < E; j++) {
+            const uint32_t e = lo + j * kPairThreads + threadIdx.x;
+            const uint64_t r = e < hi ? res[ps[j]] : 0ull;
+            m0[j] = min(m0[j], uint32_t(r) & 0xffffu);
+            dl[j] = min(dl[j], uint32_t(r >> 16) & 0xffffu);
+            bm[j] = min(bm[j], uint32_t(r >> 32) & 0xffffu);
+        }
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < E; j++) {
+        const uint32_t e = lo + j * kPairThreads + threadIdx.x;
+        if (e >= hi) continue;
+        const uint32_t rise = m0[j] + dl[j], lvl = max(m0[j], bm[j]);
+        level[e] = uint16_t(min(min(rise, lvl), kSlimMax));
+    }
+}
+
+// One owner step of one (row, range), its records staged in LDS (the range's
+// Fat buckets and Slim words, (z + 1) << cr_shift words at most): first the
+// end of batch k (pairs_f), then the start of batch k + 1 (pairs_i); either
+// may be absent.  Nothing else touches these records between the two: the
+// partition, merge and pair kernels of batch k + 1 read keys and entries only.
+//   batch k:     A = max(A, T) for its insert pairs (S3); B -= count for its
+//                delete pairs (S4); then A = min(A, max_k B) on every cell a
+//                delete touched (S5; min with the same value is idempotent)
+//   batch k + 1: each insert pair's Slim counter and Fat counter before the
+//                batch (S1), the counts added (S2), and its counter after it:
+//                res[p] = (A, growth, Bpost), each capped at 65535 (T is
+//                capped there, so the caps change no T)
+// The range is read once and written once per step.
+template <int D>
+__global__ __launch_bounds__(kOwnThreads) void k_own_step(Geom g, OwnerGeom og, uint32_t* __restrict__ rec_all,
+                                                          const PairMeta* __restrict__ pm_f,
+                                                          const uint64_t* __restrict__ pairs_f,
+                                                          const uint16_t* __restrict__ level,
+                                                          const PairMeta* __restrict__ pm_i,
+                                                          const uint64_t* __restrict__ pairs_i,
+                                                          uint64_t* __restrict__ res) {
+    extern __shared__ uint32_t L[];  // ncells records of rs words
+    constexpr uint32_t K = 8;        // insert pairs per thread kept in registers; more go through res
+    const uint32_t d = SF_ROWS(D, g);
+    uint32_t row, range;
+    owner_of(og, d, row, range);
+    const uint32_t ci = row * og.R + range, cd = d * og.R + ci;
+    const uint32_t fi0 = pm_f ? pm_f->start[ci] : 0u, fi1 = pm_f ? pm_f->start[ci + 1] : 0u;
+    const uint32_t fd0 = pm_f ? pm_f->start[cd] : 0u, fd1 = pm_f ? pm_f->start[cd + 1] : 0u;
+    const uint32_t i0 = pm_i ? pm_i->start[ci] : 0u, i1 = pm_i ? pm_i->start[ci + 1] : 0u;
+    if (fi0 == fi1 && fd0 == fd1 && i0 == i1) return;  // the range's records stay as they are
+    const uint32_t z = g.z, rs = g.rs, zmask = (1u << og.zbits) - 1;
+    const uint32_t cell0 = range << og.cr_shift;
+    const uint32_t ncells = min(1u << og.cr_shift, g.w - cell0);
+    const uint32_t nw = ncells * rs;
+    uint32_t* rec0 = rec_all + (size_t(row) * g.w + cell0) * rs;
+    for (uint32_t i = threadIdx.x; i < nw; i += kOwnThreads) L[i] = rec0[i];
+    __syncthreads();
+    if (fi0 != fi1 || fd0 != fd1) {
+        for (uint32_t p = fi0 + threadIdx.x; p < fi1; p += kOwnThreads) {
+            const uint64_t q = pairs_f[p];
+            const uint32_t code = uint32_t(q >> 32) & 0xffffu;
+            atomicMax(&L[(code >> og.zbits) * rs + z], uint32_t(level[uint32_t(q)]));
+        }
+        for (uint32_t p = fd0 + threadIdx.x; p < fd1; p += kOwnThreads) {
+            const uint32_t hi = uint32_t(pairs_f[p] >> 32), code = hi & 0xffffu;
+            atomicSub(&L[(code >> og.zbits) * rs + (code & zmask)], hi >> 16);
+        }
+        __syncthreads();
+        for (uint32_t p = fd0 + threadIdx.x; p < fd1; p += kOwnThreads) {
+            const uint32_t* r = L + ((uint32_t(pairs_f[p] >> 32) & 0xffffu) >> og.zbits) * rs;
+            uint32_t m = 0;
+            for (uint32_t f = 0; f < z; f++) m = max(m, r[f]);
+            atomicMin(const_cast<uint32_t*>(r) + z, m);
+        }
+        __syncthreads();
+    }
+    if (i0 != i1) {
+        uint64_t q[K];
+        uint32_t pre[K], a[K];
+#pragma unroll
+        for (uint32_t k = 0; k < K; k++) {
+            const uint32_t p = i0 + k * kOwnThreads + threadIdx.x;
+            q[k] = p < i1 ? pairs_i[p] : 0ull;
+            const uint32_t code = uint32_t(q[k] >> 32) & 0xffffu;
+            const uint32_t* r = L + (code >> og.zbits) * rs;
+            pre[k] = p < i1 ? r[code & zmask] : 0u;
+            a[k] = p < i1 ? r[z] : 0u;
+        }
+        // pairs beyond the registers keep (A, Bpre) in their own res word meanwhile
+        for (uint32_t p = i0 + K * kOwnThreads + threadIdx.x; p < i1; p += kOwnThreads) {
+            const uint32_t code = uint32_t(pairs_i[p] >> 32) & 0xffffu;
+            const uint32_t* r = L + (code >> og.zbits) * rs;
+            res[p] = uint64_t(r[z]) | (uint64_t(r[code & zmask]) << 32);
+        }
+        __syncthreads();  // every snapshot taken before a counter moves
+        for (uint32_t p = i0 + threadIdx.x; p < i1; p += kOwnThreads) {
+            const uint32_t hi = uint32_t(pairs_i[p] >> 32), code = hi & 0xffffu;
+            atomicAdd(&L[(code >> og.zbits) * rs + (code & zmask)], hi >> 16);
+        }
+        __syncthreads();
+        auto pack = [&](uint32_t p, uint32_t code, uint32_t av, uint32_t bpre) {
+            const uint32_t post = L[(code >> og.zbits) * rs + (code & zmask)];
+            const uint32_t grow = post - bpre;  // uint32, modular like the counter
+            res[p] = uint64_t(av) | (uint64_t(grow < kSlimMax ? grow : kSlimMax) << 16) |
+                     (uint64_t(post < kSlimMax ? post : kSlimMax) << 32);
+        };
+#pragma unroll
+        for (uint32_t k = 0; k < K; k++) {
+            const uint32_t p = i0 + k * kOwnThreads + threadIdx.x;
+            if (p < i1) pack(p, uint32_t(q[k] >> 32) & 0xffffu, a[k], pre[k]);
+        }
+        for (uint32_t p = i0 + K * kOwnThreads + threadIdx.x; p < i1; p += kOwnThreads) {
+            const uint64_t sv = res[p];
+            pack(p, uint32_t(pairs_i[p] >> 32) & 0xffffu, uint32_t(sv), uint32_t(sv >> 32));
+        }
+        __syncthreads();
+    }
+    for (uint32_t i = threadIdx.x; i < nw; i += kOwnThreads) rec0[i] = L[i];
+}
+
+}  // namespace sfk

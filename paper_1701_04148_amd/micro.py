@@ -31,6 +31,8 @@ def lib():
         L.micro_atomic_add_xcd.argtypes = [P, U64, U64, U32, U32, U32, P]
         L.micro_atomic_add_u32.restype = I
         L.micro_atomic_add_u32.argtypes = [P, U64, U64, U32, P]
+        L.micro_scatter_u64.restype = I
+        L.micro_scatter_u64.argtypes = [P, U64, U64, U32, P]
         _lib = L
     return _lib
 
@@ -76,3 +78,7 @@ def num_xcc() -> int:
 def gather_pair(table, n: int, seed: int, same_line: bool, sink):
     _ok(lib().micro_gather_pair(table.data_ptr(), table.numel(), n, seed, int(same_line),
                                 sink.data_ptr(), _stream()), "micro_gather_pair")
+
+
+def scatter_u64(table, n: int, seed: int):
+    _ok(lib().micro_scatter_u64(table.data_ptr(), table.numel(), n, seed, _stream()), "micro_scatter_u64")

@@ -22,13 +22,28 @@ def dev_keys(keys: np.ndarray):
     return torch.from_numpy(np.ascontiguousarray(keys).reshape(-1)).cuda()
 
 
-def gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base=1, calls=1, merge=False, tile=2048):
+def owner_shape(d, w, z) -> bool:
+    """Whether sf_set_merge(1) takes the owner-computes path for this shape (the rule of
+    sf.h: ranges of 2^k >= 16 cells, at most min(1024, 8192 / d) per row, at most 8192 Fat
+    counters and a 16-bit local code per range)."""
+    rmax = min(1024, 16384 // (2 * d))
+    zbits = max(0, (z - 1).bit_length())
+    sh = 4
+    while -(-w // (1 << sh)) > rmax:
+        sh += 1
+    return (1 << sh) * z <= 8192 and (1 << sh) << zbits <= 65536
+
+
+def gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base=1, calls=1, merge=1, tile=2048):
     """Updates (split into `calls` consecutive calls) then queries, on the GPU.
     Returns (fat, slim, answers)."""
     import torch
     sk = sf.Sketch(d, w, z, key_bytes=kb, seed_base=seed_base, batch_ops=b)
-    sk.set_merge(merge)
+    sk.set_merge(int(merge))
     sk.set_tile(tile)
+    path = sk.merge_path()
+    want = int(merge) if int(merge) != 1 or owner_shape(d, w, z) else 2
+    assert path == want, (merge, path, want)
     n = keys.shape[0]
     cuts = np.linspace(0, n, calls + 1).astype(np.int64)
     for lo, hi in zip(cuts[:-1], cuts[1:]):

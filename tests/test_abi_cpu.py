@@ -58,8 +58,14 @@ def test_footprint_and_budget():
     chunks = (b // 2048 + 2 * 1024 + 1) * 20   # every merge chunk: key range, whole buckets
     meta = 4 * (2 * 1024 + 1) * 4 + 3 * 256     # per-bucket totals, starts, sizes, chunk prefix; counters
     need = cells * 5 * 4 + cells * 4 * 4 + cells * 2 + 4 * b * 6 + merge + hist + chunks
+    # owner-computes S1..S5 (this shape qualifies: 1024 ranges of 1024 cells per row):
+    # pairs, their positions, per-pair snapshots, T per entry, per-tile column counts
+    ncol = 2 * 4 * 1024
+    owner = 4 * b * 8 + 4 * b * 4 + 4 * b * 8 + b * 2 + (b // 8192) * ncol * 4
+    pair_meta = (2 * 16384 + 1) * 4
+    need += owner
     assert fp >= need
-    assert fp < need + meta + (8 << 10)          # plus 256-B rounding
+    assert fp < need + meta + pair_meta + (8 << 10)          # plus 256-B rounding
     h = ctypes.c_void_p()
     rc = sf.lib().sf_create(ctypes.byref(c), fp - 1, None, ctypes.byref(h))
     assert rc == sf.SF_ENOMEM and not h.value

@@ -17,9 +17,14 @@ from tests.oracle_support import exact_counts, random_turnstile
 pytestmark = pytest.mark.gpu
 
 
-def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag="", merge=False):
+MERGE_NAMES = {0: "tile", 1: "batch+owner", 2: "batch+atomic"}
+
+
+def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag="", merge=0):
+    """merge: 0 per-tile merging, 1 batch-wide merge with owner-computes S1..S5 where the
+    shape allows, 2 batch-wide merge with atomic S1..S5 (sf_set_merge)."""
     say(f"[case] {tag} d={d} w={w} z={z} kb={kb} n={keys.shape[0]} q={queries.shape[0]} "
-        f"b={b} calls={calls} merge={'batch' if merge else 'tile'}")
+        f"b={b} calls={calls} merge={MERGE_NAMES[int(merge)]}")
     g = gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls, merge=merge)
     o = oracle_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls)
     assert_same(g[0], o[0], "fat")
@@ -32,7 +37,7 @@ def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag="", merg
                                       (8, 512, 4, 13), (5, 333, 2, 13), (16, 128, 1, 4),
                                       (2, 4096, 8, 4), (4, 256, 4, 13)])
 @pytest.mark.parametrize("b", [1000, 1 << 20])
-@pytest.mark.parametrize("merge", [False, True])
+@pytest.mark.parametrize("merge", [0, 1, 2])
 def test_mixed_small(d, w, z, kb, b, merge):
     """Several tiles and a ragged tail: 20011 mixed ops, 30% deletes."""
     rng = np.random.default_rng(d * 7 + w + kb)
@@ -41,7 +46,7 @@ def test_mixed_small(d, w, z, kb, b, merge):
 
 
 @pytest.mark.parametrize("b", [1, 3, 64])
-@pytest.mark.parametrize("merge", [False, True])
+@pytest.mark.parametrize("merge", [0, 1, 2])
 def test_small_batches_and_sequential(b, merge):
     """b = 1 is the sequential SF_F rule of Section 3.5 (the oracle's seq mode)."""
     rng = np.random.default_rng(b)
@@ -101,7 +106,7 @@ def test_insert_and_delete_entry_points():
     sk.close()
 
 
-@pytest.mark.parametrize("merge", [False, True])
+@pytest.mark.parametrize("merge", [0, 1, 2])
 def test_small_config_full_size(merge):
     """1M Zipf(1.0) inserts over 100K keys, d=4, Fat 4x65536, Slim 4x16384; all 100K queried."""
     wl = sfgen.config_small()
@@ -110,7 +115,7 @@ def test_small_config_full_size(merge):
     assert (ans.astype(np.int64) >= np.minimum(f, 65535)).all()
 
 
-@pytest.mark.parametrize("skew,merge", [(1.4, False), (1.4, True), (0.6, True), (1.0, True)])
+@pytest.mark.parametrize("skew,merge", [(1.4, 0), (1.4, 1), (0.6, 1), (1.0, 1), (1.0, 2)])
 def test_main_config_scaled(skew, merge):
     """The 32M-op configuration divided by 8 (4M ops, 10% deletes, w=2^17)."""
     wl = sfgen.config_main(skew, scale=8)
@@ -125,10 +130,10 @@ def test_main_config_full_size_as_benchmarked(skew):
     answers bit-exact against the oracle."""
     wl = sfgen.config_main(skew)
     check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, batch_for_width(wl.w),
-          tag=f"c2 full s={skew}", merge=True)
+          tag=f"c2 full s={skew}", merge=1)
 
 
-@pytest.mark.parametrize("merge", [False, True])
+@pytest.mark.parametrize("merge", [0, 1, 2])
 def test_flow_config_scaled(merge):
     """13-byte flow keys, d=8, divided by 64 (2M packets over 62.5K flows)."""
     wl = sfgen.config_flows(scale=64)
@@ -143,7 +148,8 @@ def test_batch_merge_with_one_hot_key():
     keys[rng.random(n) < 0.6] = 12345
     ops = np.zeros(n, np.uint8)
     q = np.unique(keys)[:50_000]
-    check(4, 1 << 14, 4, 4, keys, ops, q, n, tag="hot", merge=True)
+    check(4, 1 << 14, 4, 4, keys, ops, q, n, tag="hot", merge=1)
+    check(4, 1 << 14, 4, 4, keys, ops, q, n, tag="hot", merge=2)
 
 
 @pytest.mark.parametrize("kb", [4, 13])
@@ -186,7 +192,8 @@ def test_merge_chunk_packing_shapes(kb):
     keys = np.concatenate([ki, kd])
     ops = np.concatenate([np.zeros(ki.shape[0], np.uint8), np.ones(kd.shape[0], np.uint8)])
     q = np.concatenate([np.unique(ki, axis=0), cand[-1000:]])
-    check(d, w, z, kb, keys, ops, q, 1 << 20, tag="packing", merge=True)
+    for mode in (1, 2):
+        check(d, w, z, kb, keys, ops, q, 1 << 20, tag="packing", merge=mode)
 
 
 def test_query_exported_slim_collector():
@@ -338,6 +345,7 @@ def test_flow_config_full_size_bit_exact():
     th.start()
     try:
         sk = sf.Sketch(wl.d, wl.w, wl.z, key_bytes=13, batch_ops=b)
+        assert sk.merge_path() == 1                  # owner-computes S1..S5, as benchmarked
         sk.insert(dev_keys(wl.keys))
         ans = sk.query(dev_keys(wl.queries)).cpu().numpy().view(np.uint32)
         sk.sync()
