@@ -59,10 +59,11 @@ def test_footprint_and_budget():
     meta = 4 * (2 * 1024 + 1) * 4 + 3 * 256     # per-bucket totals, starts, sizes, chunk prefix; counters
     need = cells * 5 * 4 + cells * 4 * 4 + cells * 2 + 4 * b * 6 + merge + hist + chunks
     # owner-computes S1..S5 (this shape qualifies: 1024 ranges of 1024 cells per row):
-    # pairs, their positions, per-pair snapshots, T per entry, per-tile column counts
+    # pairs of two batches, their positions, per-pair snapshots, T per entry, per-tile
+    # column counts (b / 4096 tiles)
     ncol = 2 * 4 * 1024
-    owner = 4 * b * 8 + 4 * b * 4 + 4 * b * 8 + b * 2 + (b // 8192) * ncol * 4
-    pair_meta = (2 * 16384 + 1) * 4
+    owner = 2 * 4 * b * 8 + 4 * b * 4 + 4 * b * 8 + b * 2 + (b // 4096) * ncol * 4
+    pair_meta = 2 * (2 * 16384 + 1) * 4
     need += owner
     assert fp >= need
     assert fp < need + meta + pair_meta + (8 << 10)          # plus 256-B rounding
