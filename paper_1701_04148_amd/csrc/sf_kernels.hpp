@@ -709,6 +709,7 @@ __global__ __launch_bounds__(kScanBuckets * kScanSegs) void k_part_colscan_tall(
 // than a chunk.  Equal keys share a bucket, so packing never splits a key's
 // copies between chunks.
 constexpr uint32_t kStartPer = 2;
+constexpr uint32_t kBigChunks = 8, kBigList = 64;
 static_assert(2 * kMaxBuckets / kStartPer <= 1024, "k_part_start is one workgroup");
 static_assert((2 * kMaxBuckets) % kPartThreads == 0, "k_part_scatter gives each thread whole buckets");
 template <int KB, bool G>
@@ -719,6 +720,7 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
     __shared__ uint32_t tmp[16];
     __shared__ uint32_t rev[2 * kMaxBuckets / P];  // per-thread values in reverse thread order
     __shared__ uint32_t st[2 * kMaxBuckets + 1];   // bucket starts, then the end of the keys
+    __shared__ uint32_t big_b[kBigList], big_c0[kBigList], nbig;  // buckets of more than kBigChunks chunks
     const uint32_t t = threadIdx.x, nt = blockDim.x, nbt = P * nt, half = nbt / 2;
     uint32_t sz[P], sum = 0;
 #pragma unroll
@@ -763,14 +765,23 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
         nc[e] = sz[e] > H ? (sz[e] + K - 1) / K : (gs[e] && st[nxt[e]] > st[b] ? 1u : 0u);
         csum += nc[e];
     }
-    uint32_t c0 = block_scan(csum, AddOp{}, 0u, tmp) - csum;  // chunk prefix
+    if (t == 0) nbig = 0;
+    uint32_t c0 = block_scan(csum, AddOp{}, 0u, tmp) - csum;  // chunk prefix (its barriers order nbig = 0)
 #pragma unroll
     for (uint32_t e = 0; e < P; e++) {
         const uint32_t b = t * P + e, del = b >= half ? 1u : 0u;
         if (sz[e] > H) {
-            const uint32_t whole = nc[e] == 1 ? b + 1 : b;  // a bucket split over chunks is held whole by none
-            for (uint32_t q = 0; q < nc[e]; q++)
-                chunks[c0 + q] = MergeChunk{st[b] + q * K, min(K, sz[e] - q * K), del, b, whole};
+            // a hot bucket's many chunks are written by the whole workgroup below
+            uint32_t slot = kBigList;
+            if (nc[e] > kBigChunks) slot = atomicAdd(&nbig, 1u);
+            if (slot < kBigList) {
+                big_b[slot] = b;
+                big_c0[slot] = c0;
+            } else {
+                const uint32_t whole = nc[e] == 1 ? b + 1 : b;  // a bucket split over chunks is held whole by none
+                for (uint32_t q = 0; q < nc[e]; q++)
+                    chunks[c0 + q] = MergeChunk{st[b] + q * K, min(K, sz[e] - q * K), del, b, whole};
+            }
         } else if (nc[e]) {
             chunks[c0] = MergeChunk{st[b], st[nxt[e]] - st[b], del, b, nxt[e]};
         }
@@ -781,6 +792,13 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
         meta->chunk0[0] = 0;
         meta->n_ins = 0;
         meta->n_del = 0;
+    }
+    __syncthreads();
+    const uint32_t nl = min(nbig, kBigList);
+    for (uint32_t l = 0; l < nl; l++) {
+        const uint32_t b = big_b[l], cb = big_c0[l], size = st[b + 1] - st[b];
+        const uint32_t n = (size + K - 1) / K, del = b >= half ? 1u : 0u;
+        for (uint32_t q = t; q < n; q += nt) chunks[cb + q] = MergeChunk{st[b] + q * K, min(K, size - q * K), del, b, b};
     }
 }
 
