@@ -6,13 +6,19 @@ already resident in HBM: re-zero the sketch, apply the op stream (inserts and
 deletes through the deterministic batch schedule), export the Slim (what the
 monitor ships to the collector), and answer the point queries.
 
-Default workload: one SF-sketch, d=4, Fat 4 x 2^22 uint32 (w=2^20 buckets of
-z=4), Slim 4 x 2^20 uint16; 32M uint32 ops, Zipf(s=1.0) over 1M distinct
+Headline workload: one SF-sketch, d=4, Fat 4 x 2^22 uint32 (w=2^20 buckets
+of z=4), Slim 4 x 2^20 uint16; 32M uint32 ops, Zipf(s=1.0) over 1M distinct
 keys, 10% deletions of live occurrences; queries = the 1M keys + 1M absent.
+Further legs, each timed the same way and checked against the CPU oracle at
+full size: the same workload at Zipf 0.6 and 1.4, the 1M-insert sketch
+(d=4, w=2^14), the 128M-packet flow sketch (d=8, w=2^21, 13-byte keys), 1024
+sketches in one group, and the serving loop.
 
 Prints ONE JSON line (rank 0): throughput in M items/s (ops + queries), the
-dominant kernel's roofline object, and the CPU oracle timed on the host.
-Progress goes to stderr.
+dominant kernel's roofline object, the CPU oracle timed on the host (batch
+and sequential updates on one core, queries on one core and on all cores),
+and the batch schedule's accuracy against sequential SF_F.  Progress goes to
+stderr.
 """
 from __future__ import annotations
 
@@ -42,62 +48,77 @@ def source_digest() -> str:
     """Digest of the kernel sources; a stored counter reading is valid only for it."""
     h = hashlib.sha256()
     for rel in ("paper_1701_04148_amd/csrc/sf_lib.hip", "paper_1701_04148_amd/csrc/sf_device.hpp",
-                "paper_1701_04148_amd/csrc/sf_kernels.hpp", "paper_1701_04148_amd/csrc/sf_host.hpp"):
+                "paper_1701_04148_amd/csrc/sf_kernels.hpp", "paper_1701_04148_amd/csrc/sf_host.hpp",
+                "paper_1701_04148_amd/csrc/sf_owner.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kind: str, d: int, u: dict) -> int:
+def algorithmic_bytes(kind: str, d: int, u: dict, kb: int = 4) -> int:
     """Bytes one kernel kind's step must move over the timed steps, each access counted
     at its element size.  u holds the units: ins / dels / ops (op counts), q (queries),
     ie / de (merged insert / delete entries; equal to ins / dels when merging per tile),
-    cells, mixed (1 B op code per op)."""
+    cells, mixed (1 B op code per op); kb = key bytes.  The owner step (k_own_step, its
+    kinds own_step and own_final) does S1..S5 of every entry: per row an insert entry
+    reads and writes its Fat counter and reads and may write its Slim counter (12 B), a
+    delete entry reads and writes its Fat counter, reads the rest of its bucket (12 B)
+    and reads and may write its Slim counter (24 B)."""
     ob = u["ops"] if u["mixed"] else 0
+    own = u["ie"] * d * 12 + u["de"] * d * 24
     return {
-        "partition": (u["ins"] + u["dels"]) * 12 + 2 * ob,   # keys read twice, partitioned copy written
-        "merge": (u["ins"] + u["dels"]) * 4 + (u["ie"] + u["de"]) * 8,  # partitioned keys in, entries out
-        "snapshot": u["ie"] * (4 + d * (4 + 4 + 4 + 2)),     # key, Slim cell, Fat counter, snapshot out
-        "fat_add": u["ie"] * (8 + d * 8),                    # key + count, Fat read-modify-write
-        "raise": u["ie"] * (4 + d * (4 + 4 + 2)),            # key, Fat counter, snapshot in
-        "fat_sub": u["de"] * (8 + d * 8),
-        "clamp": u["de"] * (4 + d * (16 + 4)),               # key, 16-B bucket, Slim cell
-        "query": u["q"] * (4 + d * 4 + 4),                   # key, d Slim cells, answer
+        "partition": (u["ins"] + u["dels"]) * (3 * kb) + 2 * ob,  # keys read twice, partitioned copy written
+        "merge": (u["ins"] + u["dels"]) * kb + (u["ie"] + u["de"]) * (kb + 4),  # partitioned keys in, entries out
+        "pairs": (u["ie"] + u["de"]) * (2 * (kb + 4) + d * 8) + u["ie"] * d * 4,  # entries read twice, pairs out
+        "own_step": own, "own_final": own,                   # (split by launches below)
+        "level": u["ie"] * (d * (4 + 8) + 2),                # positions, pair snapshots, T out
+        "snapshot": u["ie"] * (kb + d * (4 + 4 + 4 + 2)),    # key, Slim cell, Fat counter, snapshot out
+        "fat_add": u["ie"] * (kb + 4 + d * 8),               # key + count, Fat read-modify-write
+        "raise": u["ie"] * (kb + d * (4 + 4 + 2)),           # key, Fat counter, snapshot in
+        "fat_sub": u["de"] * (kb + 4 + d * 8),
+        "clamp": u["de"] * (kb + d * (16 + 4)),              # key, 16-B bucket, Slim cell
+        "query": u["q"] * (kb + d * 4 + 4),                  # key, d Slim cells, answer
         "export": u["cells"] * 6,                            # 4-B working cell in, 2-B cell out
     }.get(kind, 0)
 
 
 def random_accesses(kind: str, d: int, u: dict) -> int:
     """Random (uncoalesced) accesses of a kernel kind over the timed steps: one per cell
-    record touched (a record holds the cell's Fat bucket and Slim word), one per atomic."""
+    record touched (a record holds the cell's Fat bucket and Slim word), one per atomic.
+    The owner path has none on the records (its ranges are staged in LDS)."""
     return {"snapshot": d * u["ie"], "fat_add": d * u["ie"], "raise": 2 * d * u["ie"],
-            "fat_sub": d * u["de"], "clamp": 2 * d * u["de"], "query": d * u["q"]}.get(kind, 0)
+            "fat_sub": d * u["de"], "clamp": 2 * d * u["de"], "query": d * u["q"],
+            "level": d * u["ie"]}.get(kind, 0)
 
 
-def step_algorithmic_bytes(d: int, n_ins: int, n_del: int, n_q: int) -> int:
+def step_algorithmic_bytes(d: int, n_ins: int, n_del: int, n_q: int, kb: int = 4) -> int:
     """The method's own bytes per op, whatever the implementation: an insert touches the
     key, d Fat counters (read-modify-write) and d Slim cells; a delete the key, d Fat
-    buckets and d Slim cells; a query the key and d Slim cells (uint16)."""
-    return n_ins * (4 + d * 8 + d * 2) + n_del * (4 + d * (8 + 12) + d * 2) + n_q * (4 + 2 * d)
+    buckets and d Slim cells; a query the key and d Slim cells (uint16).  With 13-byte
+    keys and d = 8: 93 B per insert, 29 B per query."""
+    return n_ins * (kb + d * 8 + d * 2) + n_del * (kb + d * (8 + 12) + d * 2) + n_q * (kb + 2 * d)
 
 
 def stored_traffic(kernel_kind: str, workload: str):
-    """HBM bytes per launch from the committed PMC summary, if taken on these sources."""
+    """HBM bytes per launch from the committed PMC summary, if taken on these sources and
+    this workload."""
     path = os.path.join(PROFILE_DIR, "pmc_traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_digest") != source_digest() or rec.get("workload") != workload:
+    if rec.get("source_digest") != source_digest():
         return None
-    k = rec.get("kernels", {}).get(kernel_kind)
+    k = rec.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel_kind)
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
 
 
-KIND_OF_KERNEL = {"k_snapshot": "snapshot", "k_raise": "raise", "k_clamp": "clamp",
+KIND_OF_KERNEL = {"k_own_step": "own_step", "k_level": "level", "k_pair_count": "pair_count",
+                  "k_pair_colscan": "pair_colscan", "k_pair_start": "pair_start", "k_pair_scatter": "pair_scatter",
+                  "k_snapshot": "snapshot", "k_raise": "raise", "k_clamp": "clamp",
                   "k_query": "query", "k_query_rows": "query", "k_query_min": "query", "k_pack16": "export", "k_merge": "merge",
                   "k_entries_snapshot": "snapshot", "k_entries_snapshot_rows": "snapshot",
                   "k_entries_raise": "raise", "k_entries_clamp": "clamp",
@@ -155,6 +176,24 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
             "kernels": kernels}
 
 
+def store_pmc(rec: dict) -> dict:
+    """Adds one workload's PMC record to profiles/pmc_traffic.json (records taken on
+    other kernel sources are dropped)."""
+    path = os.path.join(PROFILE_DIR, "pmc_traffic.json")
+    try:
+        with open(path) as fh:
+            allrec = json.load(fh)
+    except (OSError, ValueError):
+        allrec = {}
+    if allrec.get("source_digest") != rec["source_digest"]:
+        allrec = {"source_digest": rec["source_digest"], "workloads": {}}
+    allrec.setdefault("workloads", {})[rec["workload"]] = {
+        "copy_calibration": rec["copy_calibration"], "kernels": rec["kernels"]}
+    with open(path, "w") as fh:
+        json.dump(allrec, fh, indent=1)
+    return allrec
+
+
 def summarize_stats(stats_csv: str) -> str:
     """Text table of a rocprofv3 --stats kernel_stats.csv (per-kernel calls and durations)."""
     import csv
@@ -198,10 +237,28 @@ def summarize_trace(trace_csv: str) -> str:
     return "\n".join(lines)
 
 
-def workload_tag(args) -> str:
-    """Name of the timed workload (sketch shape, stream, schedule, tile) for stored counters."""
-    return (f"c2_d4_w{2**20 // args.scale}_z4_ops{32_000_000 // args.scale}_zipf{args.skew}_del10"
-            f"_b{args.batch_ops}_tile{args.tile}_merge{args.merge}")
+def workload_tag(leg: str, b: int, scale: int = 1) -> str:
+    """Name of a timed workload (sketch shape, stream, schedule) for stored counters."""
+    return f"{leg}_b{b}_scale{scale}"
+
+
+def cpu_info() -> dict:
+    """The host the CPU oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        aff = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "affinity_cpus": aff,
+            "threads_for_all_cores": min(16, aff)}
 
 
 def micro_ceilings(torch, sizes_mib=(1, 16, 64, 256, 4096), n=1 << 26):
@@ -270,7 +327,7 @@ def run_multi(args, torch, np, sf, sfgen):
     cfgs = [sf.make_config(m.d, int(m.w[i]), m.z, 4, 1, batch_of_w[int(m.w[i])]) for i in range(m.n)]
     G = sf.SketchGroup(cfgs)
     G.set_tile(args.tile)
-    G.set_merge(args.merge == "batch")
+    G.set_merge(args.merge != "tile")
 
     def step():
         G.reset()
@@ -318,8 +375,10 @@ def run_multi(args, torch, np, sf, sfgen):
     # the plain path: one Sketch per stream, its own launches, same kernels
     lone = [sf.Sketch(c.d, c.w, c.z, batch_ops=c.batch_ops) for c in cfgs]
     for s_ in lone:
+        # the group's kernels, one sketch and one batch per launch (the owner-computes path
+        # would also need its pair buffers per sketch)
         s_.set_tile(args.tile)
-        s_.set_merge(args.merge == "batch")
+        s_.set_merge(2 if args.merge != "tile" else 0)
     seg, qseg = m.seg.astype(np.int64), m.qseg.astype(np.int64)
 
     def lone_step():
@@ -409,7 +468,7 @@ def run_serve(args, torch, np, sf, sfgen, shape_name, w=None):
     cfg = sf.make_config(shape["d"], shape["w"], shape["z"], 4, 1, batch_for_width(shape["w"]))
     budget = 64 << 30
     pool = sf.SketchPool(cfg, hbm_budget_bytes=budget)
-    pool.set_merge(args.merge == "batch")
+    pool.set_merge(args.merge != "tile")
     slots, _ = pool.capacity()
     dev = torch.device("cuda:0")
     keys = torch.from_numpy(w.pool.view(np.int32)).to(dev)
@@ -493,24 +552,217 @@ def run_collector(np, sk, step, queries, answers, snapshots=20):
                     "collector process copies it to its GPU; query keys and answers travel over the pipe"}
 
 
+LEG_NAMES = ("main", "main_s0.6", "main_s1.4", "small", "flows")
+
+
+def leg_workload(leg: str, sfgen, scale: int = 1):
+    if leg == "small":
+        return sfgen.config_small()
+    if leg == "flows":
+        return sfgen.config_flows(scale=scale)
+    s = 1.0 if leg == "main" else float(leg.split("_s")[1])
+    return sfgen.config_main(s, scale=scale)
+
+
+def leg_config(leg: str, wl, b: int, n_del: int) -> dict:
+    kind = "uint32" if wl.key_bytes == 4 else "13-byte flow"
+    ops = (f"{wl.n_ops} {kind} ops Zipf(s={wl.meta['s']}) over {wl.meta['n_universe']} keys"
+           + (f" with {n_del} deletes" if n_del else ", insert-only"))
+    return {"workload": f"one SF-sketch d={wl.d}, Fat {wl.d}x{wl.w * wl.z} u32 (w={wl.w}, z={wl.z}), "
+                        f"Slim {wl.d}x{wl.w} u16; {ops}; export Slim; {wl.n_queries} queries "
+                        "(present + absent); keys resident in HBM",
+            "sketches": 1, "d": wl.d, "w": wl.w, "z": wl.z, "key_bytes": wl.key_bytes, "ops": wl.n_ops,
+            "deletes": n_del, "queries": wl.n_queries, "zipf_s": wl.meta["s"], "batch_ops": b}
+
+
+def gpu_leg(args, torch, np, sf, wl, b: int, leg: str, steps: int, warmup: int) -> dict:
+    """Times one single-sketch workload (reset, updates, Slim export, queries per step),
+    then the same steps with per-kernel events; returns the numbers, the answers and the
+    live sketch (for the host-fed and collector runs of the headline)."""
+    dev = torch.device("cuda:0")
+    kb = wl.key_bytes
+
+    def dev_keys(a):
+        if kb == 4:
+            return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)
+        return torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(dev)
+
+    keys = dev_keys(wl.keys)
+    ops = torch.from_numpy(wl.ops).to(dev) if wl.ops is not None else None
+    qk = dev_keys(wl.queries)
+    out = torch.empty(wl.n_queries, dtype=torch.int32, device=dev)
+    cells = wl.d * wl.w
+    slim16 = torch.empty(cells, dtype=torch.int16, device=dev)
+    n_del = int(wl.ops.sum()) if wl.ops is not None else 0
+    n_ins = wl.n_ops - n_del
+    sk = sf.Sketch(wl.d, wl.w, wl.z, key_bytes=kb, batch_ops=b)
+    sk.set_tile(args.tile)
+    sk.set_merge(1 if args.merge == "batch" else (2 if args.merge == "atomic" else 0))
+
+    def step():
+        sk.reset()
+        if ops is None:
+            sk.insert(keys)
+        else:
+            sk.update(keys, ops)
+        sf.sf_export_slim(sk._h, slim16)
+        sk.query(qk, out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ie0, de0 = sk.merge_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ie1, de1 = sk.merge_stats()
+    ms_step = elapsed * 1e3 / steps
+    value = (wl.n_ops + wl.n_queries) * steps / elapsed / 1e6
+    log(f"[bench] {leg}: {steps} steps: {ms_step:.3f} ms/step, {value:.1f} M items/s")
+    # Per-kernel durations: the same steps again with a HIP event pair around every
+    # kernel group on the sketch's stream (the events add a gap after each group, so
+    # these steps are not the timed ones).
+    sk.profile(True)
+    sk.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    prof_ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = sk.profile_read(reset=True)
+    sk.profile(False)
+    fat = sk.export_fat()
+    rows = fat.reshape(wl.d, -1).astype(np.int64).sum(axis=1)
+    if not (rows == n_ins - n_del).all():       # Section 3.4: every Fat row sums to the net weight
+        raise SystemExit(f"{leg}: Fat row sums {rows} != net weight {n_ins - n_del}")
+    answers = out.cpu().numpy().view(np.uint32).copy()
+    u = dict(ins=n_ins * steps, dels=n_del * steps, ops=wl.n_ops * steps, q=wl.n_queries * steps,
+             cells=cells * steps, mixed=ops is not None,
+             ie=(ie1 - ie0) if args.merge != "tile" else n_ins * steps,
+             de=(de1 - de0) if args.merge != "tile" else n_del * steps)
+    kernels = {}
+    for kind, (ms, launches, _) in prof.items():
+        if not launches:
+            continue
+        byt = algorithmic_bytes(kind, wl.d, u, kb)
+        acc = random_accesses(kind, wl.d, u)
+        kernels[kind] = dict(ms_total=round(ms, 3), launches=launches, avg_launch_us=round(ms * 1e3 / launches, 2),
+                             alg_gbs=round(byt / (ms * 1e-3) / 1e9, 1) if byt else None,
+                             g_accesses_s=round(acc / (ms * 1e-3) / 1e9, 2) if acc else None)
+    return dict(leg=leg, sk=sk, keys=keys, ops=ops, qk=qk, out=out, slim16=slim16, step=step,
+                ms_step=ms_step, value=value, prof_ms=prof_ms, kernels=kernels, units=u, answers=answers,
+                n_ins=n_ins, n_del=n_del, entries_per_step=[u["ie"] // steps, u["de"] // steps])
+
+
+def roofline_of(g: dict, wl, b: int, scale: int) -> dict:
+    """The dominant kernel's roofline: the owner step (k_own_step: its per-batch launches
+    and the closing launch of each update call), or the largest kind on another path."""
+    k, u, kb = g["kernels"], g["units"], g["wl_kb"]
+    if "own_step" in k:
+        kinds = [x for x in ("own_step", "own_final") if x in k]
+        ms = sum(k[x]["ms_total"] for x in kinds)
+        launches = sum(k[x]["launches"] for x in kinds)
+        name, kind_for_traffic = "k_own_step", "own_step"
+        alg = algorithmic_bytes("own_step", wl.d, u, kb)
+    else:
+        dom = max(k, key=lambda x: k[x]["ms_total"])
+        ms, launches, name, kind_for_traffic = k[dom]["ms_total"], k[dom]["launches"], dom, dom
+        alg = algorithmic_bytes(dom, wl.d, u, kb)
+    avg_us = ms * 1e3 / launches
+    achieved = alg / launches / (avg_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic(kind_for_traffic, workload_tag(g["leg"], b, scale)),
+            "avg_launch_us": round(avg_us, 2), "launches_per_step": round(launches / (u["ops"] / wl.n_ops), 2),
+            "alg_bytes_per_launch": int(alg / launches)}
+    if name == "k_own_step":
+        rec_bytes = wl.d * wl.w * (wl.z + 1) * 4
+        roof["streamed"] = {
+            "what": "each launch reads its ranges' cell records into LDS and writes them back: at most "
+                    "2 x the record array per launch",
+            "bytes_per_launch_max": 2 * rec_bytes,
+            "gbs_max": round(2 * rec_bytes / (avg_us * 1e-6) / 1e9, 1),
+            "frac_max": round(2 * rec_bytes / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        if roof["traffic"]:
+            roof["traffic_gbs"] = round(roof["traffic"] / (avg_us * 1e-6) / 1e9, 1)
+            roof["traffic_frac"] = round(roof["traffic"] / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+    return roof
+
+
+def oracle_check(np, wl, b: int, gpu_answers, time_seq: bool = True, time_queries: bool = False) -> dict:
+    """CPU oracle on the full workload: batch schedule (its answers must equal the GPU's
+    bit for bit), strict sequential SF_F (accuracy against it), and optionally the
+    queries on one core and on all cores.  Each oracle run is one thread."""
+    import oracle
+    from oracle import accuracy
+    kb = wl.key_bytes
+    runs = accuracy.run_modes(wl.d, wl.w, wl.z, kb, wl.keys, wl.ops, wl.queries, b,
+                              modes=("seq", "batch") if time_seq else ("batch",))
+    sk_b, ans_b, t_b = runs["batch"]                  # t_b: the updates alone
+    parity = bool(np.array_equal(ans_b, gpu_answers))
+    t0 = time.perf_counter()
+    sk_b.query(wl.queries)
+    t_q = time.perf_counter() - t0
+    rep = {"parity_full_size": parity}
+    items = wl.n_ops + wl.n_queries
+    rep["cpu_baseline"] = {"value": round(items / (t_b + t_q) / 1e6, 3), "unit": "Mitems/s", "cores": 1,
+                           "kind": "oracle",
+                           "sample": f"the full workload ({wl.n_ops} ops + {wl.n_queries} queries), batch "
+                                     f"schedule b={b}: updates {t_b:.1f}s + queries {t_q:.1f}s on 1 thread",
+                           "batch_updates_mops": round(wl.n_ops / t_b / 1e6, 3)}
+    if time_seq:
+        _, _, t_s = runs["seq"]
+        rep["cpu_baseline"]["seq_updates_mops"] = round(wl.n_ops / t_s / 1e6, 3)
+        rep["cpu_baseline"]["seq_s"] = round(t_s, 2)
+        rep["accuracy"] = accuracy.report(wl.d, wl.w, wl.z, kb, wl.keys, wl.ops, wl.queries, b, runs=runs)
+    if time_queries:
+        import threading
+        info = cpu_info()
+        nth = info["threads_for_all_cores"]
+        q = wl.queries
+        reps = max(1, (1 << 24) // max(1, q.shape[0]))        # about 16M queries per timing
+        qq = np.concatenate([q] * reps) if reps > 1 else q
+        t0 = time.perf_counter()
+        sk_b.query(qq)
+        t1 = time.perf_counter() - t0
+        parts = np.array_split(np.arange(qq.shape[0]), nth)
+        th = [threading.Thread(target=sk_b.query, args=(qq[p[0]:p[-1] + 1],)) for p in parts if p.size]
+        t0 = time.perf_counter()
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        tn = time.perf_counter() - t0
+        rep["cpu_baseline"].update({
+            "queries_1core_mqps": round(qq.shape[0] / t1 / 1e6, 2),
+            "queries_all_cores_mqps": round(qq.shape[0] / tn / 1e6, 2),
+            "query_threads": len(th), **info})
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--skew", type=float, default=1.0, help="Zipf s (0.6, 1.0, 1.4)")
+    ap.add_argument("--legs", default=",".join(LEG_NAMES),
+                    help="single-sketch legs to run, comma-separated (main first: it is the headline)")
     ap.add_argument("--batch-ops", type=int, default=0,
-                    help="schedule batch size b (default: min(16 w, 2^23), the accuracy-backed rule)")
-    ap.add_argument("--scale", type=int, default=1, help="divide every size (quick runs)")
-    ap.add_argument("--tile", type=int, default=2048, help="ops per duplicate-merging tile")
-    ap.add_argument("--merge", choices=("tile", "batch"), default="batch",
-                    help="merge duplicate keys per tile or across the whole schedule batch")
+                    help="schedule batch size b of the headline (default: min(16 w, 2^23), the accuracy-backed rule)")
+    ap.add_argument("--scale", type=int, default=1, help="divide the 32M-op and flow sizes (quick runs)")
+    ap.add_argument("--tile", type=int, default=2048, help="ops per duplicate-merging tile (per-tile path)")
+    ap.add_argument("--merge", choices=("tile", "batch", "atomic"), default="batch",
+                    help="batch: batch-wide merge + owner-computes S1..S5; atomic: batch-wide merge + "
+                         "atomic S1..S5; tile: per-tile merging")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain copy of this many MiB (known traffic, for byte counters)")
     ap.add_argument("--workload", choices=("main", "multi", "serve"), default="main",
-                    help="main: one sketch, 32M ops (plus the multi and serve summaries unless "
+                    help="main: the single-sketch legs (plus the multi and serve summaries unless "
                          "--no-multi / --no-serve); multi: 1024 sketches in one group; serve: the "
                          "request loop alone")
     ap.add_argument("--no-multi", action="store_true")
@@ -532,10 +784,18 @@ def main():
     ap.add_argument("--trace-summary", metavar="TRACE_CSV",
                     help="print per-kind durations from a rocprofv3 kernel trace and exit")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/pmc_traffic.json from two rocprofv3 --pmc runs and exit")
+                    help="add one leg's PMC traffic (two rocprofv3 --pmc runs) to profiles/pmc_traffic.json "
+                         "and exit; the leg is the first of --legs")
     args = ap.parse_args()
-    if not args.batch_ops:
-        args.batch_ops = batch_for_width(2**20 // args.scale)   # the single-sketch workload's w
+    legs = [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in LEG_NAMES:
+            raise SystemExit(f"unknown leg {x}; choose from {LEG_NAMES}")
+
+    def b_of(leg, w):
+        if leg == "main" and args.batch_ops:
+            return args.batch_ops
+        return batch_for_width(w)
 
     if args.stats_summary:
         print(summarize_stats(args.stats_summary))
@@ -544,11 +804,12 @@ def main():
         print(summarize_trace(args.trace_summary))
         return
     if args.pmc_summary:
-        rec = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], workload_tag(args),
+        import sfgen
+        leg = legs[0]
+        w = {"small": 16384, "flows": 2**21 // args.scale}.get(leg, 2**20 // args.scale)
+        rec = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], workload_tag(leg, b_of(leg, w), args.scale),
                             args.copy_calibration_mib << 20)
-        with open(os.path.join(PROFILE_DIR, "pmc_traffic.json"), "w") as fh:
-            json.dump(rec, fh, indent=1)
-        print(json.dumps(rec))
+        print(json.dumps(store_pmc(rec)))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -572,229 +833,98 @@ def main():
         print(json.dumps({sh: run_serve(args, torch, np, sf, sfgen, sh, w) for sh in shapes}), flush=True)
         return
 
-    t_gen = time.time()
-    wl = sfgen.config_main(args.skew, scale=args.scale)
-    log(f"[bench] workload {wl.name}: {wl.n_ops} ops ({int(wl.ops.sum())} deletes), "
-        f"{wl.n_queries} queries, generated in {time.time() - t_gen:.1f}s")
-    n_del = int(wl.ops.sum())
-    n_ins = wl.n_ops - n_del
-    cells = wl.d * wl.w
-    dev = torch.device("cuda:0")
-    keys = torch.from_numpy(wl.keys.view(np.int32)).to(dev)
-    ops = torch.from_numpy(wl.ops).to(dev)
-    qk = torch.from_numpy(wl.queries.view(np.int32)).to(dev)
-    out = torch.empty(wl.n_queries, dtype=torch.int32, device=dev)
-    slim16 = torch.empty(cells, dtype=torch.int16, device=dev)
-    b = args.batch_ops
-    sk = sf.Sketch(wl.d, wl.w, wl.z, batch_ops=b)
-    sk.set_tile(args.tile)
-    sk.set_merge(args.merge == "batch")
-
-    def step():
-        sk.reset()
-        sk.update(keys, ops)
-        sf.sf_export_slim(sk._h, slim16)
-        sk.query(qk, out)
-
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=max(1, min(8, cpu_info()["threads_for_all_cores"] // 2)))
     if args.copy_calibration_mib:
         from paper_1701_04148_amd import micro
         nb = args.copy_calibration_mib << 20
-        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
         micro.copy(src, dst, nb)
         torch.cuda.synchronize()
         del src, dst
         log(f"[bench] calibration copy of {nb} bytes done")
-    for i in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} done")
-    ie0, de0 = sk.merge_stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = elapsed * 1e3 / args.steps
-    items = (wl.n_ops + wl.n_queries) * args.steps
-    value = items / elapsed / 1e6
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} M items/s")
-    ie1, de1 = sk.merge_stats()
-    # Per-kernel durations: the same steps again with a HIP event pair around every
-    # kernel on the sketch's stream.  The event packets add a gap of about 10 us after
-    # each kernel, so these steps are not the timed ones.
-    sk.profile(True)
-    sk.profile_read(reset=True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    prof_ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    prof = sk.profile_read(reset=True)
-    sk.profile(False)
-    log(f"[bench] profiled steps: {prof_ms_step:.3f} ms/step")
 
-    # PCIe-inclusive variant (never `value`): keys and op codes from pinned host memory
-    # through sf_update_host (copies overlap the updates), query keys copied in and
-    # answers copied out every step
-    host_fed = None
-    if not args.no_host_fed:
-        hk = torch.from_numpy(wl.keys.view(np.int32)).pin_memory()
-        ho = torch.from_numpy(wl.ops).pin_memory()
-        hq = torch.from_numpy(wl.queries.view(np.int32)).pin_memory()
-        hout = torch.empty(wl.n_queries, dtype=torch.int32).pin_memory()
+    result, leg_out, jobs = None, {}, {}
+    for leg in legs:
+        t_gen = time.time()
+        wl = leg_workload(leg, sfgen, args.scale)
+        b = b_of(leg, wl.w)
+        log(f"[bench] leg {leg}: workload {wl.name}: {wl.n_ops} ops, {wl.n_queries} queries, b={b}, "
+            f"generated in {time.time() - t_gen:.1f}s")
+        g = gpu_leg(args, torch, np, sf, wl, b, leg, args.steps, args.warmup)
+        g["wl_kb"] = wl.key_bytes
+        roof = roofline_of(g, wl, b, args.scale)
+        step_bytes = step_algorithmic_bytes(wl.d, g["n_ins"], g["n_del"], wl.n_queries, wl.key_bytes)
+        rec = {"value": round(g["value"], 2), "unit": "Mitems/s", "ms_per_step": round(g["ms_step"], 3),
+               "config": leg_config(leg, wl, b, g["n_del"]), "roofline": roof,
+               "step_roofline": {"achieved": round(step_bytes / (g["ms_step"] * 1e-3) / 1e9, 1), "unit": "GB/s",
+                                 "peak": HBM_PEAK_GBS,
+                                 "frac": round(step_bytes / (g["ms_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "bytes_per_step": step_bytes, "merged_entries_per_step": g["entries_per_step"]},
+               "kernels": g["kernels"], "profiled_ms_per_step": round(g["prof_ms"], 3),
+               "merge_path": ["tile", "batch+owner", "batch+atomic"][g["sk"].merge_path()]}
+        log(f"[bench] {leg}: roofline {json.dumps(roof)}")
+        if leg == "main":
+            result = {
+                "metric": METRIC, "value": rec["value"], "unit": "Mitems/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+                "data": "synthetic", "config": rec["config"], "roofline": roof,
+                "step_roofline": rec["step_roofline"], "kernels": g["kernels"],
+                "kernels_note": "HIP-event durations from the same steps run once more with events on",
+                "profiled_ms_per_step": rec["profiled_ms_per_step"], "merge_path": rec["merge_path"],
+                "phases_ms_per_step": {
+                    "update": round(sum(v["ms_total"] for k, v in g["kernels"].items()
+                                        if k not in ("query", "export")) / args.steps, 3),
+                    "export": round(g["kernels"].get("export", {}).get("ms_total", 0.0) / args.steps, 3),
+                    "query": round(g["kernels"].get("query", {}).get("ms_total", 0.0) / args.steps, 3)}}
+            if not args.no_cpu_baseline:
+                # the headline's CPU baseline alone on the host: batch and sequential updates on
+                # one core, queries on one core and on all cores
+                log("[bench] CPU oracle on the headline workload (1 thread per mode) ...")
+                orc = oracle_check(np, wl, b, g["answers"], time_seq=True, time_queries=True)
+                log(f"[bench] oracle: {json.dumps(orc['cpu_baseline'])}; parity {orc['parity_full_size']}")
+                if not orc["parity_full_size"]:
+                    raise SystemExit("GPU query answers differ from the oracle at full size")
+                result["cpu_baseline"] = orc["cpu_baseline"]
+                result["accuracy"] = orc["accuracy"]
+                result["parity_full_size"] = True
+            sk = g["sk"]
+            if not args.no_host_fed and wl.ops is not None:
+                result["host_fed"] = run_host_fed(torch, np, sf, g, wl, b, args.steps)
+            if not args.no_collector:
+                result["collector"] = run_collector(np, sk, g["step"], wl.queries, g["answers"])
+                log(f"[bench] collector: {json.dumps(result['collector'])}")
+            if not args.no_autotune and wl.ops is not None:
+                from paper_1701_04148_amd.tune import tune_batch
+                t_tune = time.time()
+                r = tune_batch(wl.d, wl.w, wl.z, wl.keys, wl.ops, wl.queries)
+                result["autotune_check"] = {"b": r.b, "rule_b": b, "ref_b": r.ref_b, "ref_are": round(r.ref_are, 5),
+                                            "bound": round(r.bound, 5),
+                                            "candidates": [[bb, round(a, 5), round(ms, 2), ok] for bb, a, ms, ok in r.table]}
+                log(f"[bench] autotuner on this workload ({time.time() - t_tune:.1f}s): b = {r.b} (rule {b})")
+        else:
+            leg_out[leg] = rec
+            if not args.no_cpu_baseline:
+                jobs[leg] = pool.submit(oracle_check, np, wl, b, g["answers"], True, False)
+        g["sk"].close()
+        del g
+        torch.cuda.empty_cache()
 
-        def host_step():
-            sk.reset()
-            sk.update_host(hk, ho, chunk_ops=b)
-            sf.sf_export_slim(sk._h, slim16)
-            qk.copy_(hq, non_blocking=True)
-            torch.cuda.current_stream().synchronize()
-            sk.query(qk, out)
-            sk.sync()
-            hout.copy_(out)
-
-        host_step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            host_step()
-        torch.cuda.synchronize()
-        hel = time.perf_counter() - t0
-        host_fed = {"value": round(items / hel / 1e6, 2), "unit": "Mitems/s",
-                    "ms_per_step": round(hel * 1e3 / args.steps, 3),
-                    "note": "keys + op codes + query keys H2D from pinned memory and answers D2H "
-                            "each step (sf_update_host, copy chunks of b ops overlapping the updates)"}
-        log(f"[bench] host-fed (PCIe-inclusive): {host_fed['ms_per_step']} ms/step, {host_fed['value']} M items/s")
-
-    # sanity on the device result: Fat row sums = net stream weight (Section 3.4 CM property)
-    fat = sk.export_fat()
-    rows = fat.reshape(wl.d, -1).astype(np.int64).sum(axis=1)
-    if not (rows == n_ins - n_del).all():
-        raise SystemExit(f"Fat row sums {rows} != net weight {n_ins - n_del}")
-    gpu_answers = out.cpu().numpy().view(np.uint32).copy()
-
-    collector = None
-    if not args.no_collector:
-        collector = run_collector(np, sk, step, wl.queries, gpu_answers)
-        log(f"[bench] collector: {json.dumps(collector)}")
-
-    # per-kernel accounting from the events on the sketch's stream
-    kernels = {}
-    units = dict(ins=n_ins * args.steps, dels=n_del * args.steps, ops=wl.n_ops * args.steps,
-                 q=wl.n_queries * args.steps, cells=cells * args.steps, mixed=True,
-                 ie=(ie1 - ie0) if args.merge == "batch" else n_ins * args.steps,
-                 de=(de1 - de0) if args.merge == "batch" else n_del * args.steps)
-    for kind, (ms, launches, _) in prof.items():
-        if not launches:
-            continue
-        byt = algorithmic_bytes(kind, wl.d, units)
-        acc = random_accesses(kind, wl.d, units)
-        kernels[kind] = dict(ms_total=round(ms, 3), launches=launches,
-                             avg_launch_us=round(ms * 1e3 / launches, 2),
-                             alg_gbs=round(byt / (ms * 1e-3) / 1e9, 1),
-                             g_accesses_s=round(acc / (ms * 1e-3) / 1e9, 2) if acc else None)
-    dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
-    dk = kernels[dom]
-    alg_per_launch = algorithmic_bytes(dom, wl.d, units) / dk["launches"]
-    achieved = alg_per_launch / (dk["avg_launch_us"] * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(dom, workload_tag(args))}
-    log(f"[bench] kernels: {json.dumps(kernels)}")
-
-    step_bytes = step_algorithmic_bytes(wl.d, n_ins, n_del, wl.n_queries)
-    result = {
-        "metric": METRIC, "value": round(value, 2), "unit": "Mitems/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": "one SF-sketch d=4, Fat 4x2^22 u32 (w=2^20, z=4), Slim 4x2^20 u16; "
-                               f"{wl.n_ops} uint32 ops Zipf(s={args.skew}) over {wl.meta['n_universe']} keys "
-                               f"with {n_del} deletes; export Slim; {wl.n_queries} queries "
-                               "(present + absent); keys resident in HBM",
-                   "sketches": 1, "d": wl.d, "w": wl.w, "z": wl.z, "ops": wl.n_ops, "deletes": n_del,
-                   "queries": wl.n_queries, "zipf_s": args.skew, "batch_ops": b, "tile_ops": args.tile, "merge": args.merge,
-                   "scale": args.scale},
-        "roofline": roofline,
-        "step_roofline": {"achieved": round(step_bytes / (ms_step * 1e-3) / 1e9, 1), "unit": "GB/s",
-                          "peak": HBM_PEAK_GBS,
-                          "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                          "bytes_per_step": step_bytes,
-                          "merged_entries_per_step": [units["ie"] // args.steps, units["de"] // args.steps]},
-        "kernels": kernels,
-        "kernels_note": "HIP-event durations from the same steps run once more with events on",
-        "host_fed": host_fed,
-        "collector": collector,
-        "phases_ms_per_step": {
-            "update": round(sum(v["ms_total"] for k, v in kernels.items() if k not in ("query", "export"))
-                            / args.steps, 3),
-            "export": round(kernels.get("export", {}).get("ms_total", 0.0) / args.steps, 3),
-            "query": round(kernels.get("query", {}).get("ms_total", 0.0) / args.steps, 3)},
-        "profiled_ms_per_step": round(prof_ms_step, 3),
-    }
-
-    if not args.no_autotune:
-        # what the autotuner would pick for this workload (the run above uses the rule)
-        from paper_1701_04148_amd.tune import tune_batch
-        t_tune = time.time()
-        r = tune_batch(wl.d, wl.w, wl.z, wl.keys, wl.ops, wl.queries)
-        result["autotune_check"] = {"b": r.b, "rule_b": b, "ref_b": r.ref_b, "ref_are": round(r.ref_are, 5),
-                                    "bound": round(r.bound, 5),
-                                    "candidates": [[bb, round(a, 5), round(ms, 2), ok] for bb, a, ms, ok in r.table]}
-        log(f"[bench] autotuner on this workload ({time.time() - t_tune:.1f}s): b = {r.b} "
-            f"(rule {b}); table {result['autotune_check']['candidates']}")
+    if result is None:      # the headline leg was not asked for: report the first leg as the line
+        first = legs[0]
+        rec = leg_out[first]
+        result = {"metric": METRIC, "value": rec["value"], "unit": "Mitems/s", "n_gpus": 1, "steps": args.steps,
+                  "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True,
+                  "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+                  "config": rec["config"], "roofline": rec["roofline"], "kernels": rec["kernels"]}
 
     if not args.no_micro:
         log("[bench] random-access ceilings ...")
-        ceil = micro_ceilings(torch)
-        result["random_access_ceilings_g_per_s"] = ceil
-        log(f"[bench] ceilings {json.dumps(ceil)}")
-        # the dominant kernel against the measured rate of its own kind of access, at the
-        # footprint of the sketch's cell records (80 MiB: between the 64 and 256 MiB points)
-        probe = {"fat_add": ("atomic_add_u32", "u32 atomic adds"), "fat_sub": ("atomic_add_u32", "u32 atomic adds"),
-                 "snapshot": ("gather_u32", "random record reads"), "query": ("gather_u32", "random reads")}
-        if dom in probe and dk.get("g_accesses_s"):
-            key, what = probe[dom]
-            top = ceil["64MiB"][key]
-            result["roofline"]["random_access"] = {
-                "what": what, "achieved_g_per_s": dk["g_accesses_s"], "ceiling_g_per_s": top,
-                "frac": round(dk["g_accesses_s"] / top, 3), "ceiling": "measured by bench.py (libsf_micro), 64 MiB table"}
-        elif dom == "raise" and dk.get("g_accesses_s"):
-            # S3 mixes two kinds: d record reads per insert entry, then an atomic max on
-            # each of its cells still below the target (at most d, often fewer)
-            reads = dk["g_accesses_s"] / 2
-            result["roofline"]["random_access"] = {
-                "what": "d record reads per insert entry, then at most d atomic max",
-                "reads_g_per_s": round(reads, 2), "gather_ceiling_g_per_s": ceil["64MiB"]["gather_u32"],
-                "atomics_g_per_s_at_most": round(reads, 2),
-                "atomic_ceiling_g_per_s": ceil["64MiB"]["atomic_add_u32"],
-                "ceiling": "measured by bench.py (libsf_micro), 64 MiB table"}
+        result["random_access_ceilings_g_per_s"] = micro_ceilings(torch)
+        log(f"[bench] ceilings {json.dumps(result['random_access_ceilings_g_per_s'])}")
 
-    if not args.no_cpu_baseline:
-        import oracle
-        log("[bench] CPU oracle (single thread, batch schedule, same inputs) ...")
-        ref = oracle.Sketch(wl.d, wl.w, wl.z)
-        c0 = time.perf_counter()
-        rc = ref.batch(wl.keys, wl.ops, b)
-        ans = ref.query(wl.queries)
-        c_el = time.perf_counter() - c0
-        if rc:
-            raise SystemExit(f"oracle failed {rc}")
-        result["cpu_baseline"] = {"value": round((wl.n_ops + wl.n_queries) / c_el / 1e6, 3),
-                                  "unit": "Mitems/s", "cores": 1, "kind": "oracle",
-                                  "sample": f"one full step of the same workload ({wl.n_ops} ops + "
-                                            f"{wl.n_queries} queries), batch schedule b={b}, "
-                                            f"{c_el:.1f}s on 1 thread"}
-        result["parity_full_size"] = bool(np.array_equal(ans, gpu_answers))
-        log(f"[bench] oracle {c_el:.1f}s; GPU answers bit-exact: {result['parity_full_size']}")
-        if not result["parity_full_size"]:
-            raise SystemExit("GPU query answers differ from the oracle at full size")
-
-    sk.close()
-    del sk, keys, ops, qk, out
-    torch.cuda.empty_cache()
     if not args.no_multi:
         multi = run_multi(args, torch, np, sf, sfgen)
         result["sketches_1024"] = {k: multi[k] for k in ("value", "unit", "ms_per_step", "config",
@@ -809,7 +939,55 @@ def main():
         shapes = ("flows", "small") if args.serve_shape == "both" else (args.serve_shape,)
         for sh in shapes:
             result["serving" if sh == "flows" else f"serving_{sh}"] = run_serve(args, torch, np, sf, sfgen, sh, w)
+
+    for leg, fut in jobs.items():
+        log(f"[bench] waiting for the oracle of leg {leg} ...")
+        orc = fut.result()
+        if not orc["parity_full_size"]:
+            raise SystemExit(f"{leg}: GPU query answers differ from the oracle at full size")
+        cb = dict(orc["cpu_baseline"])
+        cb["note"] = "timed while other legs ran on the GPU and other oracle runs shared the host"
+        leg_out[leg].update(cpu_baseline=cb, accuracy=orc.get("accuracy"), parity_full_size=True)
+        log(f"[bench] {leg}: oracle {json.dumps(cb)}")
+    pool.shutdown()
+    if leg_out:
+        result["legs"] = leg_out
     print(json.dumps(result), flush=True)
+
+
+def run_host_fed(torch, np, sf, g, wl, b: int, steps: int) -> dict:
+    """PCIe-inclusive variant (never `value`): keys and op codes from pinned host memory
+    through sf_update_host (copies overlap the updates), query keys copied in and answers
+    copied out every step."""
+    sk, qk, out, slim16 = g["sk"], g["qk"], g["out"], g["slim16"]
+    hk = torch.from_numpy(wl.keys.view(np.int32)).pin_memory()
+    ho = torch.from_numpy(wl.ops).pin_memory()
+    hq = torch.from_numpy(wl.queries.view(np.int32)).pin_memory()
+    hout = torch.empty(wl.n_queries, dtype=torch.int32).pin_memory()
+
+    def host_step():
+        sk.reset()
+        sk.update_host(hk, ho, chunk_ops=b)
+        sf.sf_export_slim(sk._h, slim16)
+        qk.copy_(hq, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        sk.query(qk, out)
+        sk.sync()
+        hout.copy_(out)
+
+    host_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        host_step()
+    torch.cuda.synchronize()
+    hel = time.perf_counter() - t0
+    items = (wl.n_ops + wl.n_queries) * steps
+    rec = {"value": round(items / hel / 1e6, 2), "unit": "Mitems/s", "ms_per_step": round(hel * 1e3 / steps, 3),
+           "note": "keys + op codes + query keys H2D from pinned memory and answers D2H "
+                   "each step (sf_update_host, copy chunks of b ops overlapping the updates)"}
+    log(f"[bench] host-fed (PCIe-inclusive): {rec['ms_per_step']} ms/step, {rec['value']} M items/s")
+    return rec
 
 
 if __name__ == "__main__":

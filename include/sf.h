@@ -189,7 +189,12 @@ int sf_set_tile(sf_sketch *sk, uint32_t tile_ops);
  * plain stores; other shapes, and mode 2, use one device-scope atomic per
  * merged key and row.  0 merges per tile of consecutive ops.  Results are
  * identical in every mode (Section 3.4 insertion and Section 3.5 deletion
- * are sums, maxima and minima per counter).  SF_EINVAL for other values. */
+ * are sums, maxima and minima per counter).  The owner path's buffers (the
+ * pairs of two batches, their positions and snapshots: about 28 * d + 2
+ * bytes per op of batch_ops, counted in sf_footprint) are a separate
+ * allocation made by sf_create: modes 0 and 2
+ * free it (after the stream drains), mode 1 allocates it again (SF_ENOMEM if
+ * it cannot).  SF_EINVAL for other values. */
 int sf_set_merge(sf_sketch *sk, int batch_wide);
 
 /* The path sf_update takes now: 0 per-tile merging, 1 batch-wide merge with

@@ -114,6 +114,8 @@ oracle_sketch *oracle_create(uint32_t d, uint32_t w, uint32_t z, uint32_t key_by
 {
     if (d == 0 || w == 0 || z == 0 || key_bytes == 0)
         return NULL;
+    if (d > 64)  /* the per-key index buffers of the query and histogram helpers hold 64 rows */
+        return NULL;
     if ((uint64_t)w * z > (1ull << 32))
         return NULL;
     oracle_sketch *s = (oracle_sketch *)calloc(1, sizeof(*s));

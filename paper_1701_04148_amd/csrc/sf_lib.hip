@@ -59,9 +59,10 @@ struct sf_sketch {
     uint32_t* hist;   //              per-group bucket histograms     [b/8192+1][2048]
     MergeChunk* chunks;//             key range of every merge chunk
     MergeMeta* meta;
-    bool owner_ok;    // the shape fits the owner-computes path (buffers allocated)
+    bool owner_ok;    // the shape fits the owner-computes path
     bool owner_on;    // S1..S5 by (row, cell range) owners (else the entry kernels)
     OwnerBufs own;
+    char* own_base = nullptr;  // the owner path's buffers: their own allocation, held while mode 1 is set
     Profiler prof;
     // host-fed updates (sf_update_host): two device chunk buffers (keys, then
     // op codes), their events and a copy stream, made on first use
@@ -86,10 +87,11 @@ bool live(const sf_sketch* s) {
 struct Sizes {
     uint64_t fat, slim, stage, view, bpre, asnap, part, ent_key, ent_cnt, meta, hist, chunks;
     uint64_t pairs = 0, pos = 0, res = 0, level = 0, hmat = 0, pmeta = 0;  // owner path
-    uint64_t total() const {
-        return fat + slim + stage + view + bpre + asnap + part + ent_key + ent_cnt + meta + hist + chunks + pairs +
-               pos + res + level + hmat + pmeta;
+    uint64_t base() const {
+        return fat + slim + stage + view + bpre + asnap + part + ent_key + ent_cnt + meta + hist + chunks;
     }
+    uint64_t owner() const { return pairs + pos + res + level + hmat + pmeta; }
+    uint64_t total() const { return base() + owner(); }
 };
 
 Sizes sizes_of(const sf_config* c) {
@@ -239,6 +241,41 @@ int query_common(Profiler* prof, const sf_config* c, const Geom& g, const void* 
     return e == hipSuccess ? SF_OK : device_fail(e, "query launch");
 }
 
+// The owner path's buffers (a separate allocation, so that a sketch switched
+// to another merge mode gives them back).
+int owner_alloc(sf_sketch* s) {
+    const Sizes sz = sizes_of(&s->cfg);
+    char* ob = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&ob), sz.owner());
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? fail(SF_ENOMEM, "owner-path buffers: out of device memory")
+                                        : device_fail(e, "owner-path buffers");
+    }
+    s->own_base = ob;
+    s->own.pairs[0] = reinterpret_cast<uint64_t*>(ob);
+    s->own.pairs[1] = reinterpret_cast<uint64_t*>(ob + sz.pairs / 2);
+    s->own.pos = reinterpret_cast<uint32_t*>(ob + sz.pairs);
+    s->own.res = reinterpret_cast<uint64_t*>(ob + sz.pairs + sz.pos);
+    s->own.level = reinterpret_cast<uint16_t*>(ob + sz.pairs + sz.pos + sz.res);
+    s->own.hmat = reinterpret_cast<uint32_t*>(ob + sz.pairs + sz.pos + sz.res + sz.level);
+    s->own.pm[0] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat);
+    s->own.pm[1] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat + sz.pmeta / 2);
+    s->own.cur = 0;
+    s->own.pending = false;
+    s->owner_on = true;
+    return SF_OK;
+}
+
+int owner_free(sf_sketch* s) {
+    s->owner_on = false;
+    if (!s->own_base) return SF_OK;
+    hipError_t e = hipStreamSynchronize(s->stream);  // no launch may still read them
+    if (e == hipSuccess) e = hipFree(s->own_base);
+    s->own_base = nullptr;
+    return e == hipSuccess ? SF_OK : device_fail(e, "owner-path buffers free");
+}
+
 // Collector-side queries read a dense uint16 Slim one row per XCD (as
 // sf_query does after an export) once it outgrows an XCD's 4 MB L2.
 bool slim_by_rows(const sf_config& c) { return kXcds % c.d == 0 && uint64_t(c.d) * c.w * 2 > (4ull << 20); }
@@ -314,7 +351,7 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     s->merge_batch = true;
     hipError_t e = hipGetDevice(&s->device);
     char* base = nullptr;
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&base), sz.total());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&base), sz.base());
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete s;
@@ -337,18 +374,11 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     s->hist = reinterpret_cast<uint32_t*>(mq + sz.part + sz.ent_key + sz.ent_cnt + sz.meta);
     s->chunks = reinterpret_cast<MergeChunk*>(mq + sz.part + sz.ent_key + sz.ent_cnt + sz.meta + sz.hist);
     s->owner_ok = owner_geom(cfg, &s->own.og);
-    s->owner_on = s->owner_ok;
-    if (s->owner_ok) {
-        char* ob = mq + sz.part + sz.ent_key + sz.ent_cnt + sz.meta + sz.hist + sz.chunks;
-        s->own.pairs[0] = reinterpret_cast<uint64_t*>(ob);
-        s->own.pairs[1] = reinterpret_cast<uint64_t*>(ob + sz.pairs / 2);
-        s->own.pos = reinterpret_cast<uint32_t*>(ob + sz.pairs);
-        s->own.res = reinterpret_cast<uint64_t*>(ob + sz.pairs + sz.pos);
-        s->own.level = reinterpret_cast<uint16_t*>(ob + sz.pairs + sz.pos + sz.res);
-        s->own.hmat = reinterpret_cast<uint32_t*>(ob + sz.pairs + sz.pos + sz.res + sz.level);
-        s->own.pm[0] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat);
-        s->own.pm[1] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat +
-                                                   sz.pmeta / 2);
+    s->owner_on = false;
+    if (s->owner_ok && (rc = owner_alloc(s))) {
+        (void)hipFree(base);
+        delete s;
+        return rc;
     }
     e = hipMemsetAsync(s->meta, 0, sizeof(MergeMeta), s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(base, 0, sz.fat + sz.slim, s->stream);
@@ -379,6 +409,7 @@ int sf_destroy(sf_sketch* s) {
         if (s->consumed[i]) (void)hipEventDestroy(s->consumed[i]);
     }
     if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+    if (s->own_base) (void)hipFree(s->own_base);
     hipError_t e2 = hipFree(s->fat);
     delete s;
     if (e != hipSuccess) return device_fail(e, "sf_destroy sync");
@@ -601,8 +632,8 @@ int sf_set_merge(sf_sketch* s, int batch_wide) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
     if (batch_wide < 0 || batch_wide > 2) return fail(SF_EINVAL, "merge mode must be 0, 1 or 2");
     s->merge_batch = batch_wide != 0;
-    s->owner_on = batch_wide == 1 && s->owner_ok;
-    return SF_OK;
+    if (batch_wide == 1 && s->owner_ok) return s->own_base ? (s->owner_on = true, SF_OK) : owner_alloc(s);
+    return owner_free(s);
 }
 
 int sf_merge_path(sf_sketch* s) {

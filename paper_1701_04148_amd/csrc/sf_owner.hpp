@@ -324,7 +324,18 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(Geom g, OwnerGeom og, 
     const uint32_t ncells = min(1u << og.cr_shift, g.w - cell0);
     const uint32_t nw = ncells * rs;
     uint32_t* rec0 = rec_all + (size_t(row) * g.w + cell0) * rs;
-    for (uint32_t i = threadIdx.x; i < nw; i += kOwnThreads) L[i] = rec0[i];
+    // the range in 16-byte pieces where it is 16-byte aligned, several loads in
+    // flight per thread
+    const bool vec = (reinterpret_cast<uintptr_t>(rec0) & 15u) == 0;
+    const uint32_t n4 = vec ? nw / 4 : 0u;
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(rec0);
+        uint4* dst = reinterpret_cast<uint4*>(L);
+#pragma unroll 4
+        for (uint32_t i = threadIdx.x; i < n4; i += kOwnThreads) dst[i] = src[i];
+#pragma unroll 4
+        for (uint32_t i = 4 * n4 + threadIdx.x; i < nw; i += kOwnThreads) L[i] = rec0[i];
+    }
     __syncthreads();
     if (fi0 != fi1 || fd0 != fd1) {
         for (uint32_t p = fi0 + threadIdx.x; p < fi1; p += kOwnThreads) {
@@ -386,7 +397,14 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(Geom g, OwnerGeom og, 
         }
         __syncthreads();
     }
-    for (uint32_t i = threadIdx.x; i < nw; i += kOwnThreads) rec0[i] = L[i];
+    {
+        uint4* dst = reinterpret_cast<uint4*>(rec0);
+        const uint4* src = reinterpret_cast<const uint4*>(L);
+#pragma unroll 4
+        for (uint32_t i = threadIdx.x; i < n4; i += kOwnThreads) dst[i] = src[i];
+#pragma unroll 4
+        for (uint32_t i = 4 * n4 + threadIdx.x; i < nw; i += kOwnThreads) rec0[i] = L[i];
+    }
 }
 
 }  // namespace sfk
