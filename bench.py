@@ -176,10 +176,21 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int
             "kernels": kernels}
 
 
-def store_pmc(rec: dict) -> dict:
-    """Adds one workload's PMC record to profiles/pmc_traffic.json (records taken on
-    other kernel sources are dropped)."""
-    path = os.path.join(PROFILE_DIR, "pmc_traffic.json")
+def format_pmc(rec: dict) -> str:
+    """Text table of one workload's PMC record (raw KiB per dispatch, calibrated bytes)."""
+    lines = [f"# workload {rec['workload']}; kernel sources digest {rec['source_digest']}",
+             f"# calibration: a plain {rec['copy_calibration']['bytes']} B copy kernel: FETCH_SIZE x "
+             f"{rec['copy_calibration']['fetch_scale']}, WRITE_SIZE x {rec['copy_calibration']['write_scale']}",
+             f"{'kernel':16s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'bytes/launch(calibrated)':>26s}"]
+    for k, v in sorted(rec["kernels"].items(), key=lambda kv: -kv[1]["hbm_bytes_per_launch"]):
+        lines.append(f"{k:16s} {v['fetch_kib_raw']:12.1f} {v['write_kib_raw']:12.1f} {v['hbm_bytes_per_launch']:26,d}")
+    return "\n".join(lines)
+
+
+def store_pmc(rec: dict, path: str = "") -> dict:
+    """Adds one workload's PMC record to the PMC summary file (profiles/pmc_traffic.json by
+    default; records taken on other kernel sources are dropped)."""
+    path = path or os.path.join(PROFILE_DIR, "pmc_traffic.json")
     try:
         with open(path) as fh:
             allrec = json.load(fh)
@@ -316,11 +327,11 @@ def run_multi(args, torch, np, sf, sfgen):
             i = int(np.argmax(np.where(m.w == w, lens, -1)))
             k_i, o_i, q_i = m.part(i)
             n = min(k_i.shape[0], 1 << 21)
-            r = tune_batch(m.d, w, m.z, k_i[:n], o_i[:n], q_i)
+            r = tune_batch(m.d, w, m.z, k_i[:n], o_i[:n], q_i, modes=(2,))   # the group's kernels
             batch_of_w[w] = r.b
             tuned[str(w)] = {"b": r.b, "rule_b": batch_for_width(w), "ref_b": r.ref_b,
                              "ref_are": round(r.ref_are, 5), "bound": round(r.bound, 5),
-                             "candidates": [[b, round(a, 5), round(ms, 2), ok] for b, a, ms, ok in r.table]}
+                             "candidates": [[b, round(a, 5), round(ms, 2), ok] for b, a, ms, ok, _ in r.table]}
         log(f"[bench] autotuned batch per width in {time.time() - t_tune:.1f}s: "
             f"{ {w: v['b'] for w, v in tuned.items()} } (rule min(16 w, 2^23): "
             f"{ {w: v['rule_b'] for w, v in tuned.items()} })")
@@ -459,7 +470,11 @@ def serve_workload(args, sfgen):
 
 
 def run_serve(args, torch, np, sf, sfgen, shape_name, w=None):
-    """4096 streams of insert/delete/query requests through the continuous-batching loop."""
+    """4096 streams of insert/delete/query requests through the continuous-batching loop:
+    the saturation rate (every request visible at once), then arrivals replayed at each
+    offered load of --serve-loads (fractions of saturation) with per-kind latency, and a
+    sample of streams checked against the CPU oracle (their closing Slim and every query
+    answer)."""
     from paper_1701_04148_amd.serve import Server
     if w is None:
         w = serve_workload(args, sfgen)
@@ -472,43 +487,82 @@ def run_serve(args, torch, np, sf, sfgen, shape_name, w=None):
     slots, _ = pool.capacity()
     dev = torch.device("cuda:0")
     keys = torch.from_numpy(w.pool.view(np.int32)).to(dev)
-    answers = torch.empty(1 << 20, dtype=torch.int32, device=dev)          # answers are discarded
+    # a delete's keys (its pieces of the pool) joined on the device before the loop starts
+    joined = {(r.stream, r.seq): torch.cat([keys[o:o + c] for o, c in r.pieces]) for r in w.requests if r.pieces}
+    torch.cuda.synchronize()
+    answers = torch.empty(1 << 20, dtype=torch.int32, device=dev)          # answers are discarded ...
     sink = torch.empty(shape["d"] * shape["w"], dtype=torch.int16, device=dev)  # stands for the collector
+    check = sorted({0, w.n_streams // 2, w.n_streams - 1})                # ... except for these streams
+    c_slim = {st: torch.zeros(shape["d"] * shape["w"], dtype=torch.int16, device=dev) for st in check}
+    c_ans = {(r.stream, r.seq): torch.full((r.n,), -1, dtype=torch.int32, device=dev)
+             for r in w.requests if r.stream in c_slim and r.kind == sf.SF_REQ_QUERY}
     srv = Server(pool, max_launch_keys=args.serve_launch_keys, max_in_flight=3)
 
     def go(reqs, realtime):
-        return srv.run(reqs, key_of=lambda r: keys[r.off:r.off + r.n], out_of=lambda r: answers[:r.n],
-                       export_to=lambda st: sink, realtime=realtime)
+        return srv.run(reqs, key_of=lambda r: joined[(r.stream, r.seq)] if r.pieces else keys[r.off:r.off + r.n],
+                       out_of=lambda r: c_ans.get((r.stream, r.seq), answers[:r.n]),
+                       export_to=lambda st: c_slim.get(st, sink), realtime=realtime)
 
     warm = [r for r in w.requests if r.stream < 8]
     go(warm, False)
     pool.sync()
     sat = go(w.requests, False)
     pool.sync()
+    torch.cuda.synchronize()
     log(f"[bench] serving ({shape_name}) saturation: {sat.keys_per_s / 1e6:.1f} M keys/s, {sat.launches} launches, "
         f"{sat.mean_requests_per_launch:.1f} requests/launch, peak resident {sat.peak_resident}/{slots}")
+    # the sampled streams against the oracle: each request is its own batch-schedule call
+    import oracle
+    verified = 0
+    for st in check:
+        ref = oracle.Sketch(shape["d"], shape["w"], shape["z"])
+        for r in sorted((r for r in w.requests if r.stream == st), key=lambda r: r.seq):
+            k = w.keys_of(r)
+            if r.kind == sf.SF_REQ_QUERY:
+                got = c_ans[(r.stream, r.seq)].cpu().numpy().view(np.uint32)
+                if not np.array_equal(got, ref.query(k)):
+                    raise SystemExit(f"serving ({shape_name}): stream {st} query {r.seq} differs from the oracle")
+                verified += 1
+            else:
+                ops = np.full(r.n, 1 if r.kind == sf.SF_REQ_DELETE else 0, np.uint8)
+                if ref.batch(k, ops, cfg.batch_ops, checked=True):
+                    raise SystemExit("serving workload is not strict-turnstile")
+        slim = c_slim[st].cpu().numpy().view(np.uint16).reshape(shape["d"], shape["w"])
+        if not np.array_equal(slim, ref.slim()):
+            raise SystemExit(f"serving ({shape_name}): stream {st}'s Slim differs from the oracle")
+    log(f"[bench] serving ({shape_name}): streams {check} equal to the oracle ({verified} query answers, Slims)")
     span = max(r.arrival for r in w.requests)
     offered = total_keys / span
-    f = offered / (args.serve_load * sat.keys_per_s)
     import copy
-    paced = [copy.copy(r) for r in w.requests]
-    for r in paced:
-        r.arrival *= f
-    res = go(paced, True)
-    pool.sync()
-    log(f"[bench] serving ({shape_name}) at {args.serve_load:.2f} x saturation: {res.keys_per_s / 1e6:.1f} M keys/s, "
-        f"latency {res.latency_ms}, queueing {res.queue_ms}")
+    sweep = []
+    for load in [float(x) for x in args.serve_loads.split(",") if x]:
+        f = offered / (load * sat.keys_per_s)
+        paced = [copy.copy(r) for r in w.requests]
+        for r in paced:
+            r.arrival *= f
+        res = go(paced, True)
+        pool.sync()
+        sweep.append({"offered_load": load, "value": round(res.keys_per_s / 1e6, 2), "unit": "Mitems/s",
+                      "latency_ms": res.latency_ms, "queueing_ms": res.queue_ms,
+                      "latency_by_kind_ms": res.latency_by_kind_ms, "launches": res.launches,
+                      "requests_per_launch": round(res.mean_requests_per_launch, 2),
+                      "peak_resident_sketches": res.peak_resident})
+        log(f"[bench] serving ({shape_name}) at {load:.2f} x saturation: {res.keys_per_s / 1e6:.1f} M keys/s, "
+            f"latency {res.latency_ms}, by kind {res.latency_by_kind_ms}")
     pool.close()
-    return {"workload": f"{w.n_streams} streams x 16 requests (insert/delete/query 0.7/0.1/0.2, "
-                        "log-uniform 1K-1M uint32 keys, Zipf 1.0), per-stream sketch "
-                        f"d={shape['d']} Fat {shape['d']}x{shape['w'] * 4} u32, 64 GiB HBM budget "
-                        f"({slots} resident sketches)",
-            "saturation_mitems_s": round(sat.keys_per_s / 1e6, 2),
-            "offered_load": args.serve_load,
-            "value": round(res.keys_per_s / 1e6, 2), "unit": "Mitems/s",
-            "latency_ms": res.latency_ms, "queueing_ms": res.queue_ms,
-            "launches": res.launches, "requests_per_launch": round(res.mean_requests_per_launch, 2),
-            "peak_resident_sketches": res.peak_resident, "slots": slots}
+    del joined
+    torch.cuda.empty_cache()
+    head = min(sweep, key=lambda x: abs(x["offered_load"] - 0.75)) if sweep else None
+    out = {"workload": f"{w.n_streams} streams x 16 requests (insert/delete/query 0.7/0.1/0.2, "
+                       "log-uniform 1K-1M uint32 keys, Zipf 1.0; deletes drawn uniformly from the stream's live "
+                       f"occurrences), per-stream sketch d={shape['d']} Fat {shape['d']}x{shape['w'] * 4} u32, "
+                       f"64 GiB HBM budget ({slots} resident sketches)",
+           "saturation_mitems_s": round(sat.keys_per_s / 1e6, 2), "slots": slots,
+           "oracle_checked_streams": check, "oracle_checked_query_answers": verified, "sweep": sweep}
+    if head:
+        out.update({"offered_load": head["offered_load"], "value": head["value"], "unit": "Mitems/s",
+                    "latency_ms": head["latency_ms"], "latency_by_kind_ms": head["latency_by_kind_ms"]})
+    return out
 
 
 def run_collector(np, sk, step, queries, answers, snapshots=20):
@@ -553,6 +607,7 @@ def run_collector(np, sk, step, queries, answers, snapshots=20):
 
 
 LEG_NAMES = ("main", "main_s0.6", "main_s1.4", "small", "flows")
+MERGE_PATHS = ("tile", "batch, owner for batches >= w", "batch+atomic", "batch+owner always")
 
 
 def leg_workload(leg: str, sfgen, scale: int = 1):
@@ -597,7 +652,7 @@ def gpu_leg(args, torch, np, sf, wl, b: int, leg: str, steps: int, warmup: int) 
     n_ins = wl.n_ops - n_del
     sk = sf.Sketch(wl.d, wl.w, wl.z, key_bytes=kb, batch_ops=b)
     sk.set_tile(args.tile)
-    sk.set_merge(1 if args.merge == "batch" else (2 if args.merge == "atomic" else 0))
+    sk.set_merge({"batch": 1, "atomic": 2, "owner": 3, "tile": 0}[args.merge])
 
     def step():
         sk.reset()
@@ -754,9 +809,10 @@ def main():
                     help="schedule batch size b of the headline (default: min(16 w, 2^23), the accuracy-backed rule)")
     ap.add_argument("--scale", type=int, default=1, help="divide the 32M-op and flow sizes (quick runs)")
     ap.add_argument("--tile", type=int, default=2048, help="ops per duplicate-merging tile (per-tile path)")
-    ap.add_argument("--merge", choices=("tile", "batch", "atomic"), default="batch",
-                    help="batch: batch-wide merge + owner-computes S1..S5; atomic: batch-wide merge + "
-                         "atomic S1..S5; tile: per-tile merging")
+    ap.add_argument("--merge", choices=("tile", "batch", "atomic", "owner"), default="batch",
+                    help="batch: batch-wide merge + owner-computes S1..S5 for batches of at least w ops; "
+                         "atomic: batch-wide merge + atomic S1..S5; owner: owner-computes for every batch; "
+                         "tile: per-tile merging")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -777,7 +833,8 @@ def main():
     ap.add_argument("--serve-shape", choices=tuple(SERVE_SHAPES) + ("both",), default="both",
                     help="per-stream sketch: flows (d=8, the flow configuration; admission binds), "
                          "small (d=4, Fat 4 x 2^20; every stream fits) or both")
-    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / saturation")
+    ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9",
+                    help="offered loads (fractions of the measured saturation) the arrivals are replayed at")
     ap.add_argument("--serve-launch-keys", type=int, default=1 << 24)
     ap.add_argument("--stats-summary", metavar="STATS_CSV",
                     help="print a rocprofv3 --stats kernel table and exit")
@@ -786,6 +843,7 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="add one leg's PMC traffic (two rocprofv3 --pmc runs) to profiles/pmc_traffic.json "
                          "and exit; the leg is the first of --legs")
+    ap.add_argument("--pmc-out", default="", help="PMC summary file to add to (default profiles/pmc_traffic.json)")
     args = ap.parse_args()
     legs = [x for x in args.legs.split(",") if x]
     for x in legs:
@@ -809,7 +867,8 @@ def main():
         w = {"small": 16384, "flows": 2**21 // args.scale}.get(leg, 2**20 // args.scale)
         rec = summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], workload_tag(leg, b_of(leg, w), args.scale),
                             args.copy_calibration_mib << 20)
-        print(json.dumps(store_pmc(rec)))
+        store_pmc(rec, args.pmc_out)
+        print(format_pmc(rec))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -863,7 +922,7 @@ def main():
                                  "frac": round(step_bytes / (g["ms_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "bytes_per_step": step_bytes, "merged_entries_per_step": g["entries_per_step"]},
                "kernels": g["kernels"], "profiled_ms_per_step": round(g["prof_ms"], 3),
-               "merge_path": ["tile", "batch+owner", "batch+atomic"][g["sk"].merge_path()]}
+               "merge_path": MERGE_PATHS[g["sk"].merge_path()]}
         log(f"[bench] {leg}: roofline {json.dumps(roof)}")
         if leg == "main":
             result = {
@@ -893,17 +952,24 @@ def main():
             sk = g["sk"]
             if not args.no_host_fed and wl.ops is not None:
                 result["host_fed"] = run_host_fed(torch, np, sf, g, wl, b, args.steps)
+            result["query_pipeline"] = run_query_pipeline(torch, np, g, wl)
             if not args.no_collector:
                 result["collector"] = run_collector(np, sk, g["step"], wl.queries, g["answers"])
                 log(f"[bench] collector: {json.dumps(result['collector'])}")
             if not args.no_autotune and wl.ops is not None:
                 from paper_1701_04148_amd.tune import tune_batch
                 t_tune = time.time()
-                r = tune_batch(wl.d, wl.w, wl.z, wl.keys, wl.ops, wl.queries)
-                result["autotune_check"] = {"b": r.b, "rule_b": b, "ref_b": r.ref_b, "ref_are": round(r.ref_are, 5),
-                                            "bound": round(r.bound, 5),
-                                            "candidates": [[bb, round(a, 5), round(ms, 2), ok] for bb, a, ms, ok in r.table]}
-                log(f"[bench] autotuner on this workload ({time.time() - t_tune:.1f}s): b = {r.b} (rule {b})")
+                # the bound from the oracle's sequential ARE when the CPU leg has run
+                seq_are = result.get("accuracy", {}).get("seq", {}).get("are")
+                r = tune_batch(wl.d, wl.w, wl.z, wl.keys, wl.ops, wl.queries, modes=(2, 3), ref_are=seq_are)
+                result["autotune_check"] = {
+                    "b": r.b, "merge_path": MERGE_PATHS[r.mode], "rule_b": b,
+                    "ref": "oracle sequential SF_F" if seq_are is not None else f"GPU at b = {r.ref_b}",
+                    "ref_are": round(r.ref_are, 5), "bound": round(r.bound, 5),
+                    "candidates": [[bb, round(a, 5), round(ms, 2), ok, MERGE_PATHS[m]]
+                                   for bb, a, ms, ok, m in r.table]}
+                log(f"[bench] autotuner on this workload ({time.time() - t_tune:.1f}s): b = {r.b}, "
+                    f"path {result['autotune_check']['merge_path']} (rule {b})")
         else:
             leg_out[leg] = rec
             if not args.no_cpu_baseline:
@@ -953,6 +1019,40 @@ def main():
     if leg_out:
         result["legs"] = leg_out
     print(json.dumps(result), flush=True)
+
+
+def run_query_pipeline(torch, np, g, wl, batches=(20_000, 64_000, 256_000, 2_000_000), streams=(1, 4),
+                       reps: int = 20) -> dict:
+    """Host-fed query batches through sf_query_host (the multi-stream pipeline of the
+    paper's GPU implementation): keys in pinned host memory, answers back in pinned
+    host memory, per batch size and stream count: the median call latency and the
+    query rate it gives.  The sketch holds the state of the last timed step (Slim
+    exported); answers are checked against the device query of the same keys."""
+    sk = g["sk"]
+    q = wl.queries
+    ref = g["answers"]
+    rows = []
+    for n in batches:
+        n = min(n, q.shape[0])
+        hk = torch.from_numpy(np.ascontiguousarray(q[:n]).view(np.int32)).pin_memory()
+        out = torch.empty(n, dtype=torch.int32).pin_memory()
+        for st in streams:
+            sk.query_host(hk, out, streams=st)           # warm-up (buffers allocated)
+            lat = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                sk.query_host(hk, out, streams=st)
+                lat.append(time.perf_counter() - t0)
+            if not np.array_equal(out.numpy().view(np.uint32), ref[:n]):
+                raise SystemExit("sf_query_host answers differ from the device query")
+            med = float(np.median(lat))
+            rows.append({"batch": n, "streams": st, "latency_us_p50": round(med * 1e6, 1),
+                         "latency_us_p99": round(float(np.percentile(lat, 99)) * 1e6, 1),
+                         "mqps": round(n / med / 1e6, 2)})
+    log(f"[bench] host-fed query pipeline: {json.dumps(rows)}")
+    return {"rows": rows, "note": "keys H2D from pinned memory, query kernel, answers D2H, split over HIP "
+                                  "streams (the first n mod streams take one more key); call latency includes "
+                                  "the host-side launch and the wait for the last copy"}
 
 
 def run_host_fed(torch, np, sf, g, wl, b: int, steps: int) -> dict:

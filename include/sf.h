@@ -129,6 +129,19 @@ int sf_update_host(sf_sketch *sk, const void *host_keys, const uint8_t *host_ops
  * minimum. */
 int sf_query(sf_sketch *sk, const void *keys, uint64_t n, uint32_t *out);
 
+/* Host-fed batched point query, the multi-stream pipeline of the paper's GPU
+ * implementation (Section 4.2): n keys in PINNED host memory are split over
+ * `streams` HIP streams (1..16) of the sketch's own -- the first n mod streams
+ * streams take one key more -- and each stream copies its keys in, runs the
+ * query kernel (one pass over the Slim, as sf_query) and copies its answers
+ * to host_out (PINNED, n uint32), so the copies of one stream overlap the
+ * kernels of another.  The streams start after the work already on the
+ * sketch's stream, and later work on that stream waits for them.  Device
+ * buffers (one per stream) are allocated on first use and grown when a
+ * larger share arrives.  Blocks until every answer is in host_out.  SF_EINVAL
+ * for pageable memory or a bad stream count. */
+int sf_query_host(sf_sketch *sk, const void *host_keys, uint64_t n, uint32_t *host_out, uint32_t streams);
+
 /* Collector-side point query (Section 3.1 query rule) over an exported Slim
  * (Sections 1 and 3: the collector holds only the Slim): slim is a device
  * pointer to [d][w] uint16, row-major; keys and out as in sf_query; runs on
@@ -179,27 +192,29 @@ int sf_sync(sf_sketch *sk);
 int sf_set_tile(sf_sketch *sk, uint32_t tile_ops);
 
 /* Where duplicate keys are merged before they reach a counter, and how the
- * merged keys reach the counters.  1 (the default) and 2 merge across the
- * whole batch: keys are first partitioned into hash buckets, then merged per
- * chunk of whole buckets (a large bucket spans several chunks), and S1..S5
- * run once per merged key.  With 1, where the shape allows it (a range of
- * 2^k >= 16 cells, at most 1024 ranges per row and at most 8192 / d, holds
- * at most 8192 Fat counters), each (row, cell range) has one owning
- * workgroup per step that applies S1..S5 to its records with LDS sums and
- * plain stores; other shapes, and mode 2, use one device-scope atomic per
- * merged key and row.  0 merges per tile of consecutive ops.  Results are
- * identical in every mode (Section 3.4 insertion and Section 3.5 deletion
- * are sums, maxima and minima per counter).  The owner path's buffers (the
- * pairs of two batches, their positions and snapshots: about 28 * d + 2
- * bytes per op of batch_ops, counted in sf_footprint) are a separate
- * allocation made by sf_create: modes 0 and 2
- * free it (after the stream drains), mode 1 allocates it again (SF_ENOMEM if
- * it cannot).  SF_EINVAL for other values. */
+ * merged keys reach the counters.  Modes 1 (the default), 2 and 3 merge
+ * across the whole batch: keys are first partitioned into hash buckets, then
+ * merged per chunk of whole buckets (a large bucket spans several chunks),
+ * and S1..S5 run once per merged key.  Where the shape allows it (a range of
+ * 2^k >= 16 cells, at most 1024 ranges per row and at most 8192 / d, holds at
+ * most 8192 Fat counters), S1..S5 can run owner-computes: each (row, cell
+ * range) has one owning workgroup per step that stages the range's records
+ * in LDS and applies S1..S5 there; mode 1 does so for batches of at least w
+ * ops and mode 3 for every batch.  Otherwise (smaller batches in mode 1, mode
+ * 2, shapes that do not fit) one device-scope atomic per merged key and row
+ * applies them.  0 merges per tile of consecutive ops.  Results are identical
+ * in every mode (Section 3.4 insertion and Section 3.5 deletion are sums,
+ * maxima and minima per counter).  The owner path's buffers (the pairs of two
+ * batches, their positions and snapshots: about 28 * d + 2 bytes per op of
+ * batch_ops, counted in sf_footprint) are a separate allocation made by
+ * sf_create: modes 0 and 2 free it (after the stream drains), modes 1 and 3
+ * allocate it again (SF_ENOMEM if they cannot).  SF_EINVAL for other values. */
 int sf_set_merge(sf_sketch *sk, int batch_wide);
 
-/* The path sf_update takes now: 0 per-tile merging, 1 batch-wide merge with
- * owner-computes S1..S5, 2 batch-wide merge with atomic S1..S5; negative on
- * error. */
+/* The mode sf_update runs in now: 0 per-tile merging, 1 batch-wide merge with
+ * owner-computes S1..S5 for batches of at least w ops, 2 batch-wide merge with
+ * atomic S1..S5, 3 owner-computes for every batch; negative on error.  Mode 1
+ * or 3 reads 2 when the shape does not fit the owner path. */
 int sf_merge_path(sf_sketch *sk);
 
 /* Merged entries (distinct keys per merge chunk) the batch-wide merge has

@@ -59,6 +59,7 @@ SIGNATURES = {
     "sf_update": (_I, [_P, _P, _P, _U64]),
     "sf_query": (_I, [_P, _P, _U64, _P]),
     "sf_query_slim": (_I, [_P, _CFG, _P, _U64, _P, _P]),
+    "sf_query_host": (_I, [_P, _P, _U64, _P, ctypes.c_uint32]),
     "sf_query_slim_noalloc": (_I, [_P, _CFG, _P, _U64, _P, _P]),
     "sf_export_slim": (_I, [_P, _P, _U64]),
     "sf_export_fat": (_I, [_P, _P, _U64]),
@@ -325,6 +326,20 @@ class Sketch:
         sf_query(self._h, keys, out, self.key_bytes)
         return out
 
+    def query_host(self, keys, out=None, streams: int = 4):
+        """Queries of keys in pinned host memory through the multi-stream pipeline
+        (sf_query_host); answers land in pinned host memory (returned)."""
+        import torch
+        if not isinstance(keys, torch.Tensor) or keys.is_cuda or not keys.is_pinned():
+            raise TypeError("keys must be a pinned host tensor")
+        n = keys.numel() * keys.element_size() // self.cfg.key_bytes
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32).pin_memory()
+        if out.numel() < n or out.element_size() != 4:
+            raise ValueError("out must hold one 4-byte answer per key")
+        _check(lib().sf_query_host(self._h, keys.data_ptr(), n, out.data_ptr(), streams), "sf_query_host")
+        return out
+
     def export_slim(self, out=None):
         import numpy as np
         if out is None:
@@ -353,13 +368,14 @@ class Sketch:
 
     def set_merge(self, batch_wide):
         """Merge duplicate keys across the whole batch (True / 1, the default: owner-computes
-        S1..S5 where the shape allows), per tile (False / 0), or across the batch with atomic
-        S1..S5 (2)."""
+        S1..S5 for batches of at least w ops where the shape allows), per tile (False / 0),
+        across the batch with atomic S1..S5 (2), or with owner-computes for every batch (3)."""
         mode = int(batch_wide) if not isinstance(batch_wide, bool) else int(batch_wide)
         _check(lib().sf_set_merge(self._h, mode), "sf_set_merge")
 
     def merge_path(self) -> int:
-        """0 per-tile merging, 1 batch-wide merge + owner-computes S1..S5, 2 batch-wide + atomics."""
+        """0 per-tile merging, 1 batch merge + owner-computes S1..S5 for large batches, 2 batch
+        merge + atomic S1..S5, 3 owner-computes for every batch."""
         rc = lib().sf_merge_path(self._h)
         if rc < 0:
             _check(rc, "sf_merge_path")

@@ -37,6 +37,8 @@ std::string& last_error() {
 }
 }  // namespace sfh
 
+constexpr uint32_t kMaxQueryStreams = 16;
+
 struct sf_sketch {
     sf_config cfg;
     Geom g;
@@ -60,7 +62,8 @@ struct sf_sketch {
     MergeChunk* chunks;//             key range of every merge chunk
     MergeMeta* meta;
     bool owner_ok;    // the shape fits the owner-computes path
-    bool owner_on;    // S1..S5 by (row, cell range) owners (else the entry kernels)
+    bool owner_on;    // S1..S5 by (row, cell range) owners for large batches (else the entry kernels)
+    bool owner_all;   // ... for every batch, however small (merge mode 3)
     OwnerBufs own;
     char* own_base = nullptr;  // the owner path's buffers: their own allocation, held while mode 1 is set
     Profiler prof;
@@ -72,6 +75,13 @@ struct sf_sketch {
     hipEvent_t copied[2] = {nullptr, nullptr};
     hipEvent_t consumed[2] = {nullptr, nullptr};
     bool feed_busy[2] = {false, false};
+    // host-fed queries (sf_query_host): one stream, one event and one device
+    // buffer (keys, then answers) per pipeline stream, made on first use
+    hipStream_t qs[kMaxQueryStreams] = {};
+    hipEvent_t qdone[kMaxQueryStreams] = {};
+    uint8_t* qbuf[kMaxQueryStreams] = {};
+    uint64_t qbuf_keys = 0;
+    hipEvent_t qready = nullptr;
 };
 
 namespace {
@@ -123,12 +133,30 @@ Sizes sizes_of(const sf_config* c) {
     return s;
 }
 
+// The closing owner step of the pending batch, if any (before the batch that
+// follows on another path, and at the end of an update call).
+void close_owner(sf_sketch* s) {
+    if (!s->own.pending) return;
+    if (s->cfg.d == 4) owner_close<4>(&s->own, s->g, s->fat, s->stream, &s->prof);
+    else if (s->cfg.d == 8) owner_close<8>(&s->own, s->g, s->fat, s->stream, &s->prof);
+    else owner_close<0>(&s->own, s->g, s->fat, s->stream, &s->prof);
+}
+
+// Whether a batch of cnt ops takes the owner path: each owner step reads and
+// writes every record of the ranges its pairs touch, which a batch of fewer
+// than w ops touches sparsely, so small batches keep the atomic entry kernels
+// (measured: below about w / 2 ops per batch they are faster) unless mode 3
+// asks for the owner path always.
+bool use_owner(const sf_sketch* s, uint32_t cnt) { return s->owner_on && (s->owner_all || cnt >= s->cfg.w); }
+
 // Batch-wide merge: partition, merge, then S1..S5 over the entries.
 template <int KB, int D>
 void launch_merged(sf_sketch* s, const UniformPlan<KB>& plan, uint32_t cnt, bool ins, bool del) {
+    const bool own = use_owner(s, cnt);
+    if (!own) close_owner(s);  // the atomic kernels read records the pending step still changes
     MergeRun<KB, false> run{static_cast<MKey<KB, false>*>(s->part), static_cast<MKey<KB, false>*>(s->ent_key),
                             s->ent_cnt, s->meta, s->hist, s->chunks, s->stride, s->bpre, s->asnap, s->stride,
-                            s->owner_on ? &s->own : nullptr};
+                            own ? &s->own : nullptr};
     run.template launch<D>(plan, blocks_for(cnt, kPartOps), cnt, OneSketch{s->g, s->fat, s->slim}, ins, del,
                            s->stream, &s->prof);
 }
@@ -170,11 +198,7 @@ int run_updates(sf_sketch* s, const void* keys, const uint8_t* ops, uint64_t n, 
         if (kb == 4) launch_batch<4>(s, kp, op, mode, cnt, kind != kDelete, kind != kInsert);
         else launch_batch<13>(s, kp, op, mode, cnt, kind != kDelete, kind != kInsert);
     }
-    if (s->own.pending) {  // the call's last batch: its S3..S5
-        if (s->cfg.d == 4) owner_close<4>(&s->own, s->g, s->fat, s->stream, &s->prof);
-        else if (s->cfg.d == 8) owner_close<8>(&s->own, s->g, s->fat, s->stream, &s->prof);
-        else owner_close<0>(&s->own, s->g, s->fat, s->stream, &s->prof);
-    }
+    close_owner(s);  // the call's last batch: its S3..S5
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SF_OK : device_fail(e, "update launch");
 }
@@ -409,6 +433,13 @@ int sf_destroy(sf_sketch* s) {
         if (s->consumed[i]) (void)hipEventDestroy(s->consumed[i]);
     }
     if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+    for (uint32_t j = 0; j < kMaxQueryStreams; j++) {
+        if (s->qs[j]) (void)hipStreamSynchronize(s->qs[j]);
+        if (s->qbuf[j]) (void)hipFree(s->qbuf[j]);
+        if (s->qdone[j]) (void)hipEventDestroy(s->qdone[j]);
+        if (s->qs[j]) (void)hipStreamDestroy(s->qs[j]);
+    }
+    if (s->qready) (void)hipEventDestroy(s->qready);
     if (s->own_base) (void)hipFree(s->own_base);
     hipError_t e2 = hipFree(s->fat);
     delete s;
@@ -511,6 +542,80 @@ int sf_update_host(sf_sketch* s, const void* host_keys, const uint8_t* host_ops,
     // every byte has left the host buffers once the last copy is done
     e = hipEventSynchronize(s->copied[last]);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_update_host copies");
+}
+
+int sf_query_host(sf_sketch* s, const void* host_keys, uint64_t n, uint32_t* host_out, uint32_t streams) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    if (streams < 1 || streams > kMaxQueryStreams) return fail(SF_EINVAL, "streams must be in 1..16");
+    if (n == 0) return SF_OK;
+    auto pinned = [](const void* p) {
+        hipPointerAttribute_t at{};
+        if (!p || hipPointerGetAttributes(&at, p) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return at.type == hipMemoryTypeHost;
+    };
+    if (!pinned(host_keys)) return fail(SF_EINVAL, "host_keys must be pinned host memory (hipHostMalloc)");
+    if (!pinned(host_out)) return fail(SF_EINVAL, "host_out must be pinned host memory (hipHostMalloc)");
+    const uint32_t kb = s->cfg.key_bytes;
+    const uint64_t share = n / streams + (n % streams ? 1 : 0);  // the largest share
+    hipError_t e = hipSuccess;
+    if (!s->qready && (e = hipEventCreateWithFlags(&s->qready, hipEventDisableTiming)) != hipSuccess)
+        return device_fail(e, "sf_query_host setup");
+    if (s->qbuf_keys < share) {  // (re)allocate the per-stream buffers once nothing reads them
+        for (uint32_t j = 0; j < kMaxQueryStreams; j++) {
+            if (s->qs[j] && (e = hipStreamSynchronize(s->qs[j])) != hipSuccess)
+                return device_fail(e, "sf_query_host sync");
+            if (s->qbuf[j]) (void)hipFree(s->qbuf[j]);
+            s->qbuf[j] = nullptr;
+        }
+        s->qbuf_keys = 0;
+    }
+    for (uint32_t j = 0; j < streams; j++) {
+        if (!s->qs[j]) {
+            e = hipStreamCreateWithFlags(&s->qs[j], hipStreamNonBlocking);  // default priority
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->qdone[j], hipEventDisableTiming);
+            if (e != hipSuccess) return device_fail(e, "sf_query_host streams");
+        }
+        if (!s->qbuf[j]) {
+            e = hipMalloc(reinterpret_cast<void**>(&s->qbuf[j]), std::max<uint64_t>(share, s->qbuf_keys) * (kb + 4) + 4);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return e == hipErrorOutOfMemory ? fail(SF_ENOMEM, "sf_query_host buffers")
+                                                : device_fail(e, "sf_query_host buffers");
+            }
+        }
+    }
+    s->qbuf_keys = std::max<uint64_t>(s->qbuf_keys, share);
+    // every stream starts after the work already on the sketch's stream
+    if ((e = hipEventRecord(s->qready, s->stream)) != hipSuccess) return device_fail(e, "sf_query_host record");
+    // the one-pass query (the row split's scratch is the sketch's own, one at a time)
+    const void* slim = s->view_fresh ? static_cast<const void*>(s->view) : static_cast<const void*>(s->slim);
+    const uint8_t* hk = static_cast<const uint8_t*>(host_keys);
+    const uint64_t base = n / streams, extra = n % streams;
+    uint64_t off = 0;
+    for (uint32_t j = 0; j < streams; j++) {
+        const uint64_t cnt = base + (j < extra ? 1 : 0);  // the first n mod streams take one more
+        if (!cnt) continue;
+        uint8_t* dk = s->qbuf[j];
+        uint32_t* dout = reinterpret_cast<uint32_t*>(s->qbuf[j] + ((s->qbuf_keys * kb + 3) & ~uint64_t(3)));
+        e = hipStreamWaitEvent(s->qs[j], s->qready, 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(dk, hk + off * kb, cnt * kb, hipMemcpyHostToDevice, s->qs[j]);
+        if (e != hipSuccess) return device_fail(e, "sf_query_host copy in");
+        int rc = query_common(&s->prof, &s->cfg, s->g, slim, s->view_fresh, dk, cnt, dout, s->qs[j]);
+        if (rc) return rc;
+        e = hipMemcpyAsync(host_out + off, dout, cnt * 4, hipMemcpyDeviceToHost, s->qs[j]);
+        if (e == hipSuccess) e = hipEventRecord(s->qdone[j], s->qs[j]);
+        // later work on the sketch's stream (updates, resets) waits for these reads
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->qdone[j], 0);
+        if (e != hipSuccess) return device_fail(e, "sf_query_host copy out");
+        off += cnt;
+    }
+    for (uint32_t j = 0; j < streams; j++)
+        if (base + (j < extra ? 1 : 0) && (e = hipEventSynchronize(s->qdone[j])) != hipSuccess)
+            return device_fail(e, "sf_query_host wait");
+    return SF_OK;
 }
 
 int sf_query(sf_sketch* s, const void* keys, uint64_t n, uint32_t* out) {
@@ -630,15 +735,17 @@ int sf_set_tile(sf_sketch* s, uint32_t tile_ops) {
 
 int sf_set_merge(sf_sketch* s, int batch_wide) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
-    if (batch_wide < 0 || batch_wide > 2) return fail(SF_EINVAL, "merge mode must be 0, 1 or 2");
+    if (batch_wide < 0 || batch_wide > 3) return fail(SF_EINVAL, "merge mode must be 0, 1, 2 or 3");
     s->merge_batch = batch_wide != 0;
-    if (batch_wide == 1 && s->owner_ok) return s->own_base ? (s->owner_on = true, SF_OK) : owner_alloc(s);
+    s->owner_all = batch_wide == 3;
+    if ((batch_wide == 1 || batch_wide == 3) && s->owner_ok)
+        return s->own_base ? (s->owner_on = true, SF_OK) : owner_alloc(s);
     return owner_free(s);
 }
 
 int sf_merge_path(sf_sketch* s) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
-    return !s->merge_batch ? 0 : s->owner_on ? 1 : 2;
+    return !s->merge_batch ? 0 : !s->owner_on ? 2 : s->owner_all ? 3 : 1;
 }
 
 int sf_merge_stats(sf_sketch* s, uint64_t* insert_entries, uint64_t* delete_entries) {

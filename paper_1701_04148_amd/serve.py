@@ -47,6 +47,7 @@ class ServeStats:
     keys_per_s: float
     mean_requests_per_launch: float
     peak_resident: int
+    latency_by_kind_ms: dict = field(default_factory=dict)
     outcomes: list = field(repr=False, default_factory=list)
 
 
@@ -173,9 +174,13 @@ class Server:
         makespan = now()
         lat = [o.done - o.arrival for o in outcomes]
         qd = [o.issued - o.arrival for o in outcomes]
+        by_kind = {}
+        for r, o in zip(requests, outcomes):
+            by_kind.setdefault(kinds_name(r.kind), []).append(o.done - o.arrival)
         return ServeStats(N, keys_total, launches, makespan, _pct(lat), _pct(qd),
                           keys_total / makespan if makespan > 0 else 0.0,
-                          N / max(1, launches), peak, outcomes)
+                          N / max(1, launches), peak, {k: _pct(v) for k, v in sorted(by_kind.items())},
+                          outcomes)
 
 
 def kinds_name(k: int) -> str:

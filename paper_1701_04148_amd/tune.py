@@ -70,7 +70,8 @@ class TuneResult:
     ref_b: int
     ref_are: float
     bound: float
-    table: list = field(default_factory=list)   # (b, are, ms, feasible) per candidate
+    table: list = field(default_factory=list)   # (b, are, ms, feasible, merge mode) per candidate
+    mode: int = 1                                # merge mode (sf_set_merge) of the pick
 
 
 def candidates_for(w: int, n_ops: int, cap: int = 1 << 23) -> list[int]:
@@ -88,8 +89,12 @@ def candidates_for(w: int, n_ops: int, cap: int = 1 << 23) -> list[int]:
 
 def tune_batch(d: int, w: int, z: int, keys: np.ndarray, ops: np.ndarray | None, queries: np.ndarray,
                key_bytes: int = 4, candidates=None, rel: float = 1.10, abs_: float = 1e-3,
-               reps: int = 2) -> TuneResult:
-    """Pick b for sketches of shape (d, w, z) fed streams like (keys, ops)."""
+               reps: int = 2, modes=(1,), ref_are: float | None = None) -> TuneResult:
+    """Pick b (and, among `modes`, the sf_set_merge path) for sketches of shape
+    (d, w, z) fed streams like (keys, ops).  Every mode gives the same answers, so the
+    accuracy depends on b alone; each candidate keeps its fastest mode.  ref_are: the
+    sequential ARE of the sample when the caller has it (the bound is then taken from
+    it instead of the smallest candidate's)."""
     import torch
     cands = sorted(candidates or candidates_for(w, keys.shape[0]))
     f = exact_counts(keys, ops, queries)
@@ -105,28 +110,35 @@ def tune_batch(d: int, w: int, z: int, keys: np.ndarray, ops: np.ndarray | None,
     rows = []
     for b in cands:
         sk = Sketch(d, w, z, key_bytes=key_bytes, batch_ops=b)
-        best = float("inf")
-        for _ in range(reps):
-            sk.reset()
-            sk.sync()
-            t0 = time.perf_counter()
-            if dops is None:
-                sk.insert(dk)
-            else:
-                sk.update(dk, dops)
-            sk.query(dq, out)
-            sk.sync()
-            best = min(best, (time.perf_counter() - t0) * 1e3)
-        ans = out.cpu().numpy().view(np.uint32)
-        rows.append([b, are(ans, f), best])
+        best, best_mode, ans = float("inf"), modes[0], None
+        for mode in modes:
+            sk.set_merge(mode)
+            for _ in range(reps):
+                sk.reset()
+                sk.sync()
+                t0 = time.perf_counter()
+                if dops is None:
+                    sk.insert(dk)
+                else:
+                    sk.update(dk, dops)
+                sk.query(dq, out)
+                sk.sync()
+                ms = (time.perf_counter() - t0) * 1e3
+                if ms < best:
+                    best, best_mode = ms, sk.merge_path()
+            if ans is None:
+                ans = out.cpu().numpy().view(np.uint32)
+        rows.append([b, are(ans, f), best, None, best_mode])
         sk.close()
-    ref_b, ref_are = rows[0][0], rows[0][1]
+    ref_b = rows[0][0]
+    if ref_are is None:
+        ref_are = rows[0][1]
     bound = rel * ref_are + abs_
     for r in rows:
-        r.append(r[1] <= bound)
+        r[3] = r[1] <= bound
     feasible = [r for r in rows if r[3]]
-    pick = min(feasible, key=lambda r: r[2])[0] if feasible else ref_b
-    return TuneResult(pick, ref_b, ref_are, bound, rows)
+    best_row = min(feasible, key=lambda r: r[2]) if feasible else rows[0]
+    return TuneResult(best_row[0], ref_b, ref_are, bound, rows, best_row[4])
 
 
 class Autotuner:

@@ -311,7 +311,8 @@ def config_multi(seed: int = 0, n_sketches: int = 1024, length_scale: float = 1.
 
 @dataclass
 class ServeRequest:
-    """One request of the serving workload: keys are pool[off : off + n]."""
+    """One request of the serving workload: keys are pool[off : off + n], or for a
+    delete the concatenation of pool[o : o + c] over its pieces (o, c)."""
     stream: int
     seq: int          # position in the stream's request order
     kind: int         # 0 insert, 1 delete, 3 query (the sf_request kinds)
@@ -319,6 +320,7 @@ class ServeRequest:
     n: int
     arrival: float    # seconds after the start
     last: bool        # the stream closes after this request
+    pieces: tuple = None  # delete: ((off, count), ...) slices of the pool, in order
 
 
 @dataclass
@@ -327,6 +329,12 @@ class ServeWorkload:
     requests: list                  # ServeRequest, sorted by arrival
     n_streams: int
     meta: dict = field(default_factory=dict)
+
+    def keys_of(self, r: ServeRequest) -> np.ndarray:
+        """The request's keys, in order."""
+        if r.pieces:
+            return np.concatenate([self.pool[o:o + c] for o, c in r.pieces])
+        return self.pool[r.off:r.off + r.n]
 
 
 def serving(seed: int = 0, n_streams: int = 4096, per_stream: int = 16, mix=(0.7, 0.1, 0.2),
@@ -340,10 +348,14 @@ def serving(seed: int = 0, n_streams: int = 4096, per_stream: int = 16, mix=(0.7
     with probabilities mix (a delete with nothing live becomes an insert);
     sizes log-uniform in size_range.  Keys come from one pool of pool_keys
     Zipf(s) draws over a universe of distinct uint32: an insert or query takes
-    a random slice of the pool; a delete takes a suffix of the stream's most
-    recent insert that still has undeleted keys, so deletions never exceed
-    insertions (strict turnstile).  Scale offered load with open_window and
-    stream_rate."""
+    a random slice of the pool.  A delete removes n occurrences drawn uniformly
+    from the stream's live ones (all occurrences inserted and not yet deleted;
+    n is capped at their number, so the stream stays strict-turnstile): the
+    number taken from each live insert slice is multivariate hypergeometric,
+    and inside a slice they are its last live positions -- the pool's draws
+    are independent and identically distributed, so which positions of a
+    slice go does not change the distribution of the deleted keys.  Scale
+    offered load with open_window and stream_rate."""
     g_uni, g_rank, g_req, g_arr = rngs(seed)
     uni = universe_u32(g_uni, universe)
     pool = uni[zipf_ranks(g_rank, universe, s, pool_keys)]
@@ -357,21 +369,26 @@ def serving(seed: int = 0, n_streams: int = 4096, per_stream: int = 16, mix=(0.7
             n = int(round(np.exp(lo + (hi - lo) * g_req.random())))
             u = g_req.random()
             kind = 0 if u < mix[0] else (1 if u < mix[0] + mix[1] else 3)
+            live = [iv for iv in live if iv[1] > 0]
+            if kind == 1 and not live:
+                kind = 0
+            pieces = None
             if kind == 1:
-                while live and live[-1][1] == 0:
-                    live.pop()
-                if not live:
-                    kind = 0
-            if kind == 1:
-                ins = live[-1]
-                n = min(n, ins[1])
-                ins[1] -= n
-                off = ins[0] + ins[1]            # suffix of the insert's slice
+                rem = np.array([iv[1] for iv in live], dtype=np.int64)
+                n = int(min(n, rem.sum()))
+                take = g_req.multivariate_hypergeometric(rem, n)
+                pieces = []
+                for iv, c in zip(live, take):
+                    if c:
+                        iv[1] -= int(c)
+                        pieces.append((iv[0] + iv[1], int(c)))   # the slice's last live positions
+                pieces = tuple(pieces)
+                off = pieces[0][0]
             else:
                 off = int(g_req.integers(0, pool_keys - n + 1))
                 if kind == 0:
                     live.append([off, n])
-            reqs.append(ServeRequest(st, q, kind, off, n, t, q == per_stream - 1))
+            reqs.append(ServeRequest(st, q, kind, off, n, t, q == per_stream - 1, pieces))
     reqs.sort(key=lambda r: (r.arrival, r.stream, r.seq))
     return ServeWorkload(pool, reqs, n_streams,
                          dict(seed=seed, per_stream=per_stream, mix=mix, size_range=size_range,

@@ -42,7 +42,7 @@ def gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base=1, calls=1, merge=1, t
     sk.set_merge(int(merge))
     sk.set_tile(tile)
     path = sk.merge_path()
-    want = int(merge) if int(merge) != 1 or owner_shape(d, w, z) else 2
+    want = int(merge) if int(merge) not in (1, 3) or owner_shape(d, w, z) else 2
     assert path == want, (merge, path, want)
     n = keys.shape[0]
     cuts = np.linspace(0, n, calls + 1).astype(np.int64)

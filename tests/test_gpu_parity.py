@@ -17,12 +17,13 @@ from tests.oracle_support import exact_counts, random_turnstile
 pytestmark = pytest.mark.gpu
 
 
-MERGE_NAMES = {0: "tile", 1: "batch+owner", 2: "batch+atomic"}
+MERGE_NAMES = {0: "tile", 1: "batch, owner for large batches", 2: "batch+atomic", 3: "batch+owner always"}
 
 
 def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag="", merge=0):
-    """merge: 0 per-tile merging, 1 batch-wide merge with owner-computes S1..S5 where the
-    shape allows, 2 batch-wide merge with atomic S1..S5 (sf_set_merge)."""
+    """merge: 0 per-tile merging, 1 batch-wide merge with owner-computes S1..S5 for batches of
+    at least w ops where the shape allows, 2 batch-wide merge with atomic S1..S5, 3 owner-computes
+    for every batch (sf_set_merge)."""
     say(f"[case] {tag} d={d} w={w} z={z} kb={kb} n={keys.shape[0]} q={queries.shape[0]} "
         f"b={b} calls={calls} merge={MERGE_NAMES[int(merge)]}")
     g = gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls, merge=merge)
@@ -37,7 +38,7 @@ def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag="", merg
                                       (8, 512, 4, 13), (5, 333, 2, 13), (16, 128, 1, 4),
                                       (2, 4096, 8, 4), (4, 256, 4, 13)])
 @pytest.mark.parametrize("b", [1000, 1 << 20])
-@pytest.mark.parametrize("merge", [0, 1, 2])
+@pytest.mark.parametrize("merge", [0, 1, 2, 3])
 def test_mixed_small(d, w, z, kb, b, merge):
     """Several tiles and a ragged tail: 20011 mixed ops, 30% deletes."""
     rng = np.random.default_rng(d * 7 + w + kb)
@@ -46,7 +47,7 @@ def test_mixed_small(d, w, z, kb, b, merge):
 
 
 @pytest.mark.parametrize("b", [1, 3, 64])
-@pytest.mark.parametrize("merge", [0, 1, 2])
+@pytest.mark.parametrize("merge", [0, 2, 3])
 def test_small_batches_and_sequential(b, merge):
     """b = 1 is the sequential SF_F rule of Section 3.5 (the oracle's seq mode)."""
     rng = np.random.default_rng(b)
@@ -120,6 +121,9 @@ def test_main_config_scaled(skew, merge):
     """The 32M-op configuration divided by 8 (4M ops, 10% deletes, w=2^17)."""
     wl = sfgen.config_main(skew, scale=8)
     check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, 1 << 18, tag="c2/8", merge=merge)
+    if merge == 1:   # per call four batches of 5 * 2^16 ops (>= w = 2^17: owner) and a tail of 23K (atomic)
+        check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, 5 << 16, calls=3, tag="c2/8 mixed paths",
+              merge=1)
 
 
 @pytest.mark.timeout(600)
@@ -150,6 +154,7 @@ def test_batch_merge_with_one_hot_key():
     q = np.unique(keys)[:50_000]
     check(4, 1 << 14, 4, 4, keys, ops, q, n, tag="hot", merge=1)
     check(4, 1 << 14, 4, 4, keys, ops, q, n, tag="hot", merge=2)
+    check(4, 1 << 14, 4, 4, keys, ops, q, 1 << 12, tag="hot, small batches", merge=3)
 
 
 @pytest.mark.parametrize("kb", [4, 13])
@@ -413,3 +418,44 @@ def test_host_fed_updates_equal_device_updates():
     assert rc == sf.SF_EINVAL
     for s_ in (sk, ref, ins, ref2):
         s_.close()
+
+
+def test_host_fed_query_pipeline():
+    """sf_query_host (pinned host keys split over n streams, the first n_keys mod n
+    streams taking one key more, each copying in, querying and copying out) answers
+    exactly as sf_query and the oracle, with the Slim's dense copy fresh or not, for
+    stream counts that do not divide the key count; later updates wait for it; bad
+    arguments are refused."""
+    import torch
+    wl = sfgen.config_main(1.0, scale=64)                     # 500K ops, w = 2^14
+    b = 1 << 15
+    half = wl.n_ops // 2
+    sk = sf.Sketch(wl.d, wl.w, wl.z, batch_ops=b)
+    orc = oracle.Sketch(wl.d, wl.w, wl.z)
+    sk.update(dev_keys(wl.keys[:half]), torch.from_numpy(wl.ops[:half]).cuda())
+    assert orc.batch(wl.keys[:half], wl.ops[:half], b, checked=True) == 0
+    q = wl.queries[:100_003]
+    hq = torch.from_numpy(q.view(np.int32)).pin_memory()
+    ref = orc.query(q)
+    for streams in (1, 3, 4, 16):
+        say(f"[case] query pipeline streams={streams} n={q.shape[0]} (records)")
+        got = sk.query_host(hq, streams=streams).numpy().view(np.uint32)
+        assert_same(got, ref, f"host-fed query, {streams} streams")
+    sf.sf_export_slim(sk._h, torch.empty(wl.d * wl.w, dtype=torch.int16, device="cuda"))
+    for streams in (2, 7):
+        say(f"[case] query pipeline streams={streams} (dense copy)")
+        got = sk.query_host(hq, streams=streams).numpy().view(np.uint32)
+        assert_same(got, ref, f"host-fed query on the dense copy, {streams} streams")
+    tiny = torch.from_numpy(q[:5].view(np.int32)).pin_memory()  # fewer keys than streams
+    assert_same(sk.query_host(tiny, streams=16).numpy().view(np.uint32), ref[:5], "5 keys, 16 streams")
+    # the second half of the stream after the pipelined queries, then queries again
+    sk.update(dev_keys(wl.keys[half:]), torch.from_numpy(wl.ops[half:]).cuda())
+    assert orc.batch(wl.keys[half:], wl.ops[half:], b, checked=True) == 0
+    got = sk.query_host(hq, streams=4).numpy().view(np.uint32)
+    assert_same(got, orc.query(q), "after a later update")
+    assert_same(sk.query(dev_keys(q)).cpu().numpy().view(np.uint32), got, "device query")
+    out = torch.empty(q.shape[0], dtype=torch.int32).pin_memory()
+    assert sf.lib().sf_query_host(sk._h, q.ctypes.data, q.shape[0], out.data_ptr(), 4) == sf.SF_EINVAL
+    assert sf.lib().sf_query_host(sk._h, hq.data_ptr(), q.shape[0], out.data_ptr(), 0) == sf.SF_EINVAL
+    assert sf.lib().sf_query_host(sk._h, hq.data_ptr(), q.shape[0], out.data_ptr(), 17) == sf.SF_EINVAL
+    sk.close()

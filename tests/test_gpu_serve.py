@@ -19,9 +19,20 @@ def _workload(seed=1, n_streams=40, per_stream=6):
                          pool_keys=1 << 18, universe=20_000, open_window=0.02, stream_rate=400.0)
 
 
+def _key_fn(w, pool_t):
+    """Device keys of a request: a slice of the pool, or (deletes) its pieces joined
+    up front, before any pool launch reads them."""
+    import torch
+    joined = {(r.stream, r.seq): torch.cat([pool_t[o:o + c] for o, c in r.pieces])
+              for r in w.requests if r.pieces}
+    torch.cuda.synchronize()
+    return lambda r: joined[(r.stream, r.seq)] if r.pieces else pool_t[r.off:r.off + r.n]
+
+
 def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15, merge=True):
     import torch
     pool_t = torch.from_numpy(w.pool.view(np.int32)).cuda()
+    key_of = _key_fn(w, pool_t)
     outs = {i: torch.full((r.n,), -1, dtype=torch.int32, device="cuda")
             for i, r in enumerate(w.requests) if r.kind == sf.SF_REQ_QUERY}
     index = {id(r): i for i, r in enumerate(w.requests)}
@@ -30,7 +41,7 @@ def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15, merge=True):
     pool = sf.SketchPool(sf.make_config(**CFG), max_slots=max_slots)
     pool.set_merge(merge)
     srv = Server(pool, max_launch_keys=max_launch_keys, max_in_flight=3)
-    st = srv.run(w.requests, key_of=lambda r: pool_t[r.off:r.off + r.n],
+    st = srv.run(w.requests, key_of=key_of,
                  out_of=lambda r: outs[index[id(r)]], export_to=lambda s: slims[s], realtime=realtime)
     pool.sync()
     torch.cuda.synchronize()
@@ -43,6 +54,7 @@ def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15, merge=True):
 def _run_alone(w, stream):
     import torch
     pool_t = torch.from_numpy(w.pool.view(np.int32)).cuda()
+    key_of = _key_fn(w, pool_t)
     pool = sf.SketchPool(sf.make_config(**CFG), max_slots=1)
     slot = pool.acquire()
     ans = {}
@@ -50,7 +62,7 @@ def _run_alone(w, stream):
         if r.stream != stream:
             continue
         out = torch.full((r.n,), -1, dtype=torch.int32, device="cuda") if r.kind == sf.SF_REQ_QUERY else None
-        t = pool.launch([(slot, r.kind, pool_t[r.off:r.off + r.n], None, out)])
+        t = pool.launch([(slot, r.kind, key_of(r), None, out)])
         pool.wait(t)
         if out is not None:
             ans[i] = out.cpu().numpy().view(np.uint32)
@@ -66,7 +78,7 @@ def _oracle_stream(w, stream):
     for i, r in enumerate(w.requests):
         if r.stream != stream:
             continue
-        keys = w.pool[r.off:r.off + r.n]
+        keys = w.keys_of(r)
         if r.kind == sf.SF_REQ_QUERY:
             ans[i] = ref.query(keys)
         else:

@@ -56,3 +56,34 @@ def test_small_config_shape():
     assert wl.n_queries == 100_000
     f = exact_counts(wl.keys, None, wl.queries)
     assert f.sum() == 1_000_000
+
+
+def test_serving_deletes_are_live_occurrences():
+    """A delete request removes occurrences that its stream inserted and has not yet
+    deleted (strict turnstile), drawn over all of the stream's live insert slices."""
+    from collections import Counter
+    w = sfgen.serving(seed=3, n_streams=60, per_stream=14, size_range=(20, 400), pool_keys=1 << 14,
+                      universe=3000, mix=(0.5, 0.35, 0.15))
+    by_stream = {}
+    for r in w.requests:
+        by_stream.setdefault(r.stream, []).append(r)
+    multi_slice = 0
+    for reqs in by_stream.values():
+        reqs.sort(key=lambda r: r.seq)
+        live = Counter()
+        slices = []                          # (off, n) of the stream's inserts so far
+        for r in reqs:
+            keys = w.keys_of(r)
+            assert keys.shape[0] == r.n
+            if r.kind == 0:
+                live.update(keys.tolist())
+                slices.append((r.off, r.n))
+            elif r.kind == 1:
+                assert r.n > 0 and sum(c for _, c in r.pieces) == r.n
+                for o, c in r.pieces:        # every piece lies inside one of the stream's inserts
+                    assert any(so <= o and o + c <= so + sn for so, sn in slices)
+                got = Counter(keys.tolist())
+                assert all(live[k] >= v for k, v in got.items())
+                live.subtract(got)
+                multi_slice += len(r.pieces) > 1
+    assert multi_slice > 0                   # deletes reach back past the latest insert
