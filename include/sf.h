@@ -85,7 +85,9 @@ uint64_t sf_footprint(const sf_config *cfg);
  * Errors: SF_EINVAL, SF_ENOMEM, SF_EDEVICE.  *out is set only on SF_OK. */
 int sf_create(const sf_config *cfg, uint64_t hbm_budget_bytes, void *hip_stream, sf_sketch **out);
 
-/* Frees every device buffer of the sketch after its stream drains. */
+/* Frees every device buffer of the sketch after its stream drains (the
+ * sketch's lifetime; the paper has no counterpart).  SF_ESTATE for a handle
+ * that is not live; the handle is dead after the call. */
 int sf_destroy(sf_sketch *sk);
 
 /* Re-zero both subsketches (asynchronous on the sketch's stream). */
@@ -103,7 +105,12 @@ int sf_insert(sf_sketch *sk, const void *keys, uint64_t n);
  * violation is not detected: Fat counters wrap, Slim results are undefined. */
 int sf_delete(sf_sketch *sk, const void *keys, uint64_t n);
 
-/* Mixed stream of n ops: ops[t] = 0 inserts keys[t], 1 deletes it (device). */
+/* Mixed stream of n ops (the turnstile model of Section 2, with the SF_F
+ * insertion of Section 3.4 and deletion of Section 3.5): ops[t] = 0 inserts
+ * keys[t], 1 deletes it; keys and ops are device buffers of n entries.  The
+ * ops are cut into schedule batches in order; inside a batch inserts apply
+ * before deletes (the update schedule above).  Same precondition on deletes
+ * as sf_delete.  SF_EINVAL for bad pointers or op buffers shorter than n. */
 int sf_update(sf_sketch *sk, const void *keys, const uint8_t *ops, uint64_t n);
 
 /* Host-fed updates: n ops whose keys (and op codes, or NULL for all
@@ -177,11 +184,16 @@ int sf_query_slim_noalloc(const uint16_t *slim, const sf_config *cfg, const void
  * own copy of what it exported, for sf_query. */
 int sf_export_slim(sf_sketch *sk, uint16_t *out, uint64_t out_elems);
 
-/* Fat export: d*w*z uint32 counters, [d][w][z] (row, bucket, slot), host or
- * device memory, out_elems >= d*w*z.  Synchronous. */
+/* Fat export, the Fat-subsketch of Section 3.4's structure (d arrays of w
+ * buckets of z counters; Eq. (1) of Section 3.3 gives the bucket and slot):
+ * d*w*z uint32 counters, [d][w][z] (row, bucket, slot), to host or device
+ * memory, out_elems >= d*w*z.  Synchronous.  It stays with the monitor (the
+ * collector gets only the Slim); tests and tools read it.  SF_EINVAL for a
+ * null or short destination. */
 int sf_export_fat(sf_sketch *sk, uint32_t *out, uint64_t out_elems);
 
-/* Wait for all work enqueued on the sketch's stream. */
+/* Wait for all work enqueued on the sketch's stream (host synchronisation;
+ * the paper has no counterpart).  SF_EDEVICE if a kernel failed. */
 int sf_sync(sf_sketch *sk);
 
 /* Launch shape of the per-tile merging path (sf_set_merge(sk, 0)): each
