@@ -105,7 +105,7 @@ int sf_insert(sf_sketch *sk, const void *keys, uint64_t n);
  * violation is not detected: Fat counters wrap, Slim results are undefined. */
 int sf_delete(sf_sketch *sk, const void *keys, uint64_t n);
 
-/* Mixed stream of n ops (the turnstile model of Section 2, with the SF_F
+/* Mixed stream of n ops (items inserted and deleted, Section 3; SF_F's
  * insertion of Section 3.4 and deletion of Section 3.5): ops[t] = 0 inserts
  * keys[t], 1 deletes it; keys and ops are device buffers of n entries.  The
  * ops are cut into schedule batches in order; inside a batch inserts apply
