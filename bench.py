@@ -823,6 +823,7 @@ def main():
                          "request loop alone")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-host-fed", action="store_true", help="skip the PCIe-inclusive host-fed steps")
+    ap.add_argument("--no-query-pipeline", action="store_true", help="skip the host-fed query batches")
     ap.add_argument("--no-collector", action="store_true",
                     help="skip streaming the Slim to a collector process")
     ap.add_argument("--no-autotune", action="store_true",
@@ -952,7 +953,8 @@ def main():
             sk = g["sk"]
             if not args.no_host_fed and wl.ops is not None:
                 result["host_fed"] = run_host_fed(torch, np, sf, g, wl, b, args.steps)
-            result["query_pipeline"] = run_query_pipeline(torch, np, g, wl)
+            if not args.no_query_pipeline:
+                result["query_pipeline"] = run_query_pipeline(torch, np, g, wl)
             if not args.no_collector:
                 result["collector"] = run_collector(np, sk, g["step"], wl.queries, g["answers"])
                 log(f"[bench] collector: {json.dumps(result['collector'])}")

@@ -557,6 +557,17 @@ struct MinOp {
     __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a < b ? a : b; }
 };
 
+// Row of tile b (of n) in a histogram matrix, numbering the tiles XCD by XCD:
+// the dispatcher deals workgroups to the 8 XCDs round-robin, so tile b runs
+// on XCD b % 8, and with this order the runs that one XCD's tiles write into
+// a bucket (or column) are contiguous: few lines of the partitioned output
+// are written from two XCDs' L2s.  Any bijection gives the same results (the
+// order inside a bucket is free); this one only decides the write traffic.
+__device__ __forceinline__ uint32_t xcd_row(uint32_t b, uint32_t n) {
+    const uint32_t x = b % 8u, q = n / 8u, r = n % 8u;
+    return x * q + min(x, r) + b / 8u;
+}
+
 // Counts the ops of every bucket in each group's tile.
 template <int KB, bool G, class P>
 __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* __restrict__ hist_out,
@@ -571,7 +582,8 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* _
         atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2, w.g)], 1u);
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist_out[size_t(blockIdx.x) * nbt + b] = hist[b];
+    const uint32_t row = xcd_row(blockIdx.x, gridDim.x);
+    for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist_out[size_t(row) * nbt + b] = hist[b];
 }
 
 // Column scans of hist: 64 buckets per workgroup, one per lane, so that a
@@ -852,7 +864,8 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
             lstart[t * kPer + e] = run;
             run += v[e];
         }
-        for (uint32_t b = t; b < nbt; b += kPartThreads) hist[b] = meta->start[b] + offs[size_t(blockIdx.x) * nbt + b];
+        const uint32_t row = xcd_row(blockIdx.x, gridDim.x);
+        for (uint32_t b = t; b < nbt; b += kPartThreads) hist[b] = meta->start[b] + offs[size_t(row) * nbt + b];
         __syncthreads();
 #pragma unroll
         for (uint32_t r = 0; r < R; r++) {
@@ -871,7 +884,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
     } else {
         __syncthreads();
         for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
-            hist[b] = meta->start[b] + offs[size_t(blockIdx.x) * nbt + b];
+            hist[b] = meta->start[b] + offs[size_t(xcd_row(blockIdx.x, gridDim.x)) * nbt + b];
         __syncthreads();
 #pragma unroll
         for (uint32_t r = 0; r < R; r++) {

@@ -53,8 +53,10 @@ __host__ __device__ constexpr uint32_t pair_tile(uint32_t nv) {
     return t < kPairTileMin ? kPairTileMin : t > kPairTileMax ? kPairTileMax : t;
 }
 // Tiles (grid width) that cover every entry count up to cap.
+// A multiple of 8, so that in the (tile, row) grids tile b runs on XCD b % 8
+// whatever its row.
 __host__ __device__ constexpr uint32_t pair_tiles_max(uint32_t cap) {
-    const uint32_t big = (cap + kPairTileMax - 1) / kPairTileMax;
+    const uint32_t big = ((cap + kPairTileMax - 1) / kPairTileMax + 7) / 8 * 8;
     return big > kPairTiles ? big : kPairTiles;
 }
 
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(kCountThreads) void k_pair_count(const MergeMeta* _
         atomicAdd(&hist[(v < ni ? 0u : R) + (h >> og.cr_shift)], 1u);
     }
     __syncthreads();
-    uint32_t* out = hmat + size_t(blockIdx.x) * og.ncol + i * R;
+    uint32_t* out = hmat + size_t(xcd_row(blockIdx.x, (nv + T - 1) / T)) * og.ncol + i * R;
     for (uint32_t c = threadIdx.x; c < 2 * R; c += kCountThreads) out[c < R ? c : d * R + c - R] = hist[c];
 }
 
@@ -190,6 +192,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
     const uint32_t lo = blockIdx.x * T;
     if (lo >= nv) return;
     const uint32_t n = min(nv - lo, T), i = blockIdx.y;
+    const uint32_t trow = xcd_row(blockIdx.x, (nv + T - 1) / T);  // this tile's row of hmat
     const uint32_t d = SF_ROWS(D, g), R = og.R, nc = 2 * R;
     const uint32_t cmask = (1u << og.cr_shift) - 1;
     for (uint32_t c = threadIdx.x; c < nc; c += kPairThreads) cnt[c] = 0;
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
     }
     for (uint32_t c = threadIdx.x; c < nc; c += kPairThreads) {
         const uint32_t gcol = (c < R ? 0u : d * R) + i * R + (c < R ? c : c - R);
-        gb[c] = pm->start[gcol] + hmat[size_t(blockIdx.x) * og.ncol + gcol];
+        gb[c] = pm->start[gcol] + hmat[size_t(trow) * og.ncol + gcol];
     }
     __syncthreads();
 #pragma unroll
