@@ -338,7 +338,8 @@ def run_multi(args, torch, np, sf, sfgen):
     cfgs = [sf.make_config(m.d, int(m.w[i]), m.z, 4, 1, batch_of_w[int(m.w[i])]) for i in range(m.n)]
     G = sf.SketchGroup(cfgs)
     G.set_tile(args.tile)
-    G.set_merge(args.merge != "tile")
+    G.set_merge({"tile": 0, "batch": 1, "owner": 1, "atomic": 2}[args.merge])
+    log(f"[bench] group merge path {G.merge_path()} (0 per tile, 1 owner-computes, 2 atomics)")
 
     def step():
         G.reset()

@@ -299,11 +299,21 @@ int sf_group_export_fat(sf_group *g, uint32_t i, uint32_t *out, uint64_t out_ele
 int sf_group_sync(sf_group *g);
 int sf_group_set_graph(sf_group *g, int enable);
 int sf_group_set_tile(sf_group *g, uint32_t tile_ops);
-/* As sf_set_merge, per group (default 1).  Batch-wide merging treats each
- * (key, sketch) pair as one key; merged sub-rounds hold at most 2^24 ops
- * (or the largest batch_ops), tiles of the per-tile path at most round_ops.
- * Waits for the stream; the next update call re-plans. */
-int sf_group_set_merge(sf_group *g, int batch_wide);
+/* Merge path of the group (default 1): 0 per-tile merging; 1 batch-wide
+ * merging with owner-computes S1..S5 when every sketch has the same d and z
+ * (ranges of 2^k cells, k the largest with at most 8192 Fat counters and a
+ * 16-bit local code per range; a sub-round then also holds at most 1024
+ * ranges per row), else as 2; 2 batch-wide merging with atomic S1..S5.
+ * Batch-wide merging treats each (key, sketch) pair as one key; merged
+ * sub-rounds hold at most 2^24 ops (or the largest batch_ops), tiles of the
+ * per-tile path at most round_ops.  The owner-path buffers (counted by
+ * sf_group_footprint) are allocated at create time for shapes that qualify,
+ * freed by modes 0 and 2 and allocated again by mode 1 (SF_ENOMEM if that
+ * fails; the group then runs as mode 2).  SF_EINVAL for another mode.  Waits
+ * for the stream; the next update call re-plans. */
+int sf_group_set_merge(sf_group *g, int mode);
+/* The path the next update call takes: 0, 1 or 2 as in sf_group_set_merge. */
+int sf_group_merge_path(sf_group *g);
 /* As sf_merge_stats, summed over the group's sketches. */
 int sf_group_merge_stats(sf_group *g, uint64_t *insert_entries, uint64_t *delete_entries);
 /* Sub-rounds (launch groups) and tiles of the last update call's plan. */

@@ -85,6 +85,7 @@ SIGNATURES = {
     "sf_group_set_graph": (_I, [_P, _I]),
     "sf_group_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_group_set_merge": (_I, [_P, _I]),
+    "sf_group_merge_path": (_I, [_P]),
     "sf_group_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_group_rounds": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_group_profile": (_I, [_P, _I]),
@@ -507,9 +508,18 @@ class SketchGroup:
     def set_tile(self, tile_ops: int):
         _check(lib().sf_group_set_tile(self._h, tile_ops), "sf_group_set_tile")
 
-    def set_merge(self, batch_wide: bool):
-        """Merge duplicate (key, sketch) pairs across each sub-round (True, the default) or per tile."""
-        _check(lib().sf_group_set_merge(self._h, int(bool(batch_wide))), "sf_group_set_merge")
+    def set_merge(self, batch_wide):
+        """Merge duplicate (key, sketch) pairs across each sub-round (True / 1, the default:
+        owner-computes S1..S5 when every sketch has the same d and z), per tile (False / 0), or
+        across each sub-round with atomic S1..S5 (2)."""
+        _check(lib().sf_group_set_merge(self._h, int(batch_wide)), "sf_group_set_merge")
+
+    def merge_path(self) -> int:
+        """0 per-tile merging, 1 batch merge + owner-computes S1..S5, 2 batch merge + atomics."""
+        rc = lib().sf_group_merge_path(self._h)
+        if rc < 0:
+            _check(rc, "sf_group_merge_path")
+        return rc
 
     def merge_stats(self):
         """(insert entries, delete entries) emitted by the batch-wide merge so far, all sketches."""

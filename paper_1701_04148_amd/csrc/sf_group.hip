@@ -64,6 +64,17 @@ struct sf_group {
     uint32_t tile_j;
     bool use_graph;
     bool merge;                    // batch-merge path (default) or per-tile merging
+    // owner-computes S1..S5 (batch-merge path, when every sketch has the same
+    // d and z): buffers for one merged sub-round and each sub-round's ranges
+    bool owner_ok = false;         // the shapes fit (buffers allocated)
+    bool owner_on = false;         // merge mode 1
+    OwnerGeom own_og{};            // cr_shift, zbits, d (R and ncol are per sub-round)
+    OwnerBufs own{};
+    char* own_base = nullptr;
+    uint32_t* d_ranges = nullptr;  // per sub-round: qbase [n], then qsk and qr [Q each]
+    size_t ranges_cap = 0;
+    std::vector<uint32_t> h_ranges;
+    uint64_t own_sizes[6] = {};    // pairs, pos, res, level, hmat, pair meta (bytes)
     // tile table (device, growable) and its pinned host staging
     TileDesc* d_tiles = nullptr;
     size_t tiles_cap = 0;
@@ -74,6 +85,8 @@ struct sf_group {
     struct SubRound {
         uint32_t first, tiles;
         uint64_t ops;
+        uint32_t ranges = 0;       // owner path: ranges per row (Q) of its sketches
+        uint64_t table = 0;        // owner path: offset of its range table in d_ranges (words)
     };
     std::vector<SubRound> subrounds;
     uint32_t plan_kind = 0;
@@ -104,7 +117,31 @@ struct Layout {
     uint64_t state, desc, stage, bpre, asnap, part, ent_key, ent_cnt, meta, hist, chunks, total;
     uint64_t round_ops, merge_round;
     uint32_t d_max;
+    bool owner = false;             // owner-computes buffers (a second allocation, counted in total)
+    OwnerGeom og{};
+    uint64_t pairs = 0, pos = 0, res = 0, level = 0, hmat = 0, pmeta = 0;
+    uint64_t owner_bytes() const { return pairs + pos + res + level + hmat + pmeta; }
 };
+
+// The owner path for a sketch table: every sketch with the same d and z;
+// ranges of 2^k cells, k the largest with at most 8192 Fat counters per range
+// (and a 16-bit local code), at most kMaxRanges per row in one sub-round.
+bool group_owner_geom(uint32_t n, const sf_config* cfgs, OwnerGeom* og) {
+    for (uint32_t i = 1; i < n; i++)
+        if (cfgs[i].d != cfgs[0].d || cfgs[i].z != cfgs[0].z) return false;
+    const uint32_t d = cfgs[0].d, z = cfgs[0].z;
+    if (2 * d * kMaxRanges > kMaxCols) return false;
+    uint32_t zbits = 0;
+    while ((1ull << zbits) < z) zbits++;
+    uint32_t sh = 4;
+    while ((2ull << sh) * z <= kOwnCounters && ((2ull << sh) << zbits) <= 65536) sh++;
+    if ((1ull << sh) * z > kOwnCounters || ((1ull << sh) << zbits) > 65536) return false;
+    *og = OwnerGeom{};
+    og->cr_shift = sh;
+    og->zbits = zbits;
+    og->d = d;
+    return true;
+}
 
 int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) {
     if (n == 0 || !cfgs) return fail(SF_EINVAL, "a group needs at least one sketch config");
@@ -153,6 +190,17 @@ int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) 
     L.chunks = off;
     off += round256(merge_chunks_max(L.merge_round) * sizeof(MergeChunk));
     L.total = off;
+    L.owner = group_owner_geom(n, cfgs, &L.og);
+    if (L.owner) {
+        const uint64_t mr = L.merge_round, d = L.og.d;
+        L.pairs = round256(d * mr * 8);
+        L.pos = round256(d * mr * 4);
+        L.res = round256(d * mr * 8);
+        L.level = round256(mr * 2);
+        L.hmat = round256(uint64_t(pair_tiles_max(uint32_t(mr))) * 2 * d * kMaxRanges * 4);
+        L.pmeta = round256(sizeof(PairMeta));
+        L.total += L.owner_bytes();
+    }
     return SF_OK;
 }
 
@@ -207,6 +255,11 @@ int check_segments(const sf_group* g, const uint64_t* seg) {
 void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uint8_t* ops, uint32_t mode) {
     g->plan.clear();
     g->subrounds.clear();
+    const bool owner = g->merge && g->owner_on;
+    auto ranges_of = [&](uint32_t s) {
+        return owner ? uint32_t((uint64_t(g->cfg[s].w) + (1ull << g->own_og.cr_shift) - 1) >> g->own_og.cr_shift)
+                     : 0u;
+    };
     const uint32_t tile_ops = g->merge ? kPartOps : uint32_t(kBlock) * g->tile_j;
     const uint64_t limit = g->merge ? g->merge_round : g->round_ops;
     const uint64_t max_tiles = g->merge ? g->hist_groups : ~0ull;
@@ -217,18 +270,21 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
     }
     for (uint64_t k = 0; k < rounds; k++) {
         uint64_t used = 0;
-        uint32_t first = uint32_t(g->plan.size());
+        uint32_t first = uint32_t(g->plan.size()), q = 0;
         for (uint32_t s = 0; s < g->n; s++) {
             const uint64_t b = g->cfg[s].batch_ops;
             const uint64_t lo = seg[s] + k * b;
             if (lo >= seg[s + 1]) continue;
             const uint64_t cnt = std::min(b, seg[s + 1] - lo);
             const uint64_t tiles = (cnt + tile_ops - 1) / tile_ops;
-            if (used && (used + cnt > limit || g->plan.size() - first + tiles > max_tiles)) {  // close the sub-round
-                g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used});
+            if (used && (used + cnt > limit || g->plan.size() - first + tiles > max_tiles ||
+                         q + ranges_of(s) > kMaxRanges)) {  // close the sub-round
+                g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used, q});
                 first = uint32_t(g->plan.size());
                 used = 0;
+                q = 0;
             }
+            q += ranges_of(s);
             for (uint64_t off = 0; off < cnt; off += tile_ops) {
                 TileDesc t{};
                 t.keys = keys + (lo + off) * g->key_bytes;
@@ -241,20 +297,97 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
             }
             used += cnt;
         }
-        if (uint32_t(g->plan.size()) > first) g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used});
+        if (uint32_t(g->plan.size()) > first)
+            g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used, q});
     }
+    if (!owner) return;
+    // each sub-round's range table: its sketches' ranges numbered in plan order
+    g->h_ranges.clear();
+    for (auto& sr : g->subrounds) {
+        sr.table = g->h_ranges.size();
+        g->h_ranges.resize(sr.table + g->n + 2ull * sr.ranges, ~0u);
+        uint32_t* qbase = g->h_ranges.data() + sr.table;
+        uint32_t* qsk = qbase + g->n;
+        uint32_t* qr = qsk + sr.ranges;
+        uint32_t qn = 0;
+        for (uint32_t t = sr.first; t < sr.first + sr.tiles; t++) {
+            const uint32_t s = g->plan[t].sketch;
+            if (qbase[s] != ~0u) continue;
+            qbase[s] = qn;
+            for (uint32_t r = 0; r < ranges_of(s); r++, qn++) {
+                qsk[qn] = s;
+                qr[qn] = r;
+            }
+        }
+    }
+}
+
+// The owner-path buffers (pairs, positions, snapshots, T, column counts),
+// sized for one merged sub-round.
+int group_owner_alloc(sf_group* g) {
+    const uint64_t* sz = g->own_sizes;
+    const uint64_t total = sz[0] + sz[1] + sz[2] + sz[3] + sz[4] + sz[5];
+    char* ob = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&ob), total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? fail(SF_ENOMEM, "owner-path buffers: out of device memory")
+                                        : device_fail(e, "owner-path buffers");
+    }
+    g->own_base = ob;
+    g->own = OwnerBufs{};
+    g->own.og = g->own_og;
+    g->own.pairs[0] = reinterpret_cast<uint64_t*>(ob);
+    g->own.pairs[1] = nullptr;
+    g->own.pos = reinterpret_cast<uint32_t*>(ob + sz[0]);
+    g->own.res = reinterpret_cast<uint64_t*>(ob + sz[0] + sz[1]);
+    g->own.level = reinterpret_cast<uint16_t*>(ob + sz[0] + sz[1] + sz[2]);
+    g->own.hmat = reinterpret_cast<uint32_t*>(ob + sz[0] + sz[1] + sz[2] + sz[3]);
+    g->own.pm[0] = reinterpret_cast<PairMeta*>(ob + sz[0] + sz[1] + sz[2] + sz[3] + sz[4]);
+    g->own.pm[1] = nullptr;
+    g->owner_on = true;
+    return SF_OK;
+}
+
+int upload_ranges(sf_group* g) {
+    const size_t words = g->h_ranges.size();
+    if (!words) return SF_OK;
+    if (g->ranges_cap < words) {
+        if (g->d_ranges) (void)hipFree(g->d_ranges);
+        g->d_ranges = nullptr;
+        g->ranges_cap = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->d_ranges), words * 4);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? fail(SF_ENOMEM, "range tables") : device_fail(e, "range tables");
+        }
+        g->ranges_cap = words;
+    }
+    hipError_t e = hipMemcpy(g->d_ranges, g->h_ranges.data(), words * 4, hipMemcpyHostToDevice);
+    return e == hipSuccess ? SF_OK : device_fail(e, "range table upload");
 }
 
 template <int KB>
 void launch_plan(sf_group* g, bool ins, bool del, Profiler* prof) {
-    const MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(g->part), static_cast<MKey<KB, true>*>(g->ent_key),
-                                 g->ent_cnt, g->meta, g->hist, g->chunks, uint32_t(g->merge_round), g->bpre,
-                                 g->asnap,
-                                 uint32_t(g->round_ops)};
+    MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(g->part), static_cast<MKey<KB, true>*>(g->ent_key),
+                           g->ent_cnt, g->meta, g->hist, g->chunks, uint32_t(g->merge_round), g->bpre,
+                           g->asnap,
+                           uint32_t(g->round_ops)};
     const SketchTable table{g->d_desc};
+    const bool owner = g->merge && g->owner_on;
     for (auto& sr : g->subrounds) {
         const ListPlan<KB> plan{g->d_tiles + sr.first, g->d_desc};
         const uint32_t cnt = uint32_t(sr.ops);
+        if (owner) {
+            run.own = &g->own;
+            run.sub_og = g->own_og;
+            run.sub_og.R = sr.ranges;
+            run.sub_og.ncol = 2 * g->own_og.d * sr.ranges;
+            run.sub_og.xcd = (kXcds % g->own_og.d == 0 && (g->own_og.d * sr.ranges) % kXcds == 0) ? 1u : 0u;
+            run.sub_rm = TableRanges{g->d_ranges + sr.table, g->d_ranges + sr.table + g->n,
+                                     g->d_ranges + sr.table + g->n + sr.ranges};
+            run.max_z = g->cfg[0].z;
+        }
         if (!g->merge) {
             Steps<ListPlan>::by_rows<KB>(g->d_uniform, g->tile_j, plan, sr.tiles, ins, del, g->bpre, g->asnap,
                                         uint32_t(g->round_ops), g->stream, prof, cnt);
@@ -303,6 +436,7 @@ int group_updates(sf_group* g, const void* keys, const uint8_t* ops, const uint6
         if (e != hipSuccess) return device_fail(e, "group sync");
         if ((rc = ensure_device_tiles(g->d_tiles, g->tiles_cap, g->plan.size()))) return rc;
         if ((rc = upload_tiles(g, g->d_tiles, g->plan))) return rc;
+        if ((rc = upload_ranges(g))) return rc;
         g->plan_kind = kind;
         g->plan_on_device = true;
     }
@@ -381,7 +515,7 @@ int sf_group_create(uint32_t n, const sf_config* cfgs, uint64_t round_ops, uint6
     g->use_graph = true;
     g->merge = true;
     g->state_bytes = L.state;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->base), L.total);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->base), L.total - (L.owner ? L.owner_bytes() : 0));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         if (g->own_stream) (void)hipStreamDestroy(g->stream);
@@ -406,12 +540,29 @@ int sf_group_create(uint32_t n, const sf_config* cfgs, uint64_t round_ops, uint6
     g->hist = reinterpret_cast<uint32_t*>(g->base + L.hist);
     g->chunks = reinterpret_cast<MergeChunk*>(g->base + L.chunks);
     g->hist_groups = part_groups_max(L.merge_round, kHistExtra);
+    if (L.owner) {
+        g->own_og = L.og;
+        g->own_sizes[0] = L.pairs;
+        g->own_sizes[1] = L.pos;
+        g->own_sizes[2] = L.res;
+        g->own_sizes[3] = L.level;
+        g->own_sizes[4] = L.hmat;
+        g->own_sizes[5] = L.pmeta;
+        g->owner_ok = true;
+        if ((rc = group_owner_alloc(g))) {
+            (void)hipFree(g->base);
+            if (g->own_stream) (void)hipStreamDestroy(g->stream);
+            delete g;
+            return rc;
+        }
+    }
     e = hipMemcpy(g->d_desc, g->desc.data(), n * sizeof(SketchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemsetAsync(g->base, 0, L.state, g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->meta, 0, sizeof(MergeMeta), g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) {
         (void)hipFree(g->base);
+        if (g->own_base) (void)hipFree(g->own_base);
         if (g->own_stream) (void)hipStreamDestroy(g->stream);
         delete g;
         return device_fail(e, "sf_group_create init");
@@ -434,6 +585,8 @@ int sf_group_destroy(sf_group* g) {
     if (g->d_tiles) (void)hipFree(g->d_tiles);
     if (g->d_qtiles) (void)hipFree(g->d_qtiles);
     if (g->h_tiles) (void)hipHostFree(g->h_tiles);
+    if (g->d_ranges) (void)hipFree(g->d_ranges);
+    if (g->own_base) (void)hipFree(g->own_base);
     hipError_t e2 = hipFree(g->base);
     if (g->own_stream) (void)hipStreamDestroy(g->stream);
     delete g;
@@ -562,14 +715,27 @@ int sf_group_set_tile(sf_group* g, uint32_t tile_ops) {
     return SF_OK;
 }
 
-int sf_group_set_merge(sf_group* g, int batch_wide) {
+int sf_group_set_merge(sf_group* g, int mode) {
     if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    if (mode < 0 || mode > 2) return fail(SF_EINVAL, "group merge mode must be 0, 1 or 2");
     hipError_t e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return device_fail(e, "group sync");
-    g->merge = batch_wide != 0;
+    int rc = SF_OK;
+    if (mode == 1 && g->owner_ok && !g->own_base) rc = group_owner_alloc(g);
+    if (mode != 1 && g->own_base) {
+        (void)hipFree(g->own_base);
+        g->own_base = nullptr;
+    }
+    g->merge = mode != 0;
+    g->owner_on = mode == 1 && g->own_base;
     drop_graph(g);
     g->plan_on_device = false;
-    return SF_OK;
+    return rc;
+}
+
+int sf_group_merge_path(sf_group* g) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    return !g->merge ? 0 : g->owner_on ? 1 : 2;
 }
 
 int sf_group_merge_stats(sf_group* g, uint64_t* insert_entries, uint64_t* delete_entries) {

@@ -218,6 +218,7 @@ inline bool owner_geom(const sf_config* c, OwnerGeom* og) {
     og->zbits = zbits;
     og->ncol = 2 * c->d * og->R;
     og->xcd = (kXcds % c->d == 0 && (c->d * og->R) % kXcds == 0) ? 1u : 0u;
+    og->d = c->d;
     return true;
 }
 
@@ -244,13 +245,14 @@ inline size_t own_step_lds(const Geom& g, const OwnerGeom& og) {
 }
 
 // The closing owner step of an update call: S3..S5 of its last batch.
-template <int D>
-void owner_close(OwnerBufs* own, const Geom& g, uint32_t* fat, hipStream_t st, Profiler* prof) {
+inline void owner_close(OwnerBufs* own, const Geom& g, uint32_t* fat, uint32_t* slim, hipStream_t st,
+                        Profiler* prof) {
     if (!own->pending) return;
     const uint32_t prev = own->cur ^ 1u;
     Timed tm(prof, st, SF_K_OWN_FINAL, 0);
-    k_own_step<D><<<g.d * own->og.R, kOwnThreads, own_step_lds(g, own->og), st>>>(
-        g, own->og, fat, own->pm[prev], own->pairs[prev], own->level, nullptr, nullptr, own->res);
+    k_own_step<OneSketch, LoneRanges><<<g.d * own->og.R, kOwnThreads, own_step_lds(g, own->og), st>>>(
+        OneSketch{g, fat, slim}, LoneRanges{}, own->og, own->pm[prev], own->pairs[prev], own->level, nullptr,
+        nullptr, own->res);
     own->pending = false;
 }
 
@@ -270,10 +272,17 @@ struct MergeRun {
     uint32_t* bpre;        // [d][stride] S1 snapshot of Fat counters, per insert entry
     uint16_t* asnap;       // [d][stride] S1 snapshot of Slim counters, per insert entry
     uint32_t stride;
-    OwnerBufs* own = nullptr;  // lone sketch: S1..S5 by (row, cell range) owners
+    OwnerBufs* own = nullptr;  // S1..S5 by (row, cell range) owners
+    // a sketch table's sub-round: its ranges and their layout (own set)
+    TableRanges sub_rm{};
+    OwnerGeom sub_og{};
+    uint32_t max_z = 0;
 
     template <int D, class SR>
     void launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st, Profiler* prof) const;
+    template <class SR, class RM>
+    void launch_pairs(uint32_t cnt, const SR& sr, const RM& rm, const OwnerGeom& og, uint32_t set, hipStream_t st,
+                      Profiler* prof) const;
 
     // part_groups: workgroups of the partition kernels (plan tiles of at most
     // kPartOps ops); cnt: ops in the batch (<= cap).
@@ -309,11 +318,9 @@ struct MergeRun {
                                  st>>>(part, meta, chunks, ent_key, ent_cnt, cap, nb_log2, sr, bpre, asnap,
                                        own ? 0u : 1u);
         }
-        if constexpr (!G) {
-            if (own) {
-                launch_owner<D>(cnt, sr, ins, del, st, prof);
-                return;
-            }
+        if (own) {
+            launch_owner<D>(cnt, sr, ins, del, st, prof);
+            return;
         }
         if (ins) {
             {
@@ -347,35 +354,66 @@ struct MergeRun {
     }
 };
 
+// The pair partition of one batch (or sub-round) into set `set` of own.
+template <int KB, bool G>
+template <class SR, class RM>
+void MergeRun<KB, G>::launch_pairs(uint32_t cnt, const SR& sr, const RM& rm, const OwnerGeom& og, uint32_t set,
+                                   hipStream_t st, Profiler* prof) const {
+    const unsigned tiles = pair_tiles_max(cnt);
+    Timed tm(prof, st, SF_K_PAIRS, cnt);
+    k_pair_count<KB, G, SR, RM><<<dim3(tiles, og.d), kCountThreads, 0, st>>>(meta, ent_key, cap, sr, rm, og,
+                                                                            own->hmat);
+    k_pair_colscan<><<<blocks_for(og.ncol, kScanCols), kScanCols * kScanWaves, 0, st>>>(own->hmat, meta,
+                                                                                      own->pm[set], og.ncol);
+    k_pair_start<><<<1, 1024, 0, st>>>(own->pm[set], og.ncol, meta);
+    k_pair_scatter<KB, G, SR, RM><<<dim3(tiles, og.d), kPairThreads, 0, st>>>(
+        meta, ent_key, ent_cnt, cap, sr, rm, og, own->hmat, own->pm[set], own->pairs[set], own->pos, cap);
+}
+
 template <int KB, bool G>
 template <int D, class SR>
 void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st,
                                    Profiler* prof) const {
-    const OwnerGeom& og = own->og;
     const unsigned tiles = pair_tiles_max(cnt);
-    const unsigned owners = sr.g.d * og.R;
-    const uint32_t set = own->cur, prev = set ^ 1u;
-    {
-        Timed tm(prof, st, SF_K_PAIRS, cnt);
-        k_pair_count<KB, D><<<dim3(tiles, sr.g.d), kCountThreads, 0, st>>>(meta, ent_key, cap, sr.g, og, own->hmat);
-        k_pair_colscan<><<<blocks_for(og.ncol, kScanCols), kScanCols * kScanWaves, 0, st>>>(own->hmat, meta,
-                                                                                          own->pm[set], og.ncol);
-        k_pair_start<><<<1, 1024, 0, st>>>(own->pm[set], og.ncol, meta);
-        k_pair_scatter<KB, D><<<dim3(tiles, sr.g.d), kPairThreads, 0, st>>>(
-            meta, ent_key, ent_cnt, cap, sr.g, og, own->hmat, own->pm[set], own->pairs[set], own->pos, cap);
+    if constexpr (!G) {
+        // lone sketch: this batch's S1 + S2 share one owner step with the
+        // previous batch's S3..S5; its own S3..S5 wait for the next step
+        const OwnerGeom& og = own->og;
+        const uint32_t set = own->cur, prev = set ^ 1u;
+        launch_pairs(cnt, sr, LoneRanges{}, og, set, st, prof);
+        {
+            Timed tm(prof, st, SF_K_OWN_STEP, cnt);
+            k_own_step<SR, LoneRanges><<<og.d * og.R, kOwnThreads, own_step_lds(sr.g, og), st>>>(
+                sr, LoneRanges{}, og, own->pending ? own->pm[prev] : nullptr,
+                own->pending ? own->pairs[prev] : nullptr, own->level, ins ? own->pm[set] : nullptr,
+                ins ? own->pairs[set] : nullptr, own->res);
+        }
+        if (ins) {
+            Timed tm(prof, st, SF_K_LEVEL, cnt);
+            k_level<D><<<tiles, kPairThreads, 0, st>>>(meta, own->pos, cap, own->res, og.d, own->level);
+        }
+        own->pending = true;  // this batch's S3..S5 (raise, deletes, clamp) come next
+        own->cur = prev;
+    } else {
+        // sketch table: every sub-round is finished at once (the next one holds
+        // other sketches): pairs, S1 + S2, T, then S3..S5
+        const OwnerGeom og = sub_og;
+        launch_pairs(cnt, sr, sub_rm, og, 0u, st, prof);
+        const size_t lds = size_t(1) << og.cr_shift;
+        const size_t lds_bytes = lds * (max_z + 1) * 4;
+        if (ins) {
+            {
+                Timed tm(prof, st, SF_K_OWN_STEP, cnt);
+                k_own_step<SR, TableRanges><<<og.d * og.R, kOwnThreads, lds_bytes, st>>>(
+                    sr, sub_rm, og, nullptr, nullptr, own->level, own->pm[0], own->pairs[0], own->res);
+            }
+            Timed tm(prof, st, SF_K_LEVEL, cnt);
+            k_level<D><<<tiles, kPairThreads, 0, st>>>(meta, own->pos, cap, own->res, og.d, own->level);
+        }
+        Timed tm(prof, st, SF_K_OWN_FINAL, cnt);
+        k_own_step<SR, TableRanges><<<og.d * og.R, kOwnThreads, lds_bytes, st>>>(
+            sr, sub_rm, og, own->pm[0], own->pairs[0], own->level, nullptr, nullptr, own->res);
     }
-    {
-        Timed tm(prof, st, SF_K_OWN_STEP, cnt);
-        k_own_step<D><<<owners, kOwnThreads, own_step_lds(sr.g, og), st>>>(
-            sr.g, og, sr.fat, own->pending ? own->pm[prev] : nullptr, own->pending ? own->pairs[prev] : nullptr,
-            own->level, ins ? own->pm[set] : nullptr, ins ? own->pairs[set] : nullptr, own->res);
-    }
-    if (ins) {
-        Timed tm(prof, st, SF_K_LEVEL, cnt);
-        k_level<D><<<tiles, kPairThreads, 0, st>>>(meta, own->pos, cap, own->res, sr.g.d, own->level);
-    }
-    own->pending = true;  // this batch's S3..S5 (raise, deletes, clamp) come next
-    own->cur = prev;
     (void)del;
 }
 

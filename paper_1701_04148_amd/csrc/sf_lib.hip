@@ -135,12 +135,7 @@ Sizes sizes_of(const sf_config* c) {
 
 // The closing owner step of the pending batch, if any (before the batch that
 // follows on another path, and at the end of an update call).
-void close_owner(sf_sketch* s) {
-    if (!s->own.pending) return;
-    if (s->cfg.d == 4) owner_close<4>(&s->own, s->g, s->fat, s->stream, &s->prof);
-    else if (s->cfg.d == 8) owner_close<8>(&s->own, s->g, s->fat, s->stream, &s->prof);
-    else owner_close<0>(&s->own, s->g, s->fat, s->stream, &s->prof);
-}
+void close_owner(sf_sketch* s) { owner_close(&s->own, s->g, s->fat, s->slim, s->stream, &s->prof); }
 
 // Whether a batch of cnt ops takes the owner path: each owner step reads and
 // writes every record of the ranges its pairs touch, which a batch of fewer

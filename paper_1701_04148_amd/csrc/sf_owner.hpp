@@ -61,11 +61,35 @@ __host__ __device__ constexpr uint32_t pair_tiles_max(uint32_t cap) {
 }
 
 struct OwnerGeom {
-    uint32_t R;         // cell ranges per row
+    uint32_t R;         // cell ranges per row (a sketch table: of every sketch of the sub-round)
     uint32_t cr_shift;  // log2(cells per range)
     uint32_t zbits;     // bits of the slot in a pair's local code (2^zbits >= z)
     uint32_t ncol;      // 2 * d * R: insert columns (row-major), then delete columns
     uint32_t xcd;       // owner workgroup b takes row (b % 8) % d
+    uint32_t d;         // rows (the same for every sketch of a table)
+};
+
+// Which range (per row) a cell of a sketch belongs to, and back.  A lone
+// sketch's ranges are its own: range = cell >> cr_shift.  In a sketch table
+// the ranges of one sub-round's sketches are numbered one after the other
+// (the same numbering in every row): qbase[s] is sketch s's first, and range
+// q belongs to sketch qsk[q], where it is the qr[q]-th.
+struct LoneRanges {
+    __device__ __forceinline__ uint32_t q_of(uint32_t, uint32_t rng) const { return rng; }
+    __device__ __forceinline__ void range_of(uint32_t q, uint32_t& sketch, uint32_t& r) const {
+        sketch = 0;
+        r = q;
+    }
+};
+struct TableRanges {
+    const uint32_t* qbase;
+    const uint32_t* qsk;
+    const uint32_t* qr;
+    __device__ __forceinline__ uint32_t q_of(uint32_t s, uint32_t rng) const { return qbase[s] + rng; }
+    __device__ __forceinline__ void range_of(uint32_t q, uint32_t& sketch, uint32_t& r) const {
+        sketch = qsk[q];
+        r = qr[q];
+    }
 };
 
 struct PairMeta {
@@ -105,22 +129,25 @@ __device__ __forceinline__ uint32_t entry_of(uint32_t v, uint32_t ni, uint32_t c
 }
 
 // Pairs of one row of one tile per column (blockIdx.y = row).
-template <int KB, int D>
+template <int KB, bool G, class SR, class RM>
 __global__ __launch_bounds__(kCountThreads) void k_pair_count(const MergeMeta* __restrict__ meta,
-                                                              const MKey<KB, false>* __restrict__ ent_key,
-                                                              uint32_t cap, Geom g, OwnerGeom og,
+                                                              const MKey<KB, G>* __restrict__ ent_key,
+                                                              uint32_t cap, SR sr, RM rm, OwnerGeom og,
                                                               uint32_t* __restrict__ hmat) {
     __shared__ uint32_t hist[2 * kMaxRanges];
     const uint32_t ni = meta->n_ins, nv = ni + meta->n_del, T = pair_tile(nv);
     const uint32_t lo = blockIdx.x * T;
     if (lo >= nv) return;
-    const uint32_t hi = min(nv, lo + T), i = blockIdx.y, R = og.R, d = SF_ROWS(D, g);
+    const uint32_t hi = min(nv, lo + T), i = blockIdx.y, R = og.R, d = og.d;
     for (uint32_t c = threadIdx.x; c < 2 * R; c += kCountThreads) hist[c] = 0;
     __syncthreads();
     for (uint32_t v = lo + threadIdx.x; v < hi; v += kCountThreads) {
+        const MKey<KB, G> m = ent_key[entry_of(v, ni, cap)];
+        const uint32_t sk = mkey_sketch<KB, G>(m);
+        const Geom g = sr.of(sk).g;
         uint32_t h, f;
-        split(g, Mixed<KB>(ent_key[entry_of(v, ni, cap)].k).row(g.seed_base + i), h, f);
-        atomicAdd(&hist[(v < ni ? 0u : R) + (h >> og.cr_shift)], 1u);
+        split(g, Mixed<KB>(m.k).row(g.seed_base + i), h, f);
+        atomicAdd(&hist[(v < ni ? 0u : R) + rm.q_of(sk, h >> og.cr_shift)], 1u);
     }
     __syncthreads();
     uint32_t* out = hmat + size_t(xcd_row(blockIdx.x, (nv + T - 1) / T)) * og.ncol + i * R;
@@ -171,11 +198,11 @@ __global__ __launch_bounds__(1024) void k_pair_start(PairMeta* __restrict__ pm, 
 // counted per (op type, range) in LDS, staged in column order, written out as
 // one run per column.  For insert entries, the position of the pair goes to
 // pos[row][entry].
-template <int KB, int D>
+template <int KB, bool G, class SR, class RM>
 __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* __restrict__ meta,
-                                                               const MKey<KB, false>* __restrict__ ent_key,
+                                                               const MKey<KB, G>* __restrict__ ent_key,
                                                                const uint32_t* __restrict__ ent_cnt,
-                                                               uint32_t cap, Geom g, OwnerGeom og,
+                                                               uint32_t cap, SR sr, RM rm, OwnerGeom og,
                                                                const uint32_t* __restrict__ hmat,
                                                                const PairMeta* __restrict__ pm,
                                                                uint64_t* __restrict__ pairs,
@@ -193,7 +220,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
     if (lo >= nv) return;
     const uint32_t n = min(nv - lo, T), i = blockIdx.y;
     const uint32_t trow = xcd_row(blockIdx.x, (nv + T - 1) / T);  // this tile's row of hmat
-    const uint32_t d = SF_ROWS(D, g), R = og.R, nc = 2 * R;
+    const uint32_t d = og.d, R = og.R, nc = 2 * R;
     const uint32_t cmask = (1u << og.cr_shift) - 1;
     for (uint32_t c = threadIdx.x; c < nc; c += kPairThreads) cnt[c] = 0;
     __syncthreads();
@@ -206,9 +233,12 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
         if (t < n) {
             eid[j] = entry_of(lo + t, ni, cap);
             c16[j] = ent_cnt[eid[j]] & ~kRow0Done;
+            const MKey<KB, G> m = ent_key[eid[j]];
+            const uint32_t sk = mkey_sketch<KB, G>(m);
+            const Geom g = sr.of(sk).g;
             uint32_t h, f;
-            split(g, Mixed<KB>(ent_key[eid[j]].k).row(g.seed_base + i), h, f);
-            col[j] = (lo + t >= ni ? R : 0u) + (h >> og.cr_shift);
+            split(g, Mixed<KB>(m.k).row(g.seed_base + i), h, f);
+            col[j] = (lo + t >= ni ? R : 0u) + rm.q_of(sk, h >> og.cr_shift);
             code[j] = ((h & cmask) << og.zbits) | f;
             rank[j] = atomicAdd(&cnt[col[j]], 1u);
         }
@@ -304,8 +334,8 @@ __global__ __launch_bounds__(kPairThreads) void k_level(const MergeMeta* __restr
 //                res[p] = (A, growth, Bpost), each capped at 65535 (T is
 //                capped there, so the caps change no T)
 // The range is read once and written once per step.
-template <int D>
-__global__ __launch_bounds__(kOwnThreads) void k_own_step(Geom g, OwnerGeom og, uint32_t* __restrict__ rec_all,
+template <class SR, class RM>
+__global__ __launch_bounds__(kOwnThreads) void k_own_step(SR sr, RM rm, OwnerGeom og,
                                                           const PairMeta* __restrict__ pm_f,
                                                           const uint64_t* __restrict__ pairs_f,
                                                           const uint16_t* __restrict__ level,
@@ -314,19 +344,22 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(Geom g, OwnerGeom og, 
                                                           uint64_t* __restrict__ res) {
     extern __shared__ uint32_t L[];  // ncells records of rs words
     constexpr uint32_t K = 8;        // insert pairs per thread kept in registers; more go through res
-    const uint32_t d = SF_ROWS(D, g);
-    uint32_t row, range;
-    owner_of(og, d, row, range);
-    const uint32_t ci = row * og.R + range, cd = d * og.R + ci;
+    const uint32_t d = og.d;
+    uint32_t row, q;
+    owner_of(og, d, row, q);
+    const uint32_t ci = row * og.R + q, cd = d * og.R + ci;
     const uint32_t fi0 = pm_f ? pm_f->start[ci] : 0u, fi1 = pm_f ? pm_f->start[ci + 1] : 0u;
     const uint32_t fd0 = pm_f ? pm_f->start[cd] : 0u, fd1 = pm_f ? pm_f->start[cd + 1] : 0u;
     const uint32_t i0 = pm_i ? pm_i->start[ci] : 0u, i1 = pm_i ? pm_i->start[ci + 1] : 0u;
     if (fi0 == fi1 && fd0 == fd1 && i0 == i1) return;  // the range's records stay as they are
-    const uint32_t z = g.z, rs = g.rs, zmask = (1u << og.zbits) - 1;
+    uint32_t sk, range;
+    rm.range_of(q, sk, range);
+    const SketchDesc sd = sr.of(sk);
+    const uint32_t z = sd.g.z, rs = sd.g.rs, zmask = (1u << og.zbits) - 1;
     const uint32_t cell0 = range << og.cr_shift;
-    const uint32_t ncells = min(1u << og.cr_shift, g.w - cell0);
+    const uint32_t ncells = min(1u << og.cr_shift, sd.g.w - cell0);
     const uint32_t nw = ncells * rs;
-    uint32_t* rec0 = rec_all + (size_t(row) * g.w + cell0) * rs;
+    uint32_t* rec0 = sd.fat + (size_t(row) * sd.g.w + cell0) * rs;
     // the range in 16-byte pieces where it is 16-byte aligned, several loads in
     // flight per thread
     const bool vec = (reinterpret_cast<uintptr_t>(rec0) & 15u) == 0;

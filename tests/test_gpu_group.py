@@ -38,11 +38,12 @@ def _check_group(G, m, refs):
         assert_same(ans[int(m.qseg[i]):int(m.qseg[i + 1])], refs[i][2], f"queries of sketch {i}")
 
 
-@pytest.mark.parametrize("merge", [True, False])
+@pytest.mark.parametrize("merge", [1, 2, 0])
 @pytest.mark.parametrize("graph", [True, False])
 @pytest.mark.parametrize("round_ops", [0, 20_000])
 def test_group_matches_oracle_per_sketch(graph, round_ops, merge):
-    """48 sketches of different widths, stream lengths and batch sizes, mixed ops."""
+    """48 sketches of different widths, stream lengths and batch sizes, mixed ops; owner-
+    computes (1), atomic (2) and per-tile (0) merge paths."""
     import torch
     m = sfgen.config_multi(seed=3, n_sketches=48, length_scale=0.03, fat_log2=(8, 13))
     rng = np.random.default_rng(1)
@@ -52,6 +53,7 @@ def test_group_matches_oracle_per_sketch(graph, round_ops, merge):
     G = sf.SketchGroup(cfgs, round_ops=round_ops)
     G.set_graph(graph)
     G.set_merge(merge)
+    assert G.merge_path() == merge
     G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
     sub, tiles = G.rounds()
     say(f"  sub-rounds {sub}, tiles {tiles}")
@@ -160,8 +162,46 @@ def test_group_mixed_rows_and_flow_keys():
     d = rng.integers(1, 9, n)
     cfgs = _cfgs(m.w, d, rng.choice([333, 4096], n), kb=13, seeds=rng.integers(1, 100, n))
     G = sf.SketchGroup(cfgs)
+    assert G.merge_path() == 2                     # rows differ: atomic S1..S5
     G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
     _check_group(G, m, _oracle_parts(m, cfgs, kb=13))
+    G.close()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_group_owner_ranges_split_subrounds(graph):
+    """Wide sketches (32 ranges of 2048 cells per row each): a sub-round holds at most 1024
+    ranges per row, so rounds split by ranges as well as by ops; the owner path still gives
+    every sketch the oracle's state.  Two update calls, the second with other segments."""
+    import torch
+    m = sfgen.config_multi(seed=5, n_sketches=40, length_scale=0.02, fat_log2=(18, 18))
+    cfgs = _cfgs(m.w, np.full(m.n, 4), np.full(m.n, 1 << 14))
+    say(f"[case] group owner range cap n={m.n} ops={m.keys.size} graph={graph}")
+    G = sf.SketchGroup(cfgs)
+    G.set_graph(graph)
+    assert G.merge_path() == 1
+    seg = m.seg.astype(np.int64)
+    lens = np.diff(seg)
+    n1 = lens // 2
+    # first call: the first half of every stream; second: the rest
+    idx1 = np.concatenate([np.arange(seg[i], seg[i] + n1[i]) for i in range(m.n)])
+    idx2 = np.concatenate([np.arange(seg[i] + n1[i], seg[i + 1]) for i in range(m.n)])
+    seg1 = np.concatenate([[0], np.cumsum(n1)]).astype(np.uint64)
+    seg2 = np.concatenate([[0], np.cumsum(lens - n1)]).astype(np.uint64)
+    G.update(dev_keys(m.keys[idx1]), torch.from_numpy(m.ops[idx1]).cuda(), seg1)
+    sub, tiles = G.rounds()
+    say(f"  first call: sub-rounds {sub}, tiles {tiles}")
+    assert sub > int(np.ceil(n1 / (1 << 14)).max())     # 40 x 32 ranges > 1024 per sub-round
+    G.update(dev_keys(m.keys[idx2]), torch.from_numpy(m.ops[idx2]).cuda(), seg2)
+    refs = []
+    for i, c in enumerate(cfgs):
+        k, o, q = m.part(i)
+        n1_i = int(n1[i])
+        ref = oracle.Sketch(c.d, c.w, c.z, 4, c.seed_base)
+        assert ref.batch(k[:n1_i], o[:n1_i], c.batch_ops, checked=True) == 0
+        assert ref.batch(k[n1_i:], o[n1_i:], c.batch_ops, checked=True) == 0
+        refs.append((ref.fat(), ref.slim(), ref.query(q)))
+    _check_group(G, m, refs)
     G.close()
 
 
@@ -178,9 +218,10 @@ def test_group_equals_lone_sketches_and_tiles():
         s.sync()
         lone.append((s.export_fat(), s.export_slim(), s.query(dev_keys(q)).cpu().numpy().view(np.uint32)))
         s.close()
-    for merge, tile in ((True, 2048), (False, 256), (False, 2048)):
+    for merge, tile in ((1, 2048), (2, 2048), (0, 256), (0, 2048)):
         G = sf.SketchGroup(cfgs)
         G.set_merge(merge)
+        assert G.merge_path() == merge
         G.set_tile(tile)
         G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
         _check_group(G, m, lone)
