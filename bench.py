@@ -654,6 +654,7 @@ def gpu_leg(args, torch, np, sf, wl, b: int, leg: str, steps: int, warmup: int) 
     sk = sf.Sketch(wl.d, wl.w, wl.z, key_bytes=kb, batch_ops=b)
     sk.set_tile(args.tile)
     sk.set_merge({"batch": 1, "atomic": 2, "owner": 3, "tile": 0}[args.merge])
+    sk.set_streams({"auto": -1, "one": 0, "two": 1}[args.streams])
 
     def step():
         sk.reset()
@@ -814,6 +815,8 @@ def main():
                     help="batch: batch-wide merge + owner-computes S1..S5 for batches of at least w ops; "
                          "atomic: batch-wide merge + atomic S1..S5; owner: owner-computes for every batch; "
                          "tile: per-tile merging")
+    ap.add_argument("--streams", choices=("auto", "one", "two"), default="auto",
+                    help="owner path: partition of the next batch on a second stream (sf_set_streams)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

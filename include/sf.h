@@ -229,6 +229,16 @@ int sf_set_merge(sf_sketch *sk, int batch_wide);
  * or 3 reads 2 when the shape does not fit the owner path. */
 int sf_merge_path(sf_sketch *sk);
 
+/* Streams of the owner path.  With 1 the partition, merge and pair kernels of
+ * batch k + 1 run on a second stream of the sketch's (created with the owner
+ * buffers, default priority) while the owner steps of batch k run on its own
+ * stream; events order the two, and every update call returns with all of
+ * its work ordered on the sketch's stream, as with 0 (one stream).  -1 (the
+ * default) takes 1 when the cell records (d * w * (z + 1) * 4 bytes) exceed
+ * 256 MiB, the Infinity Cache, and 0 otherwise.  Results are the same either
+ * way.  SF_EINVAL for other values. */
+int sf_set_streams(sf_sketch *sk, int mode);
+
 /* Merged entries (distinct keys per merge chunk) the batch-wide merge has
  * emitted since sf_create, for inserts and deletes; waits for the stream. */
 int sf_merge_stats(sf_sketch *sk, uint64_t *insert_entries, uint64_t *delete_entries);

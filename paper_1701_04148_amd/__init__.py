@@ -67,6 +67,7 @@ SIGNATURES = {
     "sf_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_set_merge": (_I, [_P, _I]),
     "sf_merge_path": (_I, [_P]),
+    "sf_set_streams": (_I, [_P, _I]),
     "sf_update_host": (_I, [_P, _P, _P, _U64, _U64]),
     "sf_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_profile": (_I, [_P, _I]),
@@ -373,6 +374,11 @@ class Sketch:
         across the batch with atomic S1..S5 (2), or with owner-computes for every batch (3)."""
         mode = int(batch_wide) if not isinstance(batch_wide, bool) else int(batch_wide)
         _check(lib().sf_set_merge(self._h, mode), "sf_set_merge")
+
+    def set_streams(self, mode: int):
+        """Owner path: partition side of the next batch on a second stream (1), one stream (0),
+        or by batch size (-1, the default)."""
+        _check(lib().sf_set_streams(self._h, int(mode)), "sf_set_streams")
 
     def merge_path(self) -> int:
         """0 per-tile merging, 1 batch merge + owner-computes S1..S5 for large batches, 2 batch

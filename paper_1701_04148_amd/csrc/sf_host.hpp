@@ -230,13 +230,27 @@ inline bool owner_geom(const sf_config* c, OwnerGeom* og) {
 struct OwnerBufs {
     OwnerGeom og;
     uint64_t* pairs[2];  // [d * cap] pairs, in column order
-    PairMeta* pm[2];
+    PairMeta* pm[3];     // column starts (a sketch table uses set 0 only)
     uint32_t* pos;       // [d][cap] position of each insert entry's pair per row
     uint64_t* res;       // [d * cap] per insert pair: Slim before, growth, Fat after (16 bits each)
     uint16_t* level;     // [cap] T of each insert entry
     uint32_t* hmat;      // [pair_tiles_max(cap)][ncol] per-tile column counts, then offsets
-    uint32_t cur = 0;
+    uint32_t cur = 0;    // pairs set of the next batch
+    uint32_t pmc = 0;    // column-start set of the next batch
     bool pending = false;
+    // Lone sketch: the partition, merge and pair kernels run on `side` (when
+    // set), the owner steps and k_level on the sketch's stream.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_main = nullptr;  // the sketch's stream up to here (side waits before its next batch)
+    hipEvent_t ev_p = nullptr;     // a batch's pairs written (the sketch's stream waits)
+    hipEvent_t ev_l = nullptr;     // a batch's k_level done (side waits before writing pairs and pos)
+    bool use_side = false;         // run the partition side there (set per update call)
+    bool join = true;              // side must first wait for the sketch's stream
+    bool l_rec = false;            // ev_l holds the previous batch's k_level
+    hipError_t err = hipSuccess;   // first failed event call since the last check
+    void mark(hipError_t e) {
+        if (e != hipSuccess && err == hipSuccess) err = e;
+    }
 };
 
 // LDS of one owner step: the range's records.
@@ -248,10 +262,10 @@ inline size_t own_step_lds(const Geom& g, const OwnerGeom& og) {
 inline void owner_close(OwnerBufs* own, const Geom& g, uint32_t* fat, uint32_t* slim, hipStream_t st,
                         Profiler* prof) {
     if (!own->pending) return;
-    const uint32_t prev = own->cur ^ 1u;
+    const uint32_t prev = own->cur ^ 1u, pprev = (own->pmc + 2u) % 3u;
     Timed tm(prof, st, SF_K_OWN_FINAL, 0);
     k_own_step<OneSketch, LoneRanges><<<g.d * own->og.R, kOwnThreads, own_step_lds(g, own->og), st>>>(
-        OneSketch{g, fat, slim}, LoneRanges{}, own->og, own->pm[prev], own->pairs[prev], own->level, nullptr,
+        OneSketch{g, fat, slim}, LoneRanges{}, own->og, own->pm[pprev], own->pairs[prev], own->level, nullptr,
         nullptr, own->res);
     own->pending = false;
 }
@@ -279,10 +293,11 @@ struct MergeRun {
     uint32_t max_z = 0;
 
     template <int D, class SR>
-    void launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st, Profiler* prof) const;
-    template <class SR, class RM>
-    void launch_pairs(uint32_t cnt, const SR& sr, const RM& rm, const OwnerGeom& og, uint32_t set, hipStream_t st,
+    void launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st, hipStream_t ps,
                       Profiler* prof) const;
+    template <class SR, class RM>
+    void launch_pairs(uint32_t cnt, const SR& sr, const RM& rm, const OwnerGeom& og, uint32_t set, uint32_t pset,
+                      hipStream_t st, Profiler* prof, hipEvent_t before_scatter = nullptr) const;
 
     // part_groups: workgroups of the partition kernels (plan tiles of at most
     // kPartOps ops); cnt: ops in the batch (<= cap).
@@ -298,28 +313,42 @@ struct MergeRun {
         const unsigned xg = kXcds * (blocks_for(uint64_t(eg) * (D > 0 ? D : 1), kXcds) < 1024u
                                          ? blocks_for(uint64_t(eg) * (D > 0 ? D : 1), kXcds)
                                          : 1024u);
+        // A lone sketch's owner path runs partition, merge and pairs on the side
+        // stream (not while profiling: the per-kind events then time one stream)
+        hipStream_t ps = st;
+        if (!G && own && own->side && own->use_side && !(prof && prof->on)) {
+            ps = own->side;
+            if (own->join) {  // the keys (and everything before) are the sketch stream's
+                own->mark(hipEventRecord(own->ev_main, st));
+                own->mark(hipStreamWaitEvent(ps, own->ev_main, 0));
+                own->join = false;
+                own->l_rec = false;
+            }
+        } else if (own) {
+            own->join = true;
+        }
         {
-            Timed tm(prof, st, SF_K_PARTITION, cnt);
-            k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, nb_log2);
+            Timed tm(prof, ps, SF_K_PARTITION, cnt);
+            k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, nb_log2);
             // one lane per bucket pays off for 512..1024 rows; fewer rows (small
             // batches) or more (sketch tables) spread better over segments
             if (part_groups >= kScanWaves * kScanRowsReg / 2 && part_groups <= kScanWaves * kScanRowsReg)
-                k_part_colscan<uint32_t><<<blocks_for(2 * nb, kScanCols), kScanCols * kScanWaves, 0, st>>>(
+                k_part_colscan<uint32_t><<<blocks_for(2 * nb, kScanCols), kScanCols * kScanWaves, 0, ps>>>(
                     hist, part_groups, 2 * nb, meta);
             else
-                k_part_colscan_tall<uint32_t><<<blocks_for(2 * nb, kScanBuckets), kScanBuckets * kScanSegs, 0, st>>>(
+                k_part_colscan_tall<uint32_t><<<blocks_for(2 * nb, kScanBuckets), kScanBuckets * kScanSegs, 0, ps>>>(
                     hist, part_groups, 2 * nb, meta);
-            k_part_start<KB, G><<<1, 2 * nb / kStartPer, 0, st>>>(meta, chunks);
-            k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, st>>>(plan, hist, meta, part, nb_log2);
+            k_part_start<KB, G><<<1, 2 * nb / kStartPer, 0, ps>>>(meta, chunks);
+            k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, meta, part, nb_log2);
         }
         {
-            Timed tm(prof, st, SF_K_MERGE, cnt);
+            Timed tm(prof, ps, SF_K_MERGE, cnt);
             k_merge<KB, G, SR><<<blocks_for(cnt, MergeShape<KB, G>::kChunk) + 2 * nb, MergeShape<KB, G>::kThreads, 0,
-                                 st>>>(part, meta, chunks, ent_key, ent_cnt, cap, nb_log2, sr, bpre, asnap,
+                                 ps>>>(part, meta, chunks, ent_key, ent_cnt, cap, nb_log2, sr, bpre, asnap,
                                        own ? 0u : 1u);
         }
         if (own) {
-            launch_owner<D>(cnt, sr, ins, del, st, prof);
+            launch_owner<D>(cnt, sr, ins, del, st, ps, prof);
             return;
         }
         if (ins) {
@@ -358,47 +387,61 @@ struct MergeRun {
 template <int KB, bool G>
 template <class SR, class RM>
 void MergeRun<KB, G>::launch_pairs(uint32_t cnt, const SR& sr, const RM& rm, const OwnerGeom& og, uint32_t set,
-                                   hipStream_t st, Profiler* prof) const {
+                                   uint32_t pset, hipStream_t st, Profiler* prof, hipEvent_t before_scatter) const {
     const unsigned tiles = pair_tiles_max(cnt);
     Timed tm(prof, st, SF_K_PAIRS, cnt);
     k_pair_count<KB, G, SR, RM><<<dim3(tiles, og.d), kCountThreads, 0, st>>>(meta, ent_key, cap, sr, rm, og,
                                                                             own->hmat);
     k_pair_colscan<><<<blocks_for(og.ncol, kScanCols), kScanCols * kScanWaves, 0, st>>>(own->hmat, meta,
-                                                                                      own->pm[set], og.ncol);
-    k_pair_start<><<<1, 1024, 0, st>>>(own->pm[set], og.ncol, meta);
+                                                                                      own->pm[pset], og.ncol);
+    k_pair_start<><<<1, 1024, 0, st>>>(own->pm[pset], og.ncol, meta);
+    if (before_scatter) own->mark(hipStreamWaitEvent(st, before_scatter, 0));
     k_pair_scatter<KB, G, SR, RM><<<dim3(tiles, og.d), kPairThreads, 0, st>>>(
-        meta, ent_key, ent_cnt, cap, sr, rm, og, own->hmat, own->pm[set], own->pairs[set], own->pos, cap);
+        meta, ent_key, ent_cnt, cap, sr, rm, og, own->hmat, own->pm[pset], own->pairs[set], own->pos, cap);
 }
 
 template <int KB, bool G>
 template <int D, class SR>
-void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st,
+void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st, hipStream_t ps,
                                    Profiler* prof) const {
     const unsigned tiles = pair_tiles_max(cnt);
     if constexpr (!G) {
         // lone sketch: this batch's S1 + S2 share one owner step with the
-        // previous batch's S3..S5; its own S3..S5 wait for the next step
+        // previous batch's S3..S5; its own S3..S5 wait for the next step.  The
+        // pairs come from ps; their scatter overwrites pairs and pos of two
+        // batches back, which the previous batch's step and k_level read.
         const OwnerGeom& og = own->og;
         const uint32_t set = own->cur, prev = set ^ 1u;
-        launch_pairs(cnt, sr, LoneRanges{}, og, set, st, prof);
+        const uint32_t pset = own->pmc, pprev = (own->pmc + 2u) % 3u;
+        const bool two = ps != st;
+        launch_pairs(cnt, sr, LoneRanges{}, og, set, pset, ps, prof, two && own->l_rec ? own->ev_l : nullptr);
+        if (two) {
+            own->mark(hipEventRecord(own->ev_p, ps));
+            own->mark(hipStreamWaitEvent(st, own->ev_p, 0));
+        }
         {
             Timed tm(prof, st, SF_K_OWN_STEP, cnt);
             k_own_step<SR, LoneRanges><<<og.d * og.R, kOwnThreads, own_step_lds(sr.g, og), st>>>(
-                sr, LoneRanges{}, og, own->pending ? own->pm[prev] : nullptr,
-                own->pending ? own->pairs[prev] : nullptr, own->level, ins ? own->pm[set] : nullptr,
+                sr, LoneRanges{}, og, own->pending ? own->pm[pprev] : nullptr,
+                own->pending ? own->pairs[prev] : nullptr, own->level, ins ? own->pm[pset] : nullptr,
                 ins ? own->pairs[set] : nullptr, own->res);
         }
         if (ins) {
             Timed tm(prof, st, SF_K_LEVEL, cnt);
-            k_level<D><<<tiles, kPairThreads, 0, st>>>(meta, own->pos, cap, own->res, og.d, own->level);
+            k_level<D><<<tiles, kPairThreads, 0, st>>>(own->pm[pset], own->pos, cap, own->res, og.d, own->level);
+        }
+        if (two) {
+            own->mark(hipEventRecord(own->ev_l, st));
+            own->l_rec = true;
         }
         own->pending = true;  // this batch's S3..S5 (raise, deletes, clamp) come next
         own->cur = prev;
+        own->pmc = (own->pmc + 1u) % 3u;
     } else {
         // sketch table: every sub-round is finished at once (the next one holds
         // other sketches): pairs, S1 + S2, T, then S3..S5
         const OwnerGeom og = sub_og;
-        launch_pairs(cnt, sr, sub_rm, og, 0u, st, prof);
+        launch_pairs(cnt, sr, sub_rm, og, 0u, 0u, st, prof);
         const size_t lds = size_t(1) << og.cr_shift;
         const size_t lds_bytes = lds * (max_z + 1) * 4;
         if (ins) {
@@ -408,13 +451,14 @@ void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool de
                     sr, sub_rm, og, nullptr, nullptr, own->level, own->pm[0], own->pairs[0], own->res);
             }
             Timed tm(prof, st, SF_K_LEVEL, cnt);
-            k_level<D><<<tiles, kPairThreads, 0, st>>>(meta, own->pos, cap, own->res, og.d, own->level);
+            k_level<D><<<tiles, kPairThreads, 0, st>>>(own->pm[0], own->pos, cap, own->res, og.d, own->level);
         }
         Timed tm(prof, st, SF_K_OWN_FINAL, cnt);
         k_own_step<SR, TableRanges><<<og.d * og.R, kOwnThreads, lds_bytes, st>>>(
             sr, sub_rm, og, own->pm[0], own->pairs[0], own->level, nullptr, nullptr, own->res);
     }
     (void)del;
+    (void)ps;
 }
 
 template <template <int> class PT>

@@ -64,6 +64,7 @@ struct sf_sketch {
     bool owner_ok;    // the shape fits the owner-computes path
     bool owner_on;    // S1..S5 by (row, cell range) owners for large batches (else the entry kernels)
     bool owner_all;   // ... for every batch, however small (merge mode 3)
+    int streams = -1; // owner path: partition side on a second stream (1), not (0), by batch size (-1)
     OwnerBufs own;
     char* own_base = nullptr;  // the owner path's buffers: their own allocation, held while mode 1 is set
     Profiler prof;
@@ -128,7 +129,7 @@ Sizes sizes_of(const sf_config* c) {
         s.res = round256(d * b * 8);
         s.level = round256(b * 2);
         s.hmat = round256(uint64_t(pair_tiles_max(uint32_t(b))) * og.ncol * 4);
-        s.pmeta = 2 * round256(sizeof(PairMeta));
+        s.pmeta = 3 * round256(sizeof(PairMeta));
     }
     return s;
 }
@@ -144,11 +145,21 @@ void close_owner(sf_sketch* s) { owner_close(&s->own, s->g, s->fat, s->slim, s->
 // asks for the owner path always.
 bool use_owner(const sf_sketch* s, uint32_t cnt) { return s->owner_on && (s->owner_all || cnt >= s->cfg.w); }
 
+// Record arrays above the 256 MiB Infinity Cache: the owner steps then wait
+// on HBM, and the partition side of the next batch fills that time (measured:
+// 6 % per step for 8 rows of 2^21 cells).  Smaller sketches keep one stream by
+// default: their owner steps run from the cache, both sides compete for the
+// same CUs, and each cross-stream wait adds several microseconds.
+constexpr uint64_t kSideStreamRecords = 256ull << 20;
+
 // Batch-wide merge: partition, merge, then S1..S5 over the entries.
 template <int KB, int D>
 void launch_merged(sf_sketch* s, const UniformPlan<KB>& plan, uint32_t cnt, bool ins, bool del) {
     const bool own = use_owner(s, cnt);
-    if (!own) close_owner(s);  // the atomic kernels read records the pending step still changes
+    if (!own) {
+        close_owner(s);       // the atomic kernels read records the pending step still changes
+        s->own.join = true;   // and use the merge buffers on the sketch's stream
+    }
     MergeRun<KB, false> run{static_cast<MKey<KB, false>*>(s->part), static_cast<MKey<KB, false>*>(s->ent_key),
                             s->ent_cnt, s->meta, s->hist, s->chunks, s->stride, s->bpre, s->asnap, s->stride,
                             own ? &s->own : nullptr};
@@ -186,6 +197,7 @@ int run_updates(sf_sketch* s, const void* keys, const uint8_t* ops, uint64_t n, 
     const uint64_t b = s->cfg.batch_ops;
     s->view_fresh = false;
     const uint32_t mode = kind == kMixed ? kOpsArray : kind == kDelete ? kAllDelete : kAllInsert;
+    s->own.use_side = s->streams < 0 ? sizes_of(&s->cfg).fat > kSideStreamRecords : s->streams == 1;
     for (uint64_t lo = 0; lo < n; lo += b) {
         const uint32_t cnt = uint32_t(n - lo < b ? n - lo : b);
         const uint8_t* kp = k8 + lo * kb;
@@ -194,7 +206,10 @@ int run_updates(sf_sketch* s, const void* keys, const uint8_t* ops, uint64_t n, 
         else launch_batch<13>(s, kp, op, mode, cnt, kind != kDelete, kind != kInsert);
     }
     close_owner(s);  // the call's last batch: its S3..S5
+    s->own.join = true;
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = s->own.err;
+    s->own.err = hipSuccess;
     return e == hipSuccess ? SF_OK : device_fail(e, "update launch");
 }
 
@@ -262,6 +277,16 @@ int query_common(Profiler* prof, const sf_config* c, const Geom& g, const void* 
 
 // The owner path's buffers (a separate allocation, so that a sketch switched
 // to another merge mode gives them back).
+void owner_streams_free(sf_sketch* s) {
+    if (s->own.side) (void)hipStreamSynchronize(s->own.side);
+    if (s->own.ev_main) (void)hipEventDestroy(s->own.ev_main);
+    if (s->own.ev_p) (void)hipEventDestroy(s->own.ev_p);
+    if (s->own.ev_l) (void)hipEventDestroy(s->own.ev_l);
+    if (s->own.side) (void)hipStreamDestroy(s->own.side);
+    s->own.side = nullptr;
+    s->own.ev_main = s->own.ev_p = s->own.ev_l = nullptr;
+}
+
 int owner_alloc(sf_sketch* s) {
     const Sizes sz = sizes_of(&s->cfg);
     char* ob = nullptr;
@@ -278,10 +303,26 @@ int owner_alloc(sf_sketch* s) {
     s->own.res = reinterpret_cast<uint64_t*>(ob + sz.pairs + sz.pos);
     s->own.level = reinterpret_cast<uint16_t*>(ob + sz.pairs + sz.pos + sz.res);
     s->own.hmat = reinterpret_cast<uint32_t*>(ob + sz.pairs + sz.pos + sz.res + sz.level);
-    s->own.pm[0] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat);
-    s->own.pm[1] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat + sz.pmeta / 2);
+    for (int i = 0; i < 3; i++)
+        s->own.pm[i] = reinterpret_cast<PairMeta*>(ob + sz.pairs + sz.pos + sz.res + sz.level + sz.hmat +
+                                                   i * (sz.pmeta / 3));
     s->own.cur = 0;
+    s->own.pmc = 0;
     s->own.pending = false;
+    s->own.join = true;
+    if (!s->own.side) {  // the stream the partition side of the owner path runs on
+        e = hipStreamCreateWithFlags(&s->own.side, hipStreamNonBlocking);  // default priority
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->own.ev_main, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->own.ev_p, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->own.ev_l, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            owner_streams_free(s);
+            (void)hipFree(ob);
+            s->own_base = nullptr;
+            return device_fail(e, "owner-path stream");
+        }
+    }
     s->owner_on = true;
     return SF_OK;
 }
@@ -290,6 +331,7 @@ int owner_free(sf_sketch* s) {
     s->owner_on = false;
     if (!s->own_base) return SF_OK;
     hipError_t e = hipStreamSynchronize(s->stream);  // no launch may still read them
+    if (e == hipSuccess && s->own.side) e = hipStreamSynchronize(s->own.side);
     if (e == hipSuccess) e = hipFree(s->own_base);
     s->own_base = nullptr;
     return e == hipSuccess ? SF_OK : device_fail(e, "owner-path buffers free");
@@ -403,6 +445,8 @@ int sf_create(const sf_config* cfg, uint64_t hbm_budget_bytes, void* hip_stream,
     if (e == hipSuccess) e = hipMemsetAsync(base, 0, sz.fat + sz.slim, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
+        owner_streams_free(s);
+        if (s->own_base) (void)hipFree(s->own_base);
         (void)hipFree(base);
         delete s;
         return device_fail(e, "sf_create zeroing");
@@ -435,6 +479,7 @@ int sf_destroy(sf_sketch* s) {
         if (s->qs[j]) (void)hipStreamDestroy(s->qs[j]);
     }
     if (s->qready) (void)hipEventDestroy(s->qready);
+    owner_streams_free(s);
     if (s->own_base) (void)hipFree(s->own_base);
     hipError_t e2 = hipFree(s->fat);
     delete s;
@@ -717,6 +762,7 @@ int sf_export_fat(sf_sketch* s, uint32_t* out, uint64_t out_elems) {
 int sf_sync(sf_sketch* s) {
     if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
     hipError_t e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess && s->own.side) e = hipStreamSynchronize(s->own.side);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_sync");
 }
 
@@ -736,6 +782,13 @@ int sf_set_merge(sf_sketch* s, int batch_wide) {
     if ((batch_wide == 1 || batch_wide == 3) && s->owner_ok)
         return s->own_base ? (s->owner_on = true, SF_OK) : owner_alloc(s);
     return owner_free(s);
+}
+
+int sf_set_streams(sf_sketch* s, int mode) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    if (mode < -1 || mode > 1) return fail(SF_EINVAL, "streams mode must be -1, 0 or 1");
+    s->streams = mode;
+    return SF_OK;
 }
 
 int sf_merge_path(sf_sketch* s) {

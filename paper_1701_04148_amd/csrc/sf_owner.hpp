@@ -1,4 +1,5 @@
-// Owner-computes S1..S5 for a lone sketch on the batch-wide merge path.
+// Owner-computes S1..S5 on the batch-wide merge path (a lone sketch, or the
+// sub-rounds of a sketch table).
 //
 // After the merge each entry (a distinct key of a merge chunk, with its
 // count) touches one cell in each of the d rows.  Instead of d random record
@@ -25,7 +26,11 @@
 //                   of one tile sit in short runs, so one fetched line serves
 //                   several of the tile's entries)
 // The last batch of an update call ends with a k_own_step that has no next
-// batch.
+// batch.  A lone sketch runs the partition, merge and pair kernels of batch
+// k + 1 on a second stream while k_own_step and k_level of batch k run: they
+// read keys and entries only, and the buffers the two sides share are kept
+// apart (three sets of column starts, two of pairs; k_pair_scatter of batch
+// k + 1, which writes pairs and pos, waits for k_level of batch k).
 //
 // Same results as the entry kernels of sf_kernels.hpp, bit for bit: S2 and S4
 // are sums, S3 a maximum and S5 a minimum per cell, and every pair of a key
@@ -95,6 +100,7 @@ struct TableRanges {
 struct PairMeta {
     uint32_t total[kMaxCols];      // pairs per column
     uint32_t start[kMaxCols + 1];  // first pair of each column; [ncol] = all pairs
+    uint32_t n_ins, n_del;         // the batch's insert and delete entries (copied from the merge)
 };
 
 // A pair: entry index (low word); local code (cell in range << zbits | slot)
@@ -166,8 +172,9 @@ __global__ __launch_bounds__(kScanCols * kScanWaves) void k_pair_colscan(uint32_
     colscan_wide<uint32_t>(hmat, (nv + T - 1) / T, ncol, pm->total);
 }
 
-// Column starts: one workgroup, thread t owns columns kPer*t ...  Also adds
-// the batch's entries to the merge statistics.
+// Column starts: one workgroup, thread t owns columns kPer*t ...  Also keeps
+// the batch's entry counts beside them (the merge metadata is the next
+// batch's once its partition starts) and adds them to the merge statistics.
 template <int = 0>
 __global__ __launch_bounds__(1024) void k_pair_start(PairMeta* __restrict__ pm, uint32_t ncol,
                                                      MergeMeta* __restrict__ meta) {
@@ -189,6 +196,8 @@ __global__ __launch_bounds__(1024) void k_pair_start(PairMeta* __restrict__ pm, 
     }
     if (threadIdx.x == 1023) pm->start[ncol] = run;
     if (threadIdx.x == 0) {
+        pm->n_ins = meta->n_ins;
+        pm->n_del = meta->n_del;
         meta->acc_ins += meta->n_ins;
         meta->acc_del += meta->n_del;
     }
@@ -284,12 +293,12 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
 // T of every insert entry from its d pairs.  One workgroup per tile of the
 // pair partition, so the runs its pairs were written in serve its entries.
 template <int D>
-__global__ __launch_bounds__(kPairThreads) void k_level(const MergeMeta* __restrict__ meta,
+__global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restrict__ pm,
                                                         const uint32_t* __restrict__ pos, uint32_t pos_stride,
                                                         const uint64_t* __restrict__ res, uint32_t d_rt,
                                                         uint16_t* __restrict__ level) {
     constexpr uint32_t E = kPairTileMax / kPairThreads;
-    const uint32_t ni = meta->n_ins, T = pair_tile(ni + meta->n_del);
+    const uint32_t ni = pm->n_ins, T = pair_tile(ni + pm->n_del);
     const uint32_t lo = blockIdx.x * T;
     if (lo >= ni) return;
     const uint32_t hi = min(ni, lo + T), d = D ? uint32_t(D) : d_rt;

@@ -60,10 +60,10 @@ def test_footprint_and_budget():
     need = cells * 5 * 4 + cells * 4 * 4 + cells * 2 + 4 * b * 6 + merge + hist + chunks
     # owner-computes S1..S5 (this shape qualifies: 1024 ranges of 1024 cells per row):
     # pairs of two batches, their positions, per-pair snapshots, T per entry, per-tile
-    # column counts (b / 4096 tiles)
+    # column counts (b / 4096 tiles); column starts of three batches
     ncol = 2 * 4 * 1024
     owner = 2 * 4 * b * 8 + 4 * b * 4 + 4 * b * 8 + b * 2 + (b // 4096) * ncol * 4
-    pair_meta = 2 * (2 * 16384 + 1) * 4
+    pair_meta = 3 * (2 * 16384 + 3) * 4       # column totals and starts, entry counts (3 batches)
     need += owner
     assert fp >= need
     assert fp < need + meta + pair_meta + (8 << 10)          # plus 256-B rounding

@@ -20,13 +20,13 @@ pytestmark = pytest.mark.gpu
 MERGE_NAMES = {0: "tile", 1: "batch, owner for large batches", 2: "batch+atomic", 3: "batch+owner always"}
 
 
-def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag="", merge=0):
+def check(d, w, z, kb, keys, ops, queries, b, calls=1, seed_base=1, tag="", merge=0, streams=-1):
     """merge: 0 per-tile merging, 1 batch-wide merge with owner-computes S1..S5 for batches of
     at least w ops where the shape allows, 2 batch-wide merge with atomic S1..S5, 3 owner-computes
-    for every batch (sf_set_merge)."""
+    for every batch (sf_set_merge).  streams: the owner path's sf_set_streams mode."""
     say(f"[case] {tag} d={d} w={w} z={z} kb={kb} n={keys.shape[0]} q={queries.shape[0]} "
-        f"b={b} calls={calls} merge={MERGE_NAMES[int(merge)]}")
-    g = gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls, merge=merge)
+        f"b={b} calls={calls} merge={MERGE_NAMES[int(merge)]} streams={streams}")
+    g = gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls, merge=merge, streams=streams)
     o = oracle_run(d, w, z, kb, keys, ops, queries, b, seed_base, calls)
     assert_same(g[0], o[0], "fat")
     assert_same(g[1], o[1], "slim")
@@ -126,6 +126,44 @@ def test_main_config_scaled(skew, merge):
               merge=1)
 
 
+@pytest.mark.parametrize("d,w,z,kb,b,calls", [(4, 1024, 4, 4, 1024, 1), (3, 1000, 3, 4, 1500, 3),
+                                               (8, 512, 4, 13, 600, 2), (4, 1 << 14, 4, 4, 1 << 14, 4),
+                                               (5, 333, 2, 13, 333, 1)])
+@pytest.mark.parametrize("merge", [1, 3])
+def test_owner_two_streams(d, w, z, kb, b, calls, merge):
+    """The owner path with the next batch's partition, merge and pairs on a second stream:
+    many batches per call (so the two sides overlap and the sets of pairs and column starts
+    rotate), several calls, ragged tails that take the atomic path in mode 1."""
+    rng = np.random.default_rng(d * 13 + w + b)
+    keys, ops, uni = random_turnstile(rng, 40011, 4000, 0.25, key_bytes=kb)
+    check(d, w, z, kb, keys, ops, uni, b, calls=calls, tag="two streams", merge=merge, streams=1)
+
+
+def test_owner_two_streams_uniform_ops():
+    """Insert-only then delete-only calls (no k_level in a delete batch) on two streams."""
+    import torch
+    rng = np.random.default_rng(21)
+    keys, _, uni = random_turnstile(rng, 30000, 3000, 0.0)
+    dels = keys[rng.permutation(keys.size)[:9000]]
+    say("[case] two streams, insert then delete calls")
+    sk = sf.Sketch(4, 1024, 4, batch_ops=2048)
+    sk.set_merge(3)
+    sk.set_streams(1)
+    sk.insert(dev_keys(keys))
+    sk.delete(dev_keys(dels))
+    sk.insert(dev_keys(keys[:5000]))
+    q = sk.query(dev_keys(uni)).cpu().numpy().view(np.uint32)
+    sk.sync()
+    ref = oracle.Sketch(4, 1024, 4)
+    assert ref.batch(keys, None, 2048, True) == 0
+    assert ref.batch(dels, np.ones(dels.size, np.uint8), 2048, True) == 0
+    assert ref.batch(keys[:5000], None, 2048, True) == 0
+    assert_same(sk.export_fat(), ref.fat(), "fat")
+    assert_same(sk.export_slim(), ref.slim(), "slim")
+    assert_same(q, ref.query(uni), "query")
+    sk.close()
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("skew", [0.6, 1.0, 1.4])
 def test_main_config_full_size_as_benchmarked(skew):
@@ -135,6 +173,9 @@ def test_main_config_full_size_as_benchmarked(skew):
     wl = sfgen.config_main(skew)
     check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, batch_for_width(wl.w),
           tag=f"c2 full s={skew}", merge=1)
+    if skew == 1.0:   # the same with the partition side on a second stream
+        check(wl.d, wl.w, wl.z, 4, wl.keys, wl.ops, wl.queries, batch_for_width(wl.w),
+              tag=f"c2 full s={skew}", merge=1, streams=1)
 
 
 @pytest.mark.parametrize("merge", [0, 1, 2])
