@@ -327,7 +327,9 @@ def run_multi(args, torch, np, sf, sfgen):
             i = int(np.argmax(np.where(m.w == w, lens, -1)))
             k_i, o_i, q_i = m.part(i)
             n = min(k_i.shape[0], 1 << 21)
-            r = tune_batch(m.d, w, m.z, k_i[:n], o_i[:n], q_i, modes=(2,))   # the group's kernels
+            # b is the same whichever path runs the group (the answers do not depend on it);
+            # the atomic path's time of a lone sketch stands in for the group's per-width cost
+            r = tune_batch(m.d, w, m.z, k_i[:n], o_i[:n], q_i, modes=(2,))
             batch_of_w[w] = r.b
             tuned[str(w)] = {"b": r.b, "rule_b": batch_for_width(w), "ref_b": r.ref_b,
                              "ref_are": round(r.ref_are, 5), "bound": round(r.bound, 5),
@@ -336,10 +338,24 @@ def run_multi(args, torch, np, sf, sfgen):
             f"{ {w: v['b'] for w, v in tuned.items()} } (rule min(16 w, 2^23): "
             f"{ {w: v['rule_b'] for w, v in tuned.items()} })")
     cfgs = [sf.make_config(m.d, int(m.w[i]), m.z, 4, 1, batch_of_w[int(m.w[i])]) for i in range(m.n)]
-    G = sf.SketchGroup(cfgs)
+    group_mode = {"tile": 0, "batch": 1, "owner": 1, "atomic": 2}[args.merge]
+    round_ops = args.group_round_ops
+    shape = None
+    if not args.no_autotune and args.merge == "batch" and not round_ops:
+        # the group's merge path and launch-round size, timed on its own streams
+        from paper_1701_04148_amd.tune import tune_group
+        t_tune = time.time()
+        gs = tune_group(cfgs, keys, ops, m.seg)
+        group_mode, round_ops = gs.mode, gs.round_ops
+        shape = {"mode": gs.mode, "round_ops": gs.round_ops,
+                 "candidates": [[md, r, round(ms, 2), sub] for md, r, ms, sub in gs.table]}
+        log(f"[bench] autotuned group shape in {time.time() - t_tune:.1f}s: path {gs.mode}, round_ops "
+            f"{gs.round_ops} (candidates [path, round_ops, ms, launch rounds]: {shape['candidates']})")
+    G = sf.SketchGroup(cfgs, round_ops=round_ops)
     G.set_tile(args.tile)
-    G.set_merge({"tile": 0, "batch": 1, "owner": 1, "atomic": 2}[args.merge])
-    log(f"[bench] group merge path {G.merge_path()} (0 per tile, 1 owner-computes, 2 atomics)")
+    G.set_merge(group_mode)
+    path = G.merge_path()
+    log(f"[bench] group merge path {path} (0 per tile, 1 owner-computes, 2 atomics)")
 
     def step():
         G.reset()
@@ -424,9 +440,11 @@ def run_multi(args, torch, np, sf, sfgen):
                                "one graph-captured group update, then query every stream's universe",
                    "sketches": m.n, "ops": n_ops, "queries": n_q,
                    "batch_ops": ("autotuned per width" if tuned else "min(16 w, 2^23) per sketch"),
-                   "tile_ops": args.tile, "merge": args.merge, "launch_rounds": sub, "scale": args.scale},
+                   "tile_ops": args.tile, "merge": args.merge, "merge_path": path, "round_ops": round_ops,
+                   "launch_rounds": sub, "scale": args.scale},
         "merged_entries_per_step": {"insert": entries[0], "delete": entries[1]},
         "autotune": tuned,
+        "group_shape": shape,
         "one_sketch_per_launch": {"value": round(lone_value, 2), "unit": "Mitems/s",
                                   "ms_per_step": round(el1 * 1e3, 3)},
         "group_vs_lone": round(value / lone_value, 2),
@@ -815,6 +833,8 @@ def main():
                     help="batch: batch-wide merge + owner-computes S1..S5 for batches of at least w ops; "
                          "atomic: batch-wide merge + atomic S1..S5; owner: owner-computes for every batch; "
                          "tile: per-tile merging")
+    ap.add_argument("--group-round-ops", type=int, default=0,
+                    help="ops per launch round of the 1024-sketch group (0: the library's default)")
     ap.add_argument("--streams", choices=("auto", "one", "two"), default="auto",
                     help="owner path: partition of the next batch on a second stream (sf_set_streams)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

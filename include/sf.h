@@ -312,8 +312,9 @@ int sf_group_set_tile(sf_group *g, uint32_t tile_ops);
 /* Merge path of the group (default 1): 0 per-tile merging; 1 batch-wide
  * merging with owner-computes S1..S5 when every sketch has the same d and z
  * (ranges of 2^k cells, k the largest with at most 8192 Fat counters and a
- * 16-bit local code per range; a sub-round then also holds at most 1024
- * ranges per row), else as 2; 2 batch-wide merging with atomic S1..S5.
+ * 16-bit local code per range; a sub-round then also holds at most
+ * min(1024, 8192 / d) ranges per row, and no sketch may have more), else as
+ * 2; 2 batch-wide merging with atomic S1..S5.
  * Batch-wide merging treats each (key, sketch) pair as one key; merged
  * sub-rounds hold at most 2^24 ops (or the largest batch_ops), tiles of the
  * per-tile path at most round_ops.  The owner-path buffers (counted by

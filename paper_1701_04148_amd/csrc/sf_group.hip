@@ -123,19 +123,27 @@ struct Layout {
     uint64_t owner_bytes() const { return pairs + pos + res + level + hmat + pmeta; }
 };
 
+// Ranges per row one sub-round may hold: the pair kernels' tables, as far as
+// the columns of both op types over d rows fit kMaxCols.  (Twice as many
+// ranges per sub-round, in wider tables, measured slower: larger sub-rounds
+// spread a bucket over more merge chunks, which merge fewer duplicates.)
+inline uint32_t table_range_cap(uint32_t d) { return std::min<uint32_t>(kMaxRanges, kMaxCols / (2 * d)); }
+
 // The owner path for a sketch table: every sketch with the same d and z;
 // ranges of 2^k cells, k the largest with at most 8192 Fat counters per range
-// (and a 16-bit local code), at most kMaxRanges per row in one sub-round.
+// (and a 16-bit local code), at most table_range_cap(d) per row in one
+// sub-round.
 bool group_owner_geom(uint32_t n, const sf_config* cfgs, OwnerGeom* og) {
     for (uint32_t i = 1; i < n; i++)
         if (cfgs[i].d != cfgs[0].d || cfgs[i].z != cfgs[0].z) return false;
     const uint32_t d = cfgs[0].d, z = cfgs[0].z;
-    if (2 * d * kMaxRanges > kMaxCols) return false;
     uint32_t zbits = 0;
     while ((1ull << zbits) < z) zbits++;
     uint32_t sh = 4;
     while ((2ull << sh) * z <= kOwnCounters && ((2ull << sh) << zbits) <= 65536) sh++;
     if ((1ull << sh) * z > kOwnCounters || ((1ull << sh) << zbits) > 65536) return false;
+    for (uint32_t i = 0; i < n; i++)  // each sketch fits a sub-round on its own
+        if (((uint64_t(cfgs[i].w) + (1ull << sh) - 1) >> sh) > table_range_cap(d)) return false;
     *og = OwnerGeom{};
     og->cr_shift = sh;
     og->zbits = zbits;
@@ -197,7 +205,7 @@ int layout_of(uint32_t n, const sf_config* cfgs, uint64_t round_ops, Layout& L) 
         L.pos = round256(d * mr * 4);
         L.res = round256(d * mr * 8);
         L.level = round256(mr * 2);
-        L.hmat = round256(uint64_t(pair_tiles_max(uint32_t(mr))) * 2 * d * kMaxRanges * 4);
+        L.hmat = round256(uint64_t(pair_tiles_max(uint32_t(mr))) * 2 * d * table_range_cap(uint32_t(d)) * 4);
         L.pmeta = round256(sizeof(PairMeta));
         L.total += L.owner_bytes();
     }
@@ -256,6 +264,7 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
     g->plan.clear();
     g->subrounds.clear();
     const bool owner = g->merge && g->owner_on;
+    const uint32_t qcap = owner ? table_range_cap(g->own_og.d) : 0u;
     auto ranges_of = [&](uint32_t s) {
         return owner ? uint32_t((uint64_t(g->cfg[s].w) + (1ull << g->own_og.cr_shift) - 1) >> g->own_og.cr_shift)
                      : 0u;
@@ -278,7 +287,7 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
             const uint64_t cnt = std::min(b, seg[s + 1] - lo);
             const uint64_t tiles = (cnt + tile_ops - 1) / tile_ops;
             if (used && (used + cnt > limit || g->plan.size() - first + tiles > max_tiles ||
-                         q + ranges_of(s) > kMaxRanges)) {  // close the sub-round
+                         q + ranges_of(s) > qcap)) {  // close the sub-round
                 g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used, q});
                 first = uint32_t(g->plan.size());
                 used = 0;

@@ -327,9 +327,18 @@ struct MergeRun {
         } else if (own) {
             own->join = true;
         }
+        // a lone sketch's large batches of uint32 keys: tiles of kPartOpsWide
+        // ops (the staged keys of one still fit the LDS), so that every bucket's
+        // run is longer; smaller batches keep more, smaller tiles
+        constexpr bool kWideOk = !G && KB == 4;
+        const bool wide = kWideOk && cnt >= kWideBatch;
+        if (wide) part_groups = blocks_for(cnt, kPartOpsWide);
         {
             Timed tm(prof, ps, SF_K_PARTITION, cnt);
-            k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, nb_log2);
+            if (wide)
+                k_part_count<KB, G, P, kPartOpsWide><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, nb_log2);
+            else
+                k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, nb_log2);
             // one lane per bucket pays off for 512..1024 rows; fewer rows (small
             // batches) or more (sketch tables) spread better over segments
             if (part_groups >= kScanWaves * kScanRowsReg / 2 && part_groups <= kScanWaves * kScanRowsReg)
@@ -339,7 +348,15 @@ struct MergeRun {
                 k_part_colscan_tall<uint32_t><<<blocks_for(2 * nb, kScanBuckets), kScanBuckets * kScanSegs, 0, ps>>>(
                     hist, part_groups, 2 * nb, meta);
             k_part_start<KB, G><<<1, 2 * nb / kStartPer, 0, ps>>>(meta, chunks);
-            k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, meta, part, nb_log2);
+            bool done = false;
+            if constexpr (kWideOk) {
+                if (wide) {
+                    k_part_scatter<KB, G, P, kPartOpsWide><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, meta,
+                                                                                               part, nb_log2);
+                    done = true;
+                }
+            }
+            if (!done) k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, meta, part, nb_log2);
         }
         {
             Timed tm(prof, ps, SF_K_MERGE, cnt);

@@ -344,6 +344,8 @@ namespace sfk {
 
 constexpr uint32_t kMaxBuckets = 1024;         // per op type; the runtime nb is a power of two <= this
 constexpr uint32_t kPartOps = 8192;            // ops per partitioning workgroup
+constexpr uint32_t kPartOpsWide = 16384;       // ... for a lone sketch's large batches of uint32 keys
+constexpr uint32_t kWideBatch = 1u << 22;      // (batches of at least this many ops)
 constexpr uint32_t kPartThreads = 1024;        // its threads (16 waves)
 // Partitioning groups one batch (or merged sub-round) of cap ops may use:
 // full tiles plus one partial tile per sketch, at most extra sketches.
@@ -569,12 +571,12 @@ __device__ __forceinline__ uint32_t xcd_row(uint32_t b, uint32_t n) {
 }
 
 // Counts the ops of every bucket in each group's tile.
-template <int KB, bool G, class P>
+template <int KB, bool G, class P, uint32_t OPS = kPartOps>
 __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* __restrict__ hist_out,
                                                          uint32_t nb_log2) {
     __shared__ uint32_t hist[2 * kMaxBuckets];
     const uint32_t nbt = 2u << nb_log2;
-    const Work w = plan.at(blockIdx.x, kPartOps);
+    const Work w = plan.at(blockIdx.x, OPS);
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < w.count; t += kPartThreads) {
@@ -818,19 +820,19 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
 // uint32 keys are first sorted by bucket inside the group (LDS), so that the
 // group writes each bucket's keys as one contiguous run; wider keys go
 // straight to their slots.
-template <int KB, bool G, class P>
+template <int KB, bool G, class P, uint32_t OPS = kPartOps>
 __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uint32_t* __restrict__ offs,
                                                          const MergeMeta* __restrict__ meta,
                                                          MKey<KB, G>* __restrict__ part, uint32_t nb_log2) {
-    constexpr uint32_t R = kPartOps / kPartThreads;  // keys per thread
+    constexpr uint32_t R = OPS / kPartThreads;  // keys per thread
     constexpr bool kStage = sizeof(MKey<KB, G>) <= 8;
     __shared__ uint32_t hist[2 * kMaxBuckets];       // local counts, then the group's first global slot
     __shared__ uint32_t lstart[2 * kMaxBuckets];     // exclusive prefix of the local counts
     __shared__ uint32_t tmp[16];
-    __shared__ MKey<KB, G> stage[kStage ? kPartOps : 1];
-    __shared__ uint16_t sbk[kStage ? kPartOps : 1];
+    __shared__ MKey<KB, G> stage[kStage ? OPS : 1];
+    __shared__ uint16_t sbk[kStage ? OPS : 1];
     const uint32_t nbt = 2u << nb_log2;
-    const Work w = plan.at(blockIdx.x, kPartOps);
+    const Work w = plan.at(blockIdx.x, OPS);
     MKey<KB, G> k[R];
     uint32_t bk[R], rank[R];
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;

@@ -1,4 +1,5 @@
-"""Autotuner for the schedule batch size b of one sketch shape.
+"""Autotuner for the schedule batch size b of one sketch shape, and for the
+launch shape of a sketch group.
 
 The batch schedule trades accuracy for throughput: a larger b runs fewer,
 larger batches (fewer launches, more duplicate keys merged) but lets more
@@ -15,6 +16,11 @@ takes the smallest candidate (w/16) as the stand-in for sequential SF_F
 (b = 1 is far too slow to run), and picks the fastest b whose ARE stays within
 ``rel * ARE_ref + abs_`` (default 1.10x + 1e-3).  Results are cached per
 shape and stream class.
+
+A sketch group's merge path and launch-round size (how many ops one
+partition / merge / S1..S5 pass covers) change its speed, never its state:
+tune_group times whole update calls of the group's streams for every
+candidate and keeps the fastest.
 """
 from __future__ import annotations
 
@@ -23,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Sketch
+from . import Sketch, SketchGroup
 
 SLIM_MAX = 65535
 BATCH_CAP = 1 << 23
@@ -153,3 +159,46 @@ class Autotuner:
         if k not in self.cache:
             self.cache[k] = tune_batch(d, w, z, keys, ops, queries, key_bytes=key_bytes, **self.kw)
         return self.cache[k]
+
+
+@dataclass
+class GroupShape:
+    mode: int                                   # sf_group_set_merge mode of the pick
+    round_ops: int                              # ops per launch round of the pick
+    ms: float                                   # its fastest update call
+    table: list = field(default_factory=list)   # (mode, round_ops, ms, sub-rounds) per candidate
+
+
+def group_round_candidates(cfgs, caps=(1 << 22, 1 << 23, 1 << 24)) -> list[int]:
+    """Round sizes to try: each cap that holds the largest batch of any sketch (a batch is
+    never split over rounds), at least one."""
+    max_b = max(int(c.batch_ops) for c in cfgs)
+    out = sorted({max(c, max_b) for c in caps})
+    return out
+
+
+def tune_group(cfgs, keys, ops, seg, modes=(1, 2), round_ops=None, reps=2) -> GroupShape:
+    """Pick the merge path (among `modes`) and the launch-round size of a group of sketches
+    `cfgs` fed the device streams (keys, ops) cut by the host offsets seg, by timing one
+    update call per repetition (after one untimed call that also records the graph)."""
+    import torch
+    rows = []
+    for r in round_ops or group_round_candidates(cfgs):
+        for mode in modes:
+            G = SketchGroup(cfgs, round_ops=r)
+            G.set_merge(mode)
+            best = float("inf")
+            for i in range(reps + 1):
+                G.reset()
+                G.sync()
+                t0 = time.perf_counter()
+                G.update(keys, ops, seg)
+                G.sync()
+                if i:
+                    best = min(best, (time.perf_counter() - t0) * 1e3)
+            rows.append([G.merge_path(), int(r), best, G.rounds()[0]])
+            G.close()
+            del G
+            torch.cuda.empty_cache()
+    pick = min(rows, key=lambda x: x[2])
+    return GroupShape(pick[0], pick[1], pick[2], rows)

@@ -170,11 +170,11 @@ def test_group_mixed_rows_and_flow_keys():
 
 @pytest.mark.parametrize("graph", [True, False])
 def test_group_owner_ranges_split_subrounds(graph):
-    """Wide sketches (32 ranges of 2048 cells per row each): a sub-round holds at most 1024
+    """Wide sketches (64 ranges of 2048 cells per row each): a sub-round holds at most 1024
     ranges per row, so rounds split by ranges as well as by ops; the owner path still gives
     every sketch the oracle's state.  Two update calls, the second with other segments."""
     import torch
-    m = sfgen.config_multi(seed=5, n_sketches=40, length_scale=0.02, fat_log2=(18, 18))
+    m = sfgen.config_multi(seed=5, n_sketches=40, length_scale=0.02, fat_log2=(19, 19))
     cfgs = _cfgs(m.w, np.full(m.n, 4), np.full(m.n, 1 << 14))
     say(f"[case] group owner range cap n={m.n} ops={m.keys.size} graph={graph}")
     G = sf.SketchGroup(cfgs)
@@ -191,7 +191,7 @@ def test_group_owner_ranges_split_subrounds(graph):
     G.update(dev_keys(m.keys[idx1]), torch.from_numpy(m.ops[idx1]).cuda(), seg1)
     sub, tiles = G.rounds()
     say(f"  first call: sub-rounds {sub}, tiles {tiles}")
-    assert sub > int(np.ceil(n1 / (1 << 14)).max())     # 40 x 32 ranges > 1024 per sub-round
+    assert sub > int(np.ceil(n1 / (1 << 14)).max())     # 40 x 64 ranges > 1024 per sub-round
     G.update(dev_keys(m.keys[idx2]), torch.from_numpy(m.ops[idx2]).cuda(), seg2)
     refs = []
     for i, c in enumerate(cfgs):
