@@ -333,7 +333,7 @@ def run_multi(args, torch, np, sf, sfgen):
             batch_of_w[w] = r.b
             tuned[str(w)] = {"b": r.b, "rule_b": batch_for_width(w), "ref_b": r.ref_b,
                              "ref_are": round(r.ref_are, 5), "bound": round(r.bound, 5),
-                             "candidates": [[b, round(a, 5), round(ms, 2), ok] for b, a, ms, ok, _ in r.table]}
+                             "candidates": [[b, round(a, 5), round(ms, 2), ok] for b, a, ms, ok, _, _ in r.table]}
         log(f"[bench] autotuned batch per width in {time.time() - t_tune:.1f}s: "
             f"{ {w: v['b'] for w, v in tuned.items()} } (rule min(16 w, 2^23): "
             f"{ {w: v['rule_b'] for w, v in tuned.items()} })")
@@ -673,6 +673,11 @@ def gpu_leg(args, torch, np, sf, wl, b: int, leg: str, steps: int, warmup: int) 
     sk.set_tile(args.tile)
     sk.set_merge({"batch": 1, "atomic": 2, "owner": 3, "tile": 0}[args.merge])
     sk.set_streams({"auto": -1, "one": 0, "two": 1}[args.streams])
+    if args.owner_range and sk.owner_range():
+        try:
+            sk.set_owner_range(args.owner_range)
+        except sf.SFError as e:
+            log(f"[bench] {leg}: owner range 2^{args.owner_range} not allowed for this shape ({e}); default kept")
 
     def step():
         sk.reset()
@@ -835,6 +840,8 @@ def main():
                          "tile: per-tile merging")
     ap.add_argument("--group-round-ops", type=int, default=0,
                     help="ops per launch round of the 1024-sketch group (0: the library's default)")
+    ap.add_argument("--owner-range", type=int, default=0,
+                    help="owner path: ranges of 2^N cells (sf_set_owner_range; 0: the library's default)")
     ap.add_argument("--streams", choices=("auto", "one", "two"), default="auto",
                     help="owner path: partition of the next batch on a second stream (sf_set_streams)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -947,7 +954,7 @@ def main():
                                  "frac": round(step_bytes / (g["ms_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "bytes_per_step": step_bytes, "merged_entries_per_step": g["entries_per_step"]},
                "kernels": g["kernels"], "profiled_ms_per_step": round(g["prof_ms"], 3),
-               "merge_path": MERGE_PATHS[g["sk"].merge_path()]}
+               "merge_path": MERGE_PATHS[g["sk"].merge_path()], "owner_range_shift": g["sk"].owner_range()}
         log(f"[bench] {leg}: roofline {json.dumps(roof)}")
         if leg == "main":
             result = {
@@ -958,6 +965,7 @@ def main():
                 "step_roofline": rec["step_roofline"], "kernels": g["kernels"],
                 "kernels_note": "HIP-event durations from the same steps run once more with events on",
                 "profiled_ms_per_step": rec["profiled_ms_per_step"], "merge_path": rec["merge_path"],
+                "owner_range_shift": rec["owner_range_shift"],
                 "phases_ms_per_step": {
                     "update": round(sum(v["ms_total"] for k, v in g["kernels"].items()
                                         if k not in ("query", "export")) / args.steps, 3),
@@ -987,15 +995,16 @@ def main():
                 t_tune = time.time()
                 # the bound from the oracle's sequential ARE when the CPU leg has run
                 seq_are = result.get("accuracy", {}).get("seq", {}).get("are")
-                r = tune_batch(wl.d, wl.w, wl.z, wl.keys, wl.ops, wl.queries, modes=(2, 3), ref_are=seq_are)
+                r = tune_batch(wl.d, wl.w, wl.z, wl.keys, wl.ops, wl.queries, modes=(2, 3), ref_are=seq_are,
+                               shifts=None)
                 result["autotune_check"] = {
-                    "b": r.b, "merge_path": MERGE_PATHS[r.mode], "rule_b": b,
+                    "b": r.b, "merge_path": MERGE_PATHS[r.mode], "owner_range_shift": r.shift, "rule_b": b,
                     "ref": "oracle sequential SF_F" if seq_are is not None else f"GPU at b = {r.ref_b}",
                     "ref_are": round(r.ref_are, 5), "bound": round(r.bound, 5),
-                    "candidates": [[bb, round(a, 5), round(ms, 2), ok, MERGE_PATHS[m]]
-                                   for bb, a, ms, ok, m in r.table]}
+                    "candidates": [[bb, round(a, 5), round(ms, 2), ok, MERGE_PATHS[m], sh]
+                                   for bb, a, ms, ok, m, sh in r.table]}
                 log(f"[bench] autotuner on this workload ({time.time() - t_tune:.1f}s): b = {r.b}, "
-                    f"path {result['autotune_check']['merge_path']} (rule {b})")
+                    f"path {result['autotune_check']['merge_path']}, range shift {r.shift} (rule {b})")
         else:
             leg_out[leg] = rec
             if not args.no_cpu_baseline:

@@ -229,6 +229,17 @@ int sf_set_merge(sf_sketch *sk, int batch_wide);
  * or 3 reads 2 when the shape does not fit the owner path. */
 int sf_merge_path(sf_sketch *sk);
 
+/* Range size of the owner path: ranges of 2^shift cells per row.  shift 0
+ * restores the default (at least 256 cells, more where a row would otherwise
+ * have over min(1024, 8192 / d) ranges).  Allowed shifts run from that
+ * smallest one (at least 4) to the largest whose range holds at most 8192
+ * Fat counters and 2^16 (cell, slot) codes; SF_EINVAL outside them or when
+ * the shape has no owner path.  Takes effect at the next update call; the
+ * results do not depend on it. */
+int sf_set_owner_range(sf_sketch *sk, uint32_t shift);
+/* The current range shift of the owner path; 0 when the shape has none. */
+int sf_owner_range(sf_sketch *sk);
+
 /* Streams of the owner path.  With 1 the partition, merge and pair kernels of
  * batch k + 1 run on a second stream of the sketch's (created with the owner
  * buffers, default priority) while the owner steps of batch k run on its own

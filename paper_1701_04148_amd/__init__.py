@@ -68,6 +68,8 @@ SIGNATURES = {
     "sf_set_merge": (_I, [_P, _I]),
     "sf_merge_path": (_I, [_P]),
     "sf_set_streams": (_I, [_P, _I]),
+    "sf_set_owner_range": (_I, [_P, ctypes.c_uint32]),
+    "sf_owner_range": (_I, [_P]),
     "sf_update_host": (_I, [_P, _P, _P, _U64, _U64]),
     "sf_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_profile": (_I, [_P, _I]),
@@ -374,6 +376,17 @@ class Sketch:
         across the batch with atomic S1..S5 (2), or with owner-computes for every batch (3)."""
         mode = int(batch_wide) if not isinstance(batch_wide, bool) else int(batch_wide)
         _check(lib().sf_set_merge(self._h, mode), "sf_set_merge")
+
+    def set_owner_range(self, shift: int):
+        """Owner path: ranges of 2^shift cells per row (0: the default size)."""
+        _check(lib().sf_set_owner_range(self._h, int(shift)), "sf_set_owner_range")
+
+    def owner_range(self) -> int:
+        """The owner path's range shift (0 when the shape has no owner path)."""
+        rc = lib().sf_owner_range(self._h)
+        if rc < 0:
+            _check(rc, "sf_owner_range")
+        return rc
 
     def set_streams(self, mode: int):
         """Owner path: partition side of the next batch on a second stream (1), one stream (0),

@@ -201,18 +201,38 @@ void launch_steps(const P& plan, unsigned tiles, bool ins, bool del, uint32_t* b
     }
 }
 
-// Layout of the owner-computes path for a sketch shape: ranges of 2^cr_shift
-// cells (at least 16) so that a row has at most kMaxRanges of them and the
-// columns of both op types fit kMaxCols; the shape qualifies when a range's
-// Fat counters fit the owners' LDS and a pair's 16-bit local code.
-inline bool owner_geom(const sf_config* c, OwnerGeom* og) {
+// Range sizes of the owner-computes path for a sketch shape: 2^shift cells,
+// from the smallest shift (at least 4) that keeps a row at most kMaxRanges
+// ranges and the columns of both op types within kMaxCols, up to the largest
+// whose Fat counters fit the owners' LDS and a pair's 16-bit local code.  The
+// shape qualifies when the smallest is within that limit.
+inline bool owner_shifts(const sf_config* c, uint32_t* lo, uint32_t* hi) {
     const uint32_t rmax = std::min<uint32_t>(kMaxRanges, kMaxCols / (2 * c->d));
     uint32_t zbits = 0;
     while ((1ull << zbits) < c->z) zbits++;
     uint32_t sh = 4;
     while (((uint64_t(c->w) + (1ull << sh) - 1) >> sh) > rmax) sh++;
+    auto fits = [&](uint32_t x) { return (1ull << x) * c->z <= kOwnCounters && ((1ull << x) << zbits) <= 65536; };
+    if (!fits(sh)) return false;
+    *lo = sh;
+    while (fits(sh + 1) && (1ull << sh) < c->w) sh++;
+    *hi = sh;
+    return true;
+}
+
+// Default range size: at least 256 cells (fewer, busier owner workgroups and
+// a shorter column scan for narrow sketches), more where the row needs it.
+constexpr uint32_t kDefaultRangeShift = 8;
+
+// The owner layout with ranges of 2^shift cells (0: the default size).
+inline bool owner_geom(const sf_config* c, OwnerGeom* og, uint32_t shift = 0) {
+    uint32_t lo, hi;
+    if (!owner_shifts(c, &lo, &hi)) return false;
+    const uint32_t sh = shift ? shift : std::min(hi, std::max(lo, kDefaultRangeShift));
+    if (sh < lo || sh > hi) return false;
+    uint32_t zbits = 0;
+    while ((1ull << zbits) < c->z) zbits++;
     const uint64_t cr = 1ull << sh;
-    if (cr * c->z > kOwnCounters || (cr << zbits) > 65536) return false;
     og->R = uint32_t((uint64_t(c->w) + cr - 1) >> sh);
     og->cr_shift = sh;
     og->zbits = zbits;

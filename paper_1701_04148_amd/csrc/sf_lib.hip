@@ -122,7 +122,8 @@ Sizes sizes_of(const sf_config* c) {
     s.hist = round256(part_groups_max(c->batch_ops, 1) * 2 * kMaxBuckets * 4);
     s.chunks = round256(merge_chunks_max(c->batch_ops) * sizeof(MergeChunk));
     OwnerGeom og;
-    if (owner_geom(c, &og)) {
+    uint32_t lo, hi;
+    if (owner_shifts(c, &lo, &hi) && owner_geom(c, &og, lo)) {  // column counts for the most ranges
         const uint64_t b = c->batch_ops, d = c->d;
         s.pairs = 2 * round256(d * b * 8);
         s.pos = round256(d * b * 4);
@@ -782,6 +783,25 @@ int sf_set_merge(sf_sketch* s, int batch_wide) {
     if ((batch_wide == 1 || batch_wide == 3) && s->owner_ok)
         return s->own_base ? (s->owner_on = true, SF_OK) : owner_alloc(s);
     return owner_free(s);
+}
+
+int sf_set_owner_range(sf_sketch* s, uint32_t shift) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    if (!s->owner_ok) return fail(SF_EINVAL, "this sketch shape has no owner-computes path");
+    OwnerGeom og;
+    if (!owner_geom(&s->cfg, &og, shift)) {
+        uint32_t lo = 0, hi = 0;
+        owner_shifts(&s->cfg, &lo, &hi);
+        return fail(SF_EINVAL, "range shift must be 0 or within [" + std::to_string(lo) + ", " +
+                                   std::to_string(hi) + "] for this shape");
+    }
+    s->own.og = og;  // launches already queued keep the layout they were given
+    return SF_OK;
+}
+
+int sf_owner_range(sf_sketch* s) {
+    if (!live(s)) return fail(SF_ESTATE, "sketch handle is not live");
+    return s->owner_ok ? int(s->own.og.cr_shift) : 0;
 }
 
 int sf_set_streams(sf_sketch* s, int mode) {

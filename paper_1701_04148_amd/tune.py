@@ -76,8 +76,9 @@ class TuneResult:
     ref_b: int
     ref_are: float
     bound: float
-    table: list = field(default_factory=list)   # (b, are, ms, feasible, merge mode) per candidate
+    table: list = field(default_factory=list)   # (b, are, ms, feasible, merge mode, range shift) per candidate
     mode: int = 1                                # merge mode (sf_set_merge) of the pick
+    shift: int = 0                               # owner range shift (sf_set_owner_range) of the pick, 0: none
 
 
 def candidates_for(w: int, n_ops: int, cap: int = 1 << 23) -> list[int]:
@@ -95,12 +96,13 @@ def candidates_for(w: int, n_ops: int, cap: int = 1 << 23) -> list[int]:
 
 def tune_batch(d: int, w: int, z: int, keys: np.ndarray, ops: np.ndarray | None, queries: np.ndarray,
                key_bytes: int = 4, candidates=None, rel: float = 1.10, abs_: float = 1e-3,
-               reps: int = 2, modes=(1,), ref_are: float | None = None) -> TuneResult:
-    """Pick b (and, among `modes`, the sf_set_merge path) for sketches of shape
-    (d, w, z) fed streams like (keys, ops).  Every mode gives the same answers, so the
-    accuracy depends on b alone; each candidate keeps its fastest mode.  ref_are: the
-    sequential ARE of the sample when the caller has it (the bound is then taken from
-    it instead of the smallest candidate's)."""
+               reps: int = 2, modes=(1,), ref_are: float | None = None, shifts=(0,)) -> TuneResult:
+    """Pick b (and, among `modes`, the sf_set_merge path, and among `shifts`, the owner
+    path's range size: 0 the default, or every allowed one with None) for sketches of
+    shape (d, w, z) fed streams like (keys, ops).  Every mode and range size gives the
+    same answers, so the accuracy depends on b alone; each candidate keeps its fastest
+    launch shape.  ref_are: the sequential ARE of the sample when the caller has it (the
+    bound is then taken from it instead of the smallest candidate's)."""
     import torch
     cands = sorted(candidates or candidates_for(w, keys.shape[0]))
     f = exact_counts(keys, ops, queries)
@@ -116,25 +118,31 @@ def tune_batch(d: int, w: int, z: int, keys: np.ndarray, ops: np.ndarray | None,
     rows = []
     for b in cands:
         sk = Sketch(d, w, z, key_bytes=key_bytes, batch_ops=b)
-        best, best_mode, ans = float("inf"), modes[0], None
+        best, best_mode, best_shift, ans = float("inf"), modes[0], 0, None
         for mode in modes:
             sk.set_merge(mode)
-            for _ in range(reps):
-                sk.reset()
-                sk.sync()
-                t0 = time.perf_counter()
-                if dops is None:
-                    sk.insert(dk)
-                else:
-                    sk.update(dk, dops)
-                sk.query(dq, out)
-                sk.sync()
-                ms = (time.perf_counter() - t0) * 1e3
-                if ms < best:
-                    best, best_mode = ms, sk.merge_path()
-            if ans is None:
-                ans = out.cpu().numpy().view(np.uint32)
-        rows.append([b, are(ans, f), best, None, best_mode])
+            owner = sk.merge_path() in (1, 3)
+            for shift in (owner_shifts(sk) if shifts is None else shifts) if owner else (0,):
+                if owner:
+                    sk.set_owner_range(shift)
+                for _ in range(reps):
+                    sk.reset()
+                    sk.sync()
+                    t0 = time.perf_counter()
+                    if dops is None:
+                        sk.insert(dk)
+                    else:
+                        sk.update(dk, dops)
+                    sk.query(dq, out)
+                    sk.sync()
+                    ms = (time.perf_counter() - t0) * 1e3
+                    if ms < best:
+                        best, best_mode, best_shift = ms, sk.merge_path(), sk.owner_range() if owner else 0
+                if ans is None:
+                    ans = out.cpu().numpy().view(np.uint32)
+            if owner:
+                sk.set_owner_range(0)
+        rows.append([b, are(ans, f), best, None, best_mode, best_shift])
         sk.close()
     ref_b = rows[0][0]
     if ref_are is None:
@@ -144,7 +152,21 @@ def tune_batch(d: int, w: int, z: int, keys: np.ndarray, ops: np.ndarray | None,
         r[3] = r[1] <= bound
     feasible = [r for r in rows if r[3]]
     best_row = min(feasible, key=lambda r: r[2]) if feasible else rows[0]
-    return TuneResult(best_row[0], ref_b, ref_are, bound, rows, best_row[4])
+    return TuneResult(best_row[0], ref_b, ref_are, bound, rows, best_row[4], best_row[5])
+
+
+def owner_shifts(sk) -> list[int]:
+    """Every range shift sf_set_owner_range accepts for this sketch's shape."""
+    from . import SFError
+    out = []
+    for shift in range(4, 24):
+        try:
+            sk.set_owner_range(shift)
+        except SFError:
+            continue
+        out.append(shift)
+    sk.set_owner_range(0)
+    return out
 
 
 class Autotuner:

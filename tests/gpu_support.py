@@ -34,14 +34,19 @@ def owner_shape(d, w, z) -> bool:
     return (1 << sh) * z <= 8192 and (1 << sh) << zbits <= 65536
 
 
-def gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base=1, calls=1, merge=1, tile=2048, streams=-1):
+def gpu_run(d, w, z, kb, keys, ops, queries, b, seed_base=1, calls=1, merge=1, tile=2048, streams=-1,
+            shift=0):
     """Updates (split into `calls` consecutive calls) then queries, on the GPU.
-    streams: sf_set_streams mode of the owner path.  Returns (fat, slim, answers)."""
+    streams: sf_set_streams mode of the owner path; shift: its range size (sf_set_owner_range,
+    0 the default).  Returns (fat, slim, answers)."""
     import torch
     sk = sf.Sketch(d, w, z, key_bytes=kb, seed_base=seed_base, batch_ops=b)
     sk.set_merge(int(merge))
     sk.set_tile(tile)
     sk.set_streams(streams)
+    if shift:
+        sk.set_owner_range(shift)
+        assert sk.owner_range() == shift
     path = sk.merge_path()
     want = int(merge) if int(merge) not in (1, 3) or owner_shape(d, w, z) else 2
     assert path == want, (merge, path, want)

@@ -139,6 +139,36 @@ def test_owner_two_streams(d, w, z, kb, b, calls, merge):
     check(d, w, z, kb, keys, ops, uni, b, calls=calls, tag="two streams", merge=merge, streams=1)
 
 
+@pytest.mark.parametrize("d,w,z,kb", [(4, 1 << 14, 4, 4), (3, 1000, 3, 13), (8, 4096, 2, 4)])
+def test_owner_range_sizes(d, w, z, kb):
+    """Every range size the owner path accepts for the shape (from 16 cells, or the smallest
+    that keeps a row within its range limit, up to 8192 Fat counters per range) gives the
+    oracle's state; ranges larger than the row (one ragged range) included."""
+    import torch
+    rng = np.random.default_rng(d * 5 + w)
+    keys, ops, uni = random_turnstile(rng, 60_000, 6000, 0.2, key_bytes=kb)
+    b = 1 << 14
+    o = oracle_run(d, w, z, kb, keys, ops, uni, b, 1, 2)
+    sk = sf.Sketch(d, w, z, key_bytes=kb, batch_ops=b)
+    from paper_1701_04148_amd.tune import owner_shifts
+    shifts = owner_shifts(sk)
+    default = sk.owner_range()
+    say(f"[case] owner range sizes d={d} w={w} z={z} kb={kb}: shifts {shifts}, default {default}")
+    assert shifts == list(range(shifts[0], shifts[-1] + 1))
+    assert shifts[0] <= default <= shifts[-1]
+    assert (1 << shifts[-1]) * z <= 8192
+    with pytest.raises(sf.SFError):
+        sk.set_owner_range(shifts[-1] + 1)
+    with pytest.raises(sf.SFError):
+        sk.set_owner_range(shifts[0] - 1)
+    sk.close()
+    for shift in shifts:
+        g = gpu_run(d, w, z, kb, keys, ops, uni, b, 1, 2, merge=3, shift=shift)
+        assert_same(g[0], o[0], f"fat shift={shift}")
+        assert_same(g[1], o[1], f"slim shift={shift}")
+        assert_same(g[2], o[2], f"query shift={shift}")
+
+
 def test_owner_two_streams_uniform_ops():
     """Insert-only then delete-only calls (no k_level in a delete batch) on two streams."""
     import torch
