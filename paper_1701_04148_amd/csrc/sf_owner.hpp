@@ -352,7 +352,10 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(SR sr, RM rm, OwnerGeo
                                                           const uint64_t* __restrict__ pairs_i,
                                                           uint64_t* __restrict__ res) {
     extern __shared__ uint32_t L[];  // ncells records of rs words
-    constexpr uint32_t K = 8;        // insert pairs per thread kept in registers; more go through res
+    constexpr uint32_t T = kOwnThreads;
+    constexpr uint32_t K = 4;   // this batch's insert pairs per thread held in registers (more: through res)
+    constexpr uint32_t KF = 4;  // the previous batch's insert pairs per thread held in registers (more: a loop)
+    constexpr uint32_t KD = 2;  // ... and its delete pairs
     const uint32_t d = og.d;
     uint32_t row, q;
     owner_of(og, d, row, q);
@@ -369,6 +372,33 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(SR sr, RM rm, OwnerGeo
     const uint32_t ncells = min(1u << og.cr_shift, sd.g.w - cell0);
     const uint32_t nw = ncells * rs;
     uint32_t* rec0 = sd.fat + (size_t(row) * sd.g.w + cell0) * rs;
+    auto cell_of = [&](uint64_t pr) { return ((uint32_t(pr >> 32) & 0xffffu) >> og.zbits) * rs; };
+    auto slot_of = [&](uint64_t pr) { return uint32_t(pr >> 32) & zmask; };
+    // The pairs (and the T of the previous batch's inserts) do not depend on
+    // the records: their loads go out first, so that they overlap the staging
+    // of the range instead of following it.
+    uint64_t qf[KF], qd[KD], qi[K];
+#pragma unroll
+    for (uint32_t k = 0; k < KF; k++) {
+        const uint32_t p = fi0 + k * T + threadIdx.x;
+        qf[k] = p < fi1 ? pairs_f[p] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < KD; k++) {
+        const uint32_t p = fd0 + k * T + threadIdx.x;
+        qd[k] = p < fd1 ? pairs_f[p] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < K; k++) {
+        const uint32_t p = i0 + k * T + threadIdx.x;
+        qi[k] = p < i1 ? pairs_i[p] : 0ull;
+    }
+    uint32_t lv[KF];
+#pragma unroll
+    for (uint32_t k = 0; k < KF; k++) {
+        const uint32_t p = fi0 + k * T + threadIdx.x;
+        lv[k] = p < fi1 ? uint32_t(level[uint32_t(qf[k])]) : 0u;
+    }
     // the range in 16-byte pieces where it is 16-byte aligned, several loads in
     // flight per thread
     const bool vec = (reinterpret_cast<uintptr_t>(rec0) & 15u) == 0;
@@ -383,62 +413,71 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(SR sr, RM rm, OwnerGeo
     }
     __syncthreads();
     if (fi0 != fi1 || fd0 != fd1) {
-        for (uint32_t p = fi0 + threadIdx.x; p < fi1; p += kOwnThreads) {
-            const uint64_t q = pairs_f[p];
-            const uint32_t code = uint32_t(q >> 32) & 0xffffu;
-            atomicMax(&L[(code >> og.zbits) * rs + z], uint32_t(level[uint32_t(q)]));
+#pragma unroll
+        for (uint32_t k = 0; k < KF; k++)
+            if (fi0 + k * T + threadIdx.x < fi1) atomicMax(&L[cell_of(qf[k]) + z], lv[k]);
+        for (uint32_t p = fi0 + KF * T + threadIdx.x; p < fi1; p += T) {
+            const uint64_t pr = pairs_f[p];
+            atomicMax(&L[cell_of(pr) + z], uint32_t(level[uint32_t(pr)]));
         }
-        for (uint32_t p = fd0 + threadIdx.x; p < fd1; p += kOwnThreads) {
-            const uint32_t hi = uint32_t(pairs_f[p] >> 32), code = hi & 0xffffu;
-            atomicSub(&L[(code >> og.zbits) * rs + (code & zmask)], hi >> 16);
+#pragma unroll
+        for (uint32_t k = 0; k < KD; k++)
+            if (fd0 + k * T + threadIdx.x < fd1) atomicSub(&L[cell_of(qd[k]) + slot_of(qd[k])], uint32_t(qd[k] >> 48));
+        for (uint32_t p = fd0 + KD * T + threadIdx.x; p < fd1; p += T) {
+            const uint64_t pr = pairs_f[p];
+            atomicSub(&L[cell_of(pr) + slot_of(pr)], uint32_t(pr >> 48));
         }
         __syncthreads();
-        for (uint32_t p = fd0 + threadIdx.x; p < fd1; p += kOwnThreads) {
-            const uint32_t* r = L + ((uint32_t(pairs_f[p] >> 32) & 0xffffu) >> og.zbits) * rs;
+        auto clamp = [&](uint64_t pr) {
+            uint32_t* r = L + cell_of(pr);
             uint32_t m = 0;
             for (uint32_t f = 0; f < z; f++) m = max(m, r[f]);
-            atomicMin(const_cast<uint32_t*>(r) + z, m);
-        }
+            atomicMin(r + z, m);
+        };
+#pragma unroll
+        for (uint32_t k = 0; k < KD; k++)
+            if (fd0 + k * T + threadIdx.x < fd1) clamp(qd[k]);
+        for (uint32_t p = fd0 + KD * T + threadIdx.x; p < fd1; p += T) clamp(pairs_f[p]);
         __syncthreads();
     }
     if (i0 != i1) {
-        uint64_t q[K];
         uint32_t pre[K], a[K];
 #pragma unroll
         for (uint32_t k = 0; k < K; k++) {
-            const uint32_t p = i0 + k * kOwnThreads + threadIdx.x;
-            q[k] = p < i1 ? pairs_i[p] : 0ull;
-            const uint32_t code = uint32_t(q[k] >> 32) & 0xffffu;
-            const uint32_t* r = L + (code >> og.zbits) * rs;
-            pre[k] = p < i1 ? r[code & zmask] : 0u;
-            a[k] = p < i1 ? r[z] : 0u;
+            const bool in = i0 + k * T + threadIdx.x < i1;
+            const uint32_t* r = L + cell_of(qi[k]);
+            pre[k] = in ? r[slot_of(qi[k])] : 0u;
+            a[k] = in ? r[z] : 0u;
         }
         // pairs beyond the registers keep (A, Bpre) in their own res word meanwhile
-        for (uint32_t p = i0 + K * kOwnThreads + threadIdx.x; p < i1; p += kOwnThreads) {
-            const uint32_t code = uint32_t(pairs_i[p] >> 32) & 0xffffu;
-            const uint32_t* r = L + (code >> og.zbits) * rs;
-            res[p] = uint64_t(r[z]) | (uint64_t(r[code & zmask]) << 32);
+        for (uint32_t p = i0 + K * T + threadIdx.x; p < i1; p += T) {
+            const uint64_t pr = pairs_i[p];
+            const uint32_t* r = L + cell_of(pr);
+            res[p] = uint64_t(r[z]) | (uint64_t(r[slot_of(pr)]) << 32);
         }
         __syncthreads();  // every snapshot taken before a counter moves
-        for (uint32_t p = i0 + threadIdx.x; p < i1; p += kOwnThreads) {
-            const uint32_t hi = uint32_t(pairs_i[p] >> 32), code = hi & 0xffffu;
-            atomicAdd(&L[(code >> og.zbits) * rs + (code & zmask)], hi >> 16);
+#pragma unroll
+        for (uint32_t k = 0; k < K; k++)
+            if (i0 + k * T + threadIdx.x < i1) atomicAdd(&L[cell_of(qi[k]) + slot_of(qi[k])], uint32_t(qi[k] >> 48));
+        for (uint32_t p = i0 + K * T + threadIdx.x; p < i1; p += T) {
+            const uint64_t pr = pairs_i[p];
+            atomicAdd(&L[cell_of(pr) + slot_of(pr)], uint32_t(pr >> 48));
         }
         __syncthreads();
-        auto pack = [&](uint32_t p, uint32_t code, uint32_t av, uint32_t bpre) {
-            const uint32_t post = L[(code >> og.zbits) * rs + (code & zmask)];
+        auto pack = [&](uint32_t p, uint64_t pr, uint32_t av, uint32_t bpre) {
+            const uint32_t post = L[cell_of(pr) + slot_of(pr)];
             const uint32_t grow = post - bpre;  // uint32, modular like the counter
             res[p] = uint64_t(av) | (uint64_t(grow < kSlimMax ? grow : kSlimMax) << 16) |
                      (uint64_t(post < kSlimMax ? post : kSlimMax) << 32);
         };
 #pragma unroll
         for (uint32_t k = 0; k < K; k++) {
-            const uint32_t p = i0 + k * kOwnThreads + threadIdx.x;
-            if (p < i1) pack(p, uint32_t(q[k] >> 32) & 0xffffu, a[k], pre[k]);
+            const uint32_t p = i0 + k * T + threadIdx.x;
+            if (p < i1) pack(p, qi[k], a[k], pre[k]);
         }
-        for (uint32_t p = i0 + K * kOwnThreads + threadIdx.x; p < i1; p += kOwnThreads) {
+        for (uint32_t p = i0 + K * T + threadIdx.x; p < i1; p += T) {
             const uint64_t sv = res[p];
-            pack(p, uint32_t(pairs_i[p] >> 32) & 0xffffu, uint32_t(sv), uint32_t(sv >> 32));
+            pack(p, pairs_i[p], uint32_t(sv), uint32_t(sv >> 32));
         }
         __syncthreads();
     }
