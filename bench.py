@@ -302,6 +302,40 @@ def micro_ceilings(torch, sizes_mib=(1, 16, 64, 256, 4096), n=1 << 26):
     return out
 
 
+def lone_compare(args, torch, np, sf, cfgs, keys, ops, qk, out, m, group_answers):
+    """The plain path: one Sketch per stream, its own launches (the atomic S1..S5 path,
+    one sketch and one batch per launch); its answers must equal the group's."""
+    lone = [sf.Sketch(c.d, c.w, c.z, batch_ops=c.batch_ops) for c in cfgs]
+    for s_ in lone:
+        # the group's kernels, one sketch and one batch per launch (the owner-computes path
+        # would also need its pair buffers per sketch)
+        s_.set_tile(args.tile)
+        s_.set_merge(2 if args.merge != "tile" else 0)
+    seg, qseg = m.seg.astype(np.int64), m.qseg.astype(np.int64)
+
+    def lone_step():
+        for i, s_ in enumerate(lone):
+            s_.reset()
+            s_.update(keys[seg[i]:seg[i + 1]], ops[seg[i]:seg[i + 1]])
+            s_.query(qk[qseg[i]:qseg[i + 1]], out[qseg[i]:qseg[i + 1]])
+
+    lone_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lone_step()
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t0
+    lone_value = (int(m.keys.size) + int(m.queries.size)) / el1 / 1e6
+    same = bool(np.array_equal(out.cpu().numpy().view(np.uint32), group_answers))
+    log(f"[bench] one sketch per launch: {el1 * 1e3:.2f} ms/step, {lone_value:.1f} M items/s; "
+        f"answers identical to the group: {same}")
+    for s_ in lone:
+        s_.close()
+    if not same:
+        raise SystemExit("group answers differ from the one-sketch-per-launch path")
+    return lone_value, el1
+
+
 def run_multi(args, torch, np, sf, sfgen):
     """1024 sketches in one group (graph-captured rounds) vs one sketch per launch."""
     t_gen = time.time()
@@ -317,7 +351,14 @@ def run_multi(args, torch, np, sf, sfgen):
     out = torch.empty(n_q, dtype=torch.int32, device=dev)
     batch_of_w = {int(w): batch_for_width(int(w)) for w in np.unique(m.w)}
     tuned = None
-    if not args.no_autotune:
+    fixed = None
+    if args.multi_shape_in:
+        # a shape an earlier autotuned run wrote (profiling runs replay it without tuning)
+        with open(args.multi_shape_in) as f:
+            fixed = json.load(f)
+        batch_of_w.update({int(w): int(b) for w, b in fixed["batch_of_w"].items()})
+        log(f"[bench] group shape from {args.multi_shape_in}: {fixed}")
+    elif not args.no_autotune:
         # one tuning run per sketch width on that class's longest stream (at most 2M ops)
         from paper_1701_04148_amd.tune import tune_batch
         t_tune = time.time()
@@ -341,7 +382,9 @@ def run_multi(args, torch, np, sf, sfgen):
     group_mode = {"tile": 0, "batch": 1, "owner": 1, "atomic": 2}[args.merge]
     round_ops = args.group_round_ops
     shape = None
-    if not args.no_autotune and args.merge == "batch" and not round_ops:
+    if fixed is not None:
+        group_mode, round_ops = int(fixed["mode"]), int(fixed["round_ops"])
+    elif not args.no_autotune and args.merge == "batch" and not round_ops:
         # the group's merge path and launch-round size, timed on its own streams
         from paper_1701_04148_amd.tune import tune_group
         t_tune = time.time()
@@ -351,6 +394,10 @@ def run_multi(args, torch, np, sf, sfgen):
                  "candidates": [[md, r, round(ms, 2), sub] for md, r, ms, sub in gs.table]}
         log(f"[bench] autotuned group shape in {time.time() - t_tune:.1f}s: path {gs.mode}, round_ops "
             f"{gs.round_ops} (candidates [path, round_ops, ms, launch rounds]: {shape['candidates']})")
+    if args.multi_shape_out:
+        with open(args.multi_shape_out, "w") as f:
+            json.dump({"batch_of_w": {str(w): b for w, b in batch_of_w.items()}, "mode": group_mode,
+                       "round_ops": round_ops}, f)
     G = sf.SketchGroup(cfgs, round_ops=round_ops)
     G.set_tile(args.tile)
     G.set_merge(group_mode)
@@ -400,36 +447,10 @@ def run_multi(args, torch, np, sf, sfgen):
     del G
     torch.cuda.empty_cache()
 
-    # the plain path: one Sketch per stream, its own launches, same kernels
-    lone = [sf.Sketch(c.d, c.w, c.z, batch_ops=c.batch_ops) for c in cfgs]
-    for s_ in lone:
-        # the group's kernels, one sketch and one batch per launch (the owner-computes path
-        # would also need its pair buffers per sketch)
-        s_.set_tile(args.tile)
-        s_.set_merge(2 if args.merge != "tile" else 0)
-    seg, qseg = m.seg.astype(np.int64), m.qseg.astype(np.int64)
-
-    def lone_step():
-        for i, s_ in enumerate(lone):
-            s_.reset()
-            s_.update(keys[seg[i]:seg[i + 1]], ops[seg[i]:seg[i + 1]])
-            s_.query(qk[qseg[i]:qseg[i + 1]], out[qseg[i]:qseg[i + 1]])
-
-    lone_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lone_step()
-    torch.cuda.synchronize()
-    el1 = time.perf_counter() - t0
-    lone_value = (n_ops + n_q) / el1 / 1e6
-    same = bool(np.array_equal(out.cpu().numpy().view(np.uint32), group_answers))
-    log(f"[bench] one sketch per launch: {el1 * 1e3:.2f} ms/step, {lone_value:.1f} M items/s; "
-        f"answers identical to the group: {same}")
-    for s_ in lone:
-        s_.close()
-    if not same:
-        raise SystemExit("group answers differ from the one-sketch-per-launch path")
-
+    if args.no_lone_compare:
+        lone_value, el1 = None, None
+    else:
+        lone_value, el1 = lone_compare(args, torch, np, sf, cfgs, keys, ops, qk, out, m, group_answers)
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mitems/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -445,9 +466,9 @@ def run_multi(args, torch, np, sf, sfgen):
         "merged_entries_per_step": {"insert": entries[0], "delete": entries[1]},
         "autotune": tuned,
         "group_shape": shape,
-        "one_sketch_per_launch": {"value": round(lone_value, 2), "unit": "Mitems/s",
-                                  "ms_per_step": round(el1 * 1e3, 3)},
-        "group_vs_lone": round(value / lone_value, 2),
+        "one_sketch_per_launch": None if lone_value is None else {
+            "value": round(lone_value, 2), "unit": "Mitems/s", "ms_per_step": round(el1 * 1e3, 3)},
+        "group_vs_lone": None if lone_value is None else round(value / lone_value, 2),
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:
@@ -838,6 +859,10 @@ def main():
                     help="batch: batch-wide merge + owner-computes S1..S5 for batches of at least w ops; "
                          "atomic: batch-wide merge + atomic S1..S5; owner: owner-computes for every batch; "
                          "tile: per-tile merging")
+    ap.add_argument("--no-lone-compare", action="store_true",
+                    help="1024-sketch leg: skip the one-sketch-per-launch comparison (profiling runs)")
+    ap.add_argument("--multi-shape-out", default="", help="write the 1024-sketch leg's batch sizes and group shape")
+    ap.add_argument("--multi-shape-in", default="", help="run the 1024-sketch leg with a shape written before")
     ap.add_argument("--group-round-ops", type=int, default=0,
                     help="ops per launch round of the 1024-sketch group (0: the library's default)")
     ap.add_argument("--owner-range", type=int, default=0,
@@ -1032,6 +1057,9 @@ def main():
                                                          "one_sketch_per_launch", "group_vs_lone")}
         if multi.get("autotune"):
             result["sketches_1024"]["autotuned_b"] = {w: v["b"] for w, v in multi["autotune"].items()}
+        if multi.get("group_shape"):
+            result["sketches_1024"]["group_shape"] = multi["group_shape"]
+        result["sketches_1024"]["kernels"] = multi["kernels"]
         if "cpu_baseline" in multi:
             result["sketches_1024"]["cpu_baseline"] = multi["cpu_baseline"]
         torch.cuda.empty_cache()
