@@ -381,26 +381,31 @@ def run_multi(args, torch, np, sf, sfgen):
     cfgs = [sf.make_config(m.d, int(m.w[i]), m.z, 4, 1, batch_of_w[int(m.w[i])]) for i in range(m.n)]
     group_mode = {"tile": 0, "batch": 1, "owner": 1, "atomic": 2}[args.merge]
     round_ops = args.group_round_ops
+    owner_ratio = args.group_owner_ratio
     shape = None
     if fixed is not None:
         group_mode, round_ops = int(fixed["mode"]), int(fixed["round_ops"])
+        owner_ratio = float(fixed.get("owner_ratio", 0.0))
     elif not args.no_autotune and args.merge == "batch" and not round_ops:
         # the group's merge path and launch-round size, timed on its own streams
         from paper_1701_04148_amd.tune import tune_group
         t_tune = time.time()
         gs = tune_group(cfgs, keys, ops, m.seg)
-        group_mode, round_ops = gs.mode, gs.round_ops
-        shape = {"mode": gs.mode, "round_ops": gs.round_ops,
-                 "candidates": [[md, r, round(ms, 2), sub] for md, r, ms, sub in gs.table]}
-        log(f"[bench] autotuned group shape in {time.time() - t_tune:.1f}s: path {gs.mode}, round_ops "
-            f"{gs.round_ops} (candidates [path, round_ops, ms, launch rounds]: {shape['candidates']})")
+        group_mode, round_ops, owner_ratio = gs.mode, gs.round_ops, gs.ratio
+        shape = {"mode": gs.mode, "owner_ratio": gs.ratio, "round_ops": gs.round_ops,
+                 "candidates": [[md, ra, r, round(ms, 2), sub] for md, ra, r, ms, sub in gs.table]}
+        log(f"[bench] autotuned group shape in {time.time() - t_tune:.1f}s: path {gs.mode}, owner ratio "
+            f"{gs.ratio}, round_ops {gs.round_ops} (candidates [path, owner ratio, round_ops, ms, launch "
+            f"rounds]: {shape['candidates']})")
     if args.multi_shape_out:
         with open(args.multi_shape_out, "w") as f:
             json.dump({"batch_of_w": {str(w): b for w, b in batch_of_w.items()}, "mode": group_mode,
-                       "round_ops": round_ops}, f)
+                       "owner_ratio": owner_ratio, "round_ops": round_ops}, f)
     G = sf.SketchGroup(cfgs, round_ops=round_ops)
     G.set_tile(args.tile)
     G.set_merge(group_mode)
+    if G.merge_path() == 1:
+        G.set_owner_ratio(owner_ratio)
     path = G.merge_path()
     log(f"[bench] group merge path {path} (0 per tile, 1 owner-computes, 2 atomics)")
 
@@ -461,7 +466,8 @@ def run_multi(args, torch, np, sf, sfgen):
                                "one graph-captured group update, then query every stream's universe",
                    "sketches": m.n, "ops": n_ops, "queries": n_q,
                    "batch_ops": ("autotuned per width" if tuned else "min(16 w, 2^23) per sketch"),
-                   "tile_ops": args.tile, "merge": args.merge, "merge_path": path, "round_ops": round_ops,
+                   "tile_ops": args.tile, "merge": args.merge, "merge_path": path, "owner_ratio": owner_ratio,
+                   "round_ops": round_ops,
                    "launch_rounds": sub, "scale": args.scale},
         "merged_entries_per_step": {"insert": entries[0], "delete": entries[1]},
         "autotune": tuned,
@@ -863,6 +869,8 @@ def main():
                     help="1024-sketch leg: skip the one-sketch-per-launch comparison (profiling runs)")
     ap.add_argument("--multi-shape-out", default="", help="write the 1024-sketch leg's batch sizes and group shape")
     ap.add_argument("--multi-shape-in", default="", help="run the 1024-sketch leg with a shape written before")
+    ap.add_argument("--group-owner-ratio", type=float, default=0.0,
+                    help="1024-sketch leg without autotuning: sf_group_set_owner_ratio")
     ap.add_argument("--group-round-ops", type=int, default=0,
                     help="ops per launch round of the 1024-sketch group (0: the library's default)")
     ap.add_argument("--owner-range", type=int, default=0,

@@ -334,6 +334,14 @@ int sf_group_set_tile(sf_group *g, uint32_t tile_ops);
  * fails; the group then runs as mode 2).  SF_EINVAL for another mode.  Waits
  * for the stream; the next update call re-plans. */
 int sf_group_set_merge(sf_group *g, int mode);
+/* Mode 1 per sketch and round: a sketch's batch takes the owner path when it
+ * has at least ratio * w ops, else the atomic entry kernels (both run in
+ * one sub-round, each on its own sketches).  The owner path streams all of a
+ * sketch's ranges, so a batch that touches them sparsely costs less with
+ * atomics.  0 (the default) sends every batch to the owner path.  Results
+ * are the same for every ratio.  SF_EINVAL outside [0, 1e6]; waits for the
+ * stream; the next update call re-plans. */
+int sf_group_set_owner_ratio(sf_group *g, double ratio);
 /* The path the next update call takes: 0, 1 or 2 as in sf_group_set_merge. */
 int sf_group_merge_path(sf_group *g);
 /* As sf_merge_stats, summed over the group's sketches. */

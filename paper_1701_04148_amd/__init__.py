@@ -89,6 +89,7 @@ SIGNATURES = {
     "sf_group_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_group_set_merge": (_I, [_P, _I]),
     "sf_group_merge_path": (_I, [_P]),
+    "sf_group_set_owner_ratio": (_I, [_P, ctypes.c_double]),
     "sf_group_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_group_rounds": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_group_profile": (_I, [_P, _I]),
@@ -532,6 +533,11 @@ class SketchGroup:
         owner-computes S1..S5 when every sketch has the same d and z), per tile (False / 0), or
         across each sub-round with atomic S1..S5 (2)."""
         _check(lib().sf_group_set_merge(self._h, int(batch_wide)), "sf_group_set_merge")
+
+    def set_owner_ratio(self, ratio: float):
+        """Mode 1: a sketch's batch is owner-computed when it has at least ratio * w ops, else it
+        takes the atomic kernels in the same sub-round (0: every batch owner-computed)."""
+        _check(lib().sf_group_set_owner_ratio(self._h, float(ratio)), "sf_group_set_owner_ratio")
 
     def merge_path(self) -> int:
         """0 per-tile merging, 1 batch merge + owner-computes S1..S5, 2 batch merge + atomics."""

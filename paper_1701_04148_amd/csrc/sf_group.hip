@@ -68,6 +68,7 @@ struct sf_group {
     // d and z): buffers for one merged sub-round and each sub-round's ranges
     bool owner_ok = false;         // the shapes fit (buffers allocated)
     bool owner_on = false;         // merge mode 1
+    double own_ratio = 0.0;        // a sketch's batch is owner-computed when its ops >= own_ratio * w
     OwnerGeom own_og{};            // cr_shift, zbits, d (R and ncol are per sub-round)
     OwnerBufs own{};
     char* own_base = nullptr;
@@ -85,8 +86,9 @@ struct sf_group {
     struct SubRound {
         uint32_t first, tiles;
         uint64_t ops;
-        uint32_t ranges = 0;       // owner path: ranges per row (Q) of its sketches
+        uint32_t ranges = 0;       // owner path: ranges per row (Q) of its owner-computed sketches
         uint64_t table = 0;        // owner path: offset of its range table in d_ranges (words)
+        bool atomic_side = false;  // owner path: some of its sketches keep the atomic entry kernels
     };
     std::vector<SubRound> subrounds;
     uint32_t plan_kind = 0;
@@ -265,9 +267,15 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
     g->subrounds.clear();
     const bool owner = g->merge && g->owner_on;
     const uint32_t qcap = owner ? table_range_cap(g->own_og.d) : 0u;
-    auto ranges_of = [&](uint32_t s) {
-        return owner ? uint32_t((uint64_t(g->cfg[s].w) + (1ull << g->own_og.cr_shift) - 1) >> g->own_og.cr_shift)
-                     : 0u;
+    // the owner path streams every range of a sketch; a batch that touches its
+    // sketch sparsely (fewer than own_ratio * w ops) keeps the atomic kernels
+    auto owns = [&](uint32_t s, uint64_t cnt) {
+        return owner && double(cnt) >= g->own_ratio * double(g->cfg[s].w);
+    };
+    auto ranges_of = [&](uint32_t s, uint64_t cnt) {
+        return owns(s, cnt)
+                   ? uint32_t((uint64_t(g->cfg[s].w) + (1ull << g->own_og.cr_shift) - 1) >> g->own_og.cr_shift)
+                   : 0u;
     };
     const uint32_t tile_ops = g->merge ? kPartOps : uint32_t(kBlock) * g->tile_j;
     const uint64_t limit = g->merge ? g->merge_round : g->round_ops;
@@ -280,6 +288,7 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
     for (uint64_t k = 0; k < rounds; k++) {
         uint64_t used = 0;
         uint32_t first = uint32_t(g->plan.size()), q = 0;
+        bool side = false;
         for (uint32_t s = 0; s < g->n; s++) {
             const uint64_t b = g->cfg[s].batch_ops;
             const uint64_t lo = seg[s] + k * b;
@@ -287,13 +296,15 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
             const uint64_t cnt = std::min(b, seg[s + 1] - lo);
             const uint64_t tiles = (cnt + tile_ops - 1) / tile_ops;
             if (used && (used + cnt > limit || g->plan.size() - first + tiles > max_tiles ||
-                         q + ranges_of(s) > qcap)) {  // close the sub-round
-                g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used, q});
+                         q + ranges_of(s, cnt) > qcap)) {  // close the sub-round
+                g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used, q, 0, side});
                 first = uint32_t(g->plan.size());
                 used = 0;
                 q = 0;
+                side = false;
             }
-            q += ranges_of(s);
+            q += ranges_of(s, cnt);
+            side = side || (owner && !owns(s, cnt));
             for (uint64_t off = 0; off < cnt; off += tile_ops) {
                 TileDesc t{};
                 t.keys = keys + (lo + off) * g->key_bytes;
@@ -307,7 +318,7 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
             used += cnt;
         }
         if (uint32_t(g->plan.size()) > first)
-            g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used, q});
+            g->subrounds.push_back({first, uint32_t(g->plan.size()) - first, used, q, 0, side});
     }
     if (!owner) return;
     // each sub-round's range table: its sketches' ranges numbered in plan order
@@ -319,11 +330,13 @@ void build_plan(sf_group* g, const uint64_t* seg, const uint8_t* keys, const uin
         uint32_t* qsk = qbase + g->n;
         uint32_t* qr = qsk + sr.ranges;
         uint32_t qn = 0;
-        for (uint32_t t = sr.first; t < sr.first + sr.tiles; t++) {
+        for (uint32_t t = sr.first; t < sr.first + sr.tiles;) {
             const uint32_t s = g->plan[t].sketch;
-            if (qbase[s] != ~0u) continue;
+            uint64_t cnt = 0;  // the sketch's batch: its consecutive tiles
+            for (; t < sr.first + sr.tiles && g->plan[t].sketch == s; t++) cnt += g->plan[t].count;
+            if (!owns(s, cnt)) continue;  // atomic path: no ranges (qbase stays ~0)
             qbase[s] = qn;
-            for (uint32_t r = 0; r < ranges_of(s); r++, qn++) {
+            for (uint32_t r = 0, nr = ranges_of(s, cnt); r < nr; r++, qn++) {
                 qsk[qn] = s;
                 qr[qn] = r;
             }
@@ -387,8 +400,10 @@ void launch_plan(sf_group* g, bool ins, bool del, Profiler* prof) {
     for (auto& sr : g->subrounds) {
         const ListPlan<KB> plan{g->d_tiles + sr.first, g->d_desc};
         const uint32_t cnt = uint32_t(sr.ops);
-        if (owner) {
+        run.own = nullptr;
+        if (owner && sr.ranges) {
             run.own = &g->own;
+            run.side_atomic = sr.atomic_side;
             run.sub_og = g->own_og;
             run.sub_og.R = sr.ranges;
             run.sub_og.ncol = 2 * g->own_og.d * sr.ranges;
@@ -740,6 +755,17 @@ int sf_group_set_merge(sf_group* g, int mode) {
     drop_graph(g);
     g->plan_on_device = false;
     return rc;
+}
+
+int sf_group_set_owner_ratio(sf_group* g, double ratio) {
+    if (!live(g)) return fail(SF_ESTATE, "group handle is not live");
+    if (!(ratio >= 0.0 && ratio <= 1e6)) return fail(SF_EINVAL, "owner ratio must be in [0, 1e6]");
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return device_fail(e, "group sync");
+    g->own_ratio = ratio;
+    drop_graph(g);
+    g->plan_on_device = false;
+    return SF_OK;
 }
 
 int sf_group_merge_path(sf_group* g) {

@@ -311,6 +311,7 @@ struct MergeRun {
     TableRanges sub_rm{};
     OwnerGeom sub_og{};
     uint32_t max_z = 0;
+    bool side_atomic = false;  // ... some of whose sketches take the atomic entry kernels
 
     template <int D, class SR>
     void launch_owner(uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st, hipStream_t ps,
@@ -329,7 +330,6 @@ struct MergeRun {
         const unsigned eg = blocks_for(cnt, kBlock) < 4096u ? blocks_for(cnt, kBlock) : 4096u;
         // S1 one row per XCD when the row count divides the XCD count: the same
         // threads per row as eg per entry, in a multiple of 8 workgroups
-        constexpr bool kRowsPerXcd = D > 0 && kXcds % D == 0;
         const unsigned xg = kXcds * (blocks_for(uint64_t(eg) * (D > 0 ? D : 1), kXcds) < 1024u
                                          ? blocks_for(uint64_t(eg) * (D > 0 ? D : 1), kXcds)
                                          : 1024u);
@@ -385,9 +385,23 @@ struct MergeRun {
                                        own ? 0u : 1u);
         }
         if (own) {
+            if constexpr (G) {
+                // a sub-round whose sparse sketches keep the atomic path: their
+                // entries first (SketchSide skips the owner-computed sketches)
+                if (side_atomic)
+                    launch_entries<D>(eg, xg, cnt, SketchSide{sr.t, sub_rm.qbase}, ins, del, st, prof);
+            }
             launch_owner<D>(cnt, sr, ins, del, st, ps, prof);
             return;
         }
+        launch_entries<D>(eg, xg, cnt, sr, ins, del, st, prof);
+    }
+
+    // S1..S5 with one device-scope atomic per entry and row (the entries sr takes).
+    template <int D, class SR>
+    void launch_entries(unsigned eg, unsigned xg, uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st,
+                        Profiler* prof) const {
+        constexpr bool kRowsPerXcd = D > 0 && kXcds % D == 0;
         if (ins) {
             {
                 Timed tm(prof, st, SF_K_SNAPSHOT, cnt);
@@ -431,7 +445,7 @@ void MergeRun<KB, G>::launch_pairs(uint32_t cnt, const SR& sr, const RM& rm, con
                                                                             own->hmat);
     k_pair_colscan<><<<blocks_for(og.ncol, kScanCols), kScanCols * kScanWaves, 0, st>>>(own->hmat, meta,
                                                                                       own->pm[pset], og.ncol);
-    k_pair_start<><<<1, 1024, 0, st>>>(own->pm[pset], og.ncol, meta);
+    k_pair_start<><<<1, 1024, 0, st>>>(own->pm[pset], og.ncol, meta, side_atomic ? 0u : 1u);
     if (before_scatter) own->mark(hipStreamWaitEvent(st, before_scatter, 0));
     k_pair_scatter<KB, G, SR, RM><<<dim3(tiles, og.d), kPairThreads, 0, st>>>(
         meta, ent_key, ent_cnt, cap, sr, rm, og, own->hmat, own->pm[pset], own->pairs[set], own->pos, cap);
@@ -465,7 +479,8 @@ void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool de
         }
         if (ins) {
             Timed tm(prof, st, SF_K_LEVEL, cnt);
-            k_level<D><<<tiles, kPairThreads, 0, st>>>(own->pm[pset], own->pos, cap, own->res, og.d, own->level);
+            k_level<D><<<tiles, kPairThreads, 0, st>>>(own->pm[pset], ent_key, LoneRanges{}, own->pos, cap,
+                                                       own->res, og.d, own->level);
         }
         if (two) {
             own->mark(hipEventRecord(own->ev_l, st));
@@ -488,7 +503,8 @@ void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool de
                     sr, sub_rm, og, nullptr, nullptr, own->level, own->pm[0], own->pairs[0], own->res);
             }
             Timed tm(prof, st, SF_K_LEVEL, cnt);
-            k_level<D><<<tiles, kPairThreads, 0, st>>>(own->pm[0], own->pos, cap, own->res, og.d, own->level);
+            k_level<D><<<tiles, kPairThreads, 0, st>>>(own->pm[0], ent_key, sub_rm, own->pos, cap, own->res,
+                                                       og.d, own->level);
         }
         Timed tm(prof, st, SF_K_OWN_FINAL, cnt);
         k_own_step<SR, TableRanges><<<og.d * og.R, kOwnThreads, lds_bytes, st>>>(

@@ -1018,16 +1018,27 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
     }
 }
 
-// Where an entry's sketch lives: one sketch, or a table of them.
+// Where an entry's sketch lives: one sketch, or a table of them.  take(s):
+// whether the entry kernels serve sketch s's entries (all of them, except
+// in a sketch table's sub-round that also has owner-computed sketches:
+// SketchSide then leaves to the owner path every sketch with ranges).
 struct OneSketch {
     Geom g;
     uint32_t* fat;
     uint32_t* slim;
     __device__ __forceinline__ SketchDesc of(uint32_t) const { return SketchDesc{g, fat, slim}; }
+    __device__ __forceinline__ bool take(uint32_t) const { return true; }
 };
 struct SketchTable {
     const SketchDesc* t;
     __device__ __forceinline__ SketchDesc of(uint32_t s) const { return t[s]; }
+    __device__ __forceinline__ bool take(uint32_t) const { return true; }
+};
+struct SketchSide {
+    const SketchDesc* t;
+    const uint32_t* qbase;  // the sub-round's first range of each sketch, ~0: none (atomic path)
+    __device__ __forceinline__ SketchDesc of(uint32_t s) const { return t[s]; }
+    __device__ __forceinline__ bool take(uint32_t s) const { return qbase[s] == ~0u; }
 };
 
 // S1 over merged insert entries: Slim and Fat counters before the batch.
@@ -1041,6 +1052,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_snapshot(const MergeMeta* __
     const uint32_t n = meta->n_ins;
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
         const MKey<KB, G> m = ent_key[e];
+        if (!sr.take(mkey_sketch<KB, G>(m))) continue;
         const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
         const uint32_t d = SF_ROWS(D, sd.g);
         const uint32_t i0 = ent_cnt[e] & kRow0Done ? 1u : 0u;  // row 0 taken by the merge
@@ -1080,6 +1092,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_fat(MergeMeta* __restrict__ 
         const uint32_t v = del ? 0u - cnt : cnt;
         const uint32_t i0 = raw & kRow0Done ? 1u : 0u;  // row 0 added by the merge
         const MKey<KB, G> m = ent_key[id];
+        if (!sr.take(mkey_sketch<KB, G>(m))) continue;
         const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
         const uint32_t d = SF_ROWS(D, sd.g);
         const Mixed<KB> mx(m.k);
@@ -1104,6 +1117,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_raise(const MergeMeta* __res
     const uint32_t n = meta->n_ins;
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
         const MKey<KB, G> m = ent_key[e];
+        if (!sr.take(mkey_sketch<KB, G>(m))) continue;
         const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
         const uint32_t d = SF_ROWS(D, sd.g);
         const Mixed<KB> mx(m.k);
@@ -1147,6 +1161,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_clamp(const MergeMeta* __res
     const uint32_t n = meta->n_del;
     for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < n; e += gridDim.x * kBlock) {
         const MKey<KB, G> m = ent_key[cap - 1 - e];
+        if (!sr.take(mkey_sketch<KB, G>(m))) continue;
         const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
         const uint32_t d = SF_ROWS(D, sd.g);
         const Mixed<KB> mx(m.k);
@@ -1190,6 +1205,7 @@ __global__ __launch_bounds__(kBlock) void k_entries_snapshot_rows(const MergeMet
     for (uint32_t e = xr.slot * kBlock + threadIdx.x; e < n; e += xr.nslots * kBlock) {
         if (xr.r == 0 && (ent_cnt[e] & kRow0Done)) continue;  // row 0 taken by the merge
         const MKey<KB, G> m = ent_key[e];
+        if (!sr.take(mkey_sketch<KB, G>(m))) continue;
         const SketchDesc sd = sr.of(mkey_sketch<KB, G>(m));
         uint32_t h, f;
         split(sd.g, Mixed<KB>(m.k).row(sd.g.seed_base + xr.r), h, f);

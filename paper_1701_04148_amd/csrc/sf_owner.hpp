@@ -80,6 +80,7 @@ struct OwnerGeom {
 // (the same numbering in every row): qbase[s] is sketch s's first, and range
 // q belongs to sketch qsk[q], where it is the qr[q]-th.
 struct LoneRanges {
+    __device__ __forceinline__ bool has(uint32_t) const { return true; }
     __device__ __forceinline__ uint32_t q_of(uint32_t, uint32_t rng) const { return rng; }
     __device__ __forceinline__ void range_of(uint32_t q, uint32_t& sketch, uint32_t& r) const {
         sketch = 0;
@@ -90,6 +91,9 @@ struct TableRanges {
     const uint32_t* qbase;
     const uint32_t* qsk;
     const uint32_t* qr;
+    // whether sketch s is owner-computed in this sub-round (else its entries
+    // take the atomic entry kernels)
+    __device__ __forceinline__ bool has(uint32_t s) const { return qbase[s] != ~0u; }
     __device__ __forceinline__ uint32_t q_of(uint32_t s, uint32_t rng) const { return qbase[s] + rng; }
     __device__ __forceinline__ void range_of(uint32_t q, uint32_t& sketch, uint32_t& r) const {
         sketch = qsk[q];
@@ -150,6 +154,7 @@ __global__ __launch_bounds__(kCountThreads) void k_pair_count(const MergeMeta* _
     for (uint32_t v = lo + threadIdx.x; v < hi; v += kCountThreads) {
         const MKey<KB, G> m = ent_key[entry_of(v, ni, cap)];
         const uint32_t sk = mkey_sketch<KB, G>(m);
+        if (!rm.has(sk)) continue;
         const Geom g = sr.of(sk).g;
         uint32_t h, f;
         split(g, Mixed<KB>(m.k).row(g.seed_base + i), h, f);
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(kScanCols * kScanWaves) void k_pair_colscan(uint32_
 // batch's once its partition starts) and adds them to the merge statistics.
 template <int = 0>
 __global__ __launch_bounds__(1024) void k_pair_start(PairMeta* __restrict__ pm, uint32_t ncol,
-                                                     MergeMeta* __restrict__ meta) {
+                                                     MergeMeta* __restrict__ meta, uint32_t add_stats) {
     constexpr uint32_t kPer = kMaxCols / 1024;
     __shared__ uint32_t tmp[16];
     uint32_t v[kPer], sum = 0;
@@ -198,8 +203,10 @@ __global__ __launch_bounds__(1024) void k_pair_start(PairMeta* __restrict__ pm, 
     if (threadIdx.x == 0) {
         pm->n_ins = meta->n_ins;
         pm->n_del = meta->n_del;
-        meta->acc_ins += meta->n_ins;
-        meta->acc_del += meta->n_del;
+        if (add_stats) {  // (else the entry kernels of the same sub-round count them)
+            meta->acc_ins += meta->n_ins;
+            meta->acc_del += meta->n_del;
+        }
     }
 }
 
@@ -234,22 +241,27 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
     for (uint32_t c = threadIdx.x; c < nc; c += kPairThreads) cnt[c] = 0;
     __syncthreads();
     uint32_t eid[E], c16[E], col[E], code[E], rank[E];
+    bool own[E];  // the entry's sketch is owner-computed (always, for a lone sketch)
 #pragma unroll
     for (uint32_t j = 0; j < E; j++) {
         const uint32_t t = j * kPairThreads + threadIdx.x;
         eid[j] = 0;
+        own[j] = false;
         c16[j] = col[j] = code[j] = rank[j] = 0;
         if (t < n) {
             eid[j] = entry_of(lo + t, ni, cap);
-            c16[j] = ent_cnt[eid[j]] & ~kRow0Done;
             const MKey<KB, G> m = ent_key[eid[j]];
             const uint32_t sk = mkey_sketch<KB, G>(m);
-            const Geom g = sr.of(sk).g;
-            uint32_t h, f;
-            split(g, Mixed<KB>(m.k).row(g.seed_base + i), h, f);
-            col[j] = (lo + t >= ni ? R : 0u) + rm.q_of(sk, h >> og.cr_shift);
-            code[j] = ((h & cmask) << og.zbits) | f;
-            rank[j] = atomicAdd(&cnt[col[j]], 1u);
+            own[j] = rm.has(sk);
+            if (own[j]) {
+                c16[j] = ent_cnt[eid[j]] & ~kRow0Done;
+                const Geom g = sr.of(sk).g;
+                uint32_t h, f;
+                split(g, Mixed<KB>(m.k).row(g.seed_base + i), h, f);
+                col[j] = (lo + t >= ni ? R : 0u) + rm.q_of(sk, h >> og.cr_shift);
+                code[j] = ((h & cmask) << og.zbits) | f;
+                rank[j] = atomicAdd(&cnt[col[j]], 1u);
+            }
         }
     }
     __syncthreads();
@@ -274,17 +286,18 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
         gb[c] = pm->start[gcol] + hmat[size_t(trow) * og.ncol + gcol];
     }
     __syncthreads();
+    const uint32_t nst = lst[nc - 1] + cnt[nc - 1];  // pairs staged: the tile's owner-computed entries
 #pragma unroll
     for (uint32_t j = 0; j < E; j++) {
         const uint32_t t = j * kPairThreads + threadIdx.x;
-        if (t >= n) continue;
+        if (t >= n || !own[j]) continue;
         const uint32_t s = lst[col[j]] + rank[j];
         stage[s] = make_pair(eid[j], code[j], c16[j]);
         scol[s] = uint16_t(col[j]);
         if (lo + t < ni) pos[size_t(i) * pos_stride + eid[j]] = gb[col[j]] + rank[j];
     }
     __syncthreads();
-    for (uint32_t s = threadIdx.x; s < n; s += kPairThreads) {
+    for (uint32_t s = threadIdx.x; s < nst; s += kPairThreads) {
         const uint32_t c = scol[s];
         pairs[gb[c] + (s - lst[c])] = stage[s];
     }
@@ -292,8 +305,9 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
 
 // T of every insert entry from its d pairs.  One workgroup per tile of the
 // pair partition, so the runs its pairs were written in serve its entries.
-template <int D>
+template <int D, int KB, bool G, class RM>
 __global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restrict__ pm,
+                                                        const MKey<KB, G>* __restrict__ ent_key, RM rm,
                                                         const uint32_t* __restrict__ pos, uint32_t pos_stride,
                                                         const uint64_t* __restrict__ res, uint32_t d_rt,
                                                         uint16_t* __restrict__ level) {
@@ -302,6 +316,12 @@ __global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restri
     const uint32_t lo = blockIdx.x * T;
     if (lo >= ni) return;
     const uint32_t hi = min(ni, lo + T), d = D ? uint32_t(D) : d_rt;
+    bool in[E];  // an insert entry of an owner-computed sketch (its pairs hold its snapshots)
+#pragma unroll
+    for (uint32_t j = 0; j < E; j++) {
+        const uint32_t e = lo + j * kPairThreads + threadIdx.x;
+        in[j] = e < hi && rm.has(mkey_sketch<KB, G>(ent_key[e < hi ? e : lo]));
+    }
     uint32_t m0[E], dl[E], bm[E];
 #pragma unroll
     for (uint32_t j = 0; j < E; j++) m0[j] = dl[j] = bm[j] = kSlimMax;
@@ -310,12 +330,11 @@ __global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restri
 #pragma unroll
         for (uint32_t j = 0; j < E; j++) {
             const uint32_t e = lo + j * kPairThreads + threadIdx.x;
-            ps[j] = e < hi ? pos[size_t(i) * pos_stride + e] : 0u;
+            ps[j] = in[j] ? pos[size_t(i) * pos_stride + e] : 0u;
         }
 #pragma unroll
         for (uint32_t j = 0; j < E; j++) {
-            const uint32_t e = lo + j * kPairThreads + threadIdx.x;
-            const uint64_t r = e < hi ? res[ps[j]] : 0ull;
+            const uint64_t r = in[j] ? res[ps[j]] : 0ull;
             m0[j] = min(m0[j], uint32_t(r) & 0xffffu);
             dl[j] = min(dl[j], uint32_t(r >> 16) & 0xffffu);
             bm[j] = min(bm[j], uint32_t(r >> 32) & 0xffffu);
@@ -324,7 +343,7 @@ __global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restri
 #pragma unroll
     for (uint32_t j = 0; j < E; j++) {
         const uint32_t e = lo + j * kPairThreads + threadIdx.x;
-        if (e >= hi) continue;
+        if (!in[j]) continue;
         const uint32_t rise = m0[j] + dl[j], lvl = max(m0[j], bm[j]);
         level[e] = uint16_t(min(min(rise, lvl), kSlimMax));
     }

@@ -188,7 +188,8 @@ class GroupShape:
     mode: int                                   # sf_group_set_merge mode of the pick
     round_ops: int                              # ops per launch round of the pick
     ms: float                                   # its fastest update call
-    table: list = field(default_factory=list)   # (mode, round_ops, ms, sub-rounds) per candidate
+    table: list = field(default_factory=list)   # (mode, ratio, round_ops, ms, sub-rounds) per candidate
+    ratio: float = 0.0                          # sf_group_set_owner_ratio of the pick (mode 1)
 
 
 def group_round_candidates(cfgs, caps=(1 << 22, 1 << 23, 1 << 24)) -> list[int]:
@@ -199,28 +200,33 @@ def group_round_candidates(cfgs, caps=(1 << 22, 1 << 23, 1 << 24)) -> list[int]:
     return out
 
 
-def tune_group(cfgs, keys, ops, seg, modes=(1, 2), round_ops=None, reps=2) -> GroupShape:
-    """Pick the merge path (among `modes`) and the launch-round size of a group of sketches
-    `cfgs` fed the device streams (keys, ops) cut by the host offsets seg, by timing one
-    update call per repetition (after one untimed call that also records the graph)."""
+def tune_group(cfgs, keys, ops, seg, modes=(1, 2), ratios=(0.0, 0.5, 1.0, 2.0), round_ops=None,
+               reps=2) -> GroupShape:
+    """Pick the merge path (among `modes`; for mode 1 also the owner ratio among `ratios`)
+    and the launch-round size of a group of sketches `cfgs` fed the device streams (keys,
+    ops) cut by the host offsets seg, by timing one update call per repetition (after one
+    untimed call that also records the graph)."""
     import torch
     rows = []
     for r in round_ops or group_round_candidates(cfgs):
+        G = SketchGroup(cfgs, round_ops=r)
         for mode in modes:
-            G = SketchGroup(cfgs, round_ops=r)
             G.set_merge(mode)
-            best = float("inf")
-            for i in range(reps + 1):
-                G.reset()
-                G.sync()
-                t0 = time.perf_counter()
-                G.update(keys, ops, seg)
-                G.sync()
-                if i:
-                    best = min(best, (time.perf_counter() - t0) * 1e3)
-            rows.append([G.merge_path(), int(r), best, G.rounds()[0]])
-            G.close()
-            del G
-            torch.cuda.empty_cache()
-    pick = min(rows, key=lambda x: x[2])
-    return GroupShape(pick[0], pick[1], pick[2], rows)
+            for ratio in (ratios if G.merge_path() == 1 else (0.0,)):
+                if G.merge_path() == 1:
+                    G.set_owner_ratio(ratio)
+                best = float("inf")
+                for i in range(reps + 1):
+                    G.reset()
+                    G.sync()
+                    t0 = time.perf_counter()
+                    G.update(keys, ops, seg)
+                    G.sync()
+                    if i:
+                        best = min(best, (time.perf_counter() - t0) * 1e3)
+                rows.append([G.merge_path(), float(ratio), int(r), best, G.rounds()[0]])
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    pick = min(rows, key=lambda x: x[3])
+    return GroupShape(pick[0], pick[2], pick[3], rows, pick[1])

@@ -38,22 +38,27 @@ def _check_group(G, m, refs):
         assert_same(ans[int(m.qseg[i]):int(m.qseg[i + 1])], refs[i][2], f"queries of sketch {i}")
 
 
-@pytest.mark.parametrize("merge", [1, 2, 0])
+@pytest.mark.parametrize("merge,ratio", [(1, 0.0), (1, 1.0), (1, 8.0), (1, 1e6), (2, 0.0), (0, 0.0)])
 @pytest.mark.parametrize("graph", [True, False])
 @pytest.mark.parametrize("round_ops", [0, 20_000])
-def test_group_matches_oracle_per_sketch(graph, round_ops, merge):
+def test_group_matches_oracle_per_sketch(graph, round_ops, merge, ratio):
     """48 sketches of different widths, stream lengths and batch sizes, mixed ops; owner-
-    computes (1), atomic (2) and per-tile (0) merge paths."""
+    computes (1) -- every batch (ratio 0), batches of at least ratio * w ops with the others on
+    the atomic kernels in the same sub-rounds, or none (ratio 1e6) --, atomic (2) and per-tile (0)
+    merge paths."""
     import torch
     m = sfgen.config_multi(seed=3, n_sketches=48, length_scale=0.03, fat_log2=(8, 13))
     rng = np.random.default_rng(1)
     batch = rng.choice([700, 2048, 5000, 1 << 20], size=m.n)
     cfgs = _cfgs(m.w, np.full(m.n, 4), batch)
-    say(f"[case] group n={m.n} ops={m.keys.size} graph={graph} round_ops={round_ops} merge={merge}")
+    say(f"[case] group n={m.n} ops={m.keys.size} graph={graph} round_ops={round_ops} merge={merge} "
+        f"ratio={ratio}")
     G = sf.SketchGroup(cfgs, round_ops=round_ops)
     G.set_graph(graph)
     G.set_merge(merge)
     assert G.merge_path() == merge
+    if merge == 1:
+        G.set_owner_ratio(ratio)
     G.update(dev_keys(m.keys), torch.from_numpy(m.ops).cuda(), m.seg)
     sub, tiles = G.rounds()
     say(f"  sub-rounds {sub}, tiles {tiles}")
@@ -243,6 +248,10 @@ def test_group_insert_delete_and_errors():
         G.insert(keys, np.array([0, 200, 100], np.uint64))       # decreasing offsets
     with pytest.raises(sf.SFError):
         G.insert(keys, np.array([0, 100, 1 << 30], np.uint64))   # past the key buffer
+    with pytest.raises(sf.SFError):
+        G.set_owner_ratio(-1.0)
+    with pytest.raises(sf.SFError):
+        G.set_merge(3)
     G.close()
     with pytest.raises(sf.SFError):
         sf.SketchGroup([sf.make_config(4, 64, 4, 4), sf.make_config(4, 64, 4, 13)])
