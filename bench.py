@@ -487,7 +487,8 @@ def run_multi(args, torch, np, sf, sfgen):
             ref = oracle.Sketch(m.d, int(m.w[n_s]), m.z)
             ref.batch(k_i, o_i, cfgs[n_s].batch_ops)
             ans = ref.query(q_i)
-            if not np.array_equal(ans, group_answers[qseg[n_s]:qseg[n_s + 1]]):
+            q0, q1 = int(m.qseg[n_s]), int(m.qseg[n_s + 1])
+            if not np.array_equal(ans, group_answers[q0:q1]):
                 raise SystemExit(f"sketch {n_s}: GPU answers differ from the oracle")
             items += k_i.shape[0] + q_i.shape[0]
             n_s += 1
