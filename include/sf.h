@@ -230,12 +230,14 @@ int sf_set_merge(sf_sketch *sk, int batch_wide);
 int sf_merge_path(sf_sketch *sk);
 
 /* Range size of the owner path: ranges of 2^shift cells per row.  shift 0
- * restores the default (at least 256 cells, more where a row would otherwise
- * have over min(1024, 8192 / d) ranges).  Allowed shifts run from that
- * smallest one (at least 4) to the largest whose range holds at most 8192
- * Fat counters and 2^16 (cell, slot) codes; SF_EINVAL outside them or when
- * the shape has no owner path.  Takes effect at the next update call; the
- * results do not depend on it. */
+ * restores the default (about 512 ranges per row but at least 256 cells,
+ * within the allowed sizes: 2048 cells at w = 2^20, 256 at w = 2^14).
+ * Ranges of more than 24 KiB of records get 512-thread workgroups, smaller
+ * ones 256.  Allowed shifts run from the smallest that keeps a row within
+ * min(1024, 8192 / d) ranges (at least 4) to the largest whose range holds
+ * at most 8192 Fat counters and 2^16 (cell, slot) codes; SF_EINVAL outside
+ * them or when the shape has no owner path.  Takes effect at the next update
+ * call; the results do not depend on it. */
 int sf_set_owner_range(sf_sketch *sk, uint32_t shift);
 /* The current range shift of the owner path; 0 when the shape has none. */
 int sf_owner_range(sf_sketch *sk);

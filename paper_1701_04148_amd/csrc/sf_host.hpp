@@ -220,15 +220,20 @@ inline bool owner_shifts(const sf_config* c, uint32_t* lo, uint32_t* hi) {
     return true;
 }
 
-// Default range size: at least 256 cells (fewer, busier owner workgroups and
-// a shorter column scan for narrow sketches), more where the row needs it.
-constexpr uint32_t kDefaultRangeShift = 8;
+// Default range size: about kDefaultRanges ranges per row, at least 256
+// cells (fewer, busier owner workgroups and a shorter column scan for narrow
+// sketches), within the allowed sizes.  (Measured: 2048-cell ranges at
+// w = 2^20, 256 at w = 2^14.)
+constexpr uint32_t kDefaultRangeShiftMin = 8, kDefaultRangesLog2 = 9;
 
 // The owner layout with ranges of 2^shift cells (0: the default size).
 inline bool owner_geom(const sf_config* c, OwnerGeom* og, uint32_t shift = 0) {
     uint32_t lo, hi;
     if (!owner_shifts(c, &lo, &hi)) return false;
-    const uint32_t sh = shift ? shift : std::min(hi, std::max(lo, kDefaultRangeShift));
+    uint32_t wl = 0;
+    while ((1ull << (wl + 1)) <= c->w) wl++;  // floor(log2 w)
+    const uint32_t want = std::max(kDefaultRangeShiftMin, wl > kDefaultRangesLog2 ? wl - kDefaultRangesLog2 : 0u);
+    const uint32_t sh = shift ? shift : std::min(hi, std::max(lo, want));
     if (sh < lo || sh > hi) return false;
     uint32_t zbits = 0;
     while ((1ull << zbits) < c->z) zbits++;
@@ -278,15 +283,27 @@ inline size_t own_step_lds(const Geom& g, const OwnerGeom& og) {
     return (size_t(1) << og.cr_shift) * g.rs * 4;
 }
 
+// One owner-step launch: 512-thread workgroups for ranges of more than
+// kOwnWideLds bytes (fewer of them fit a CU, so each gets more waves).
+template <class SR, class RM>
+inline void launch_own_step(unsigned grid, size_t lds, hipStream_t st, const SR& sr, const RM& rm,
+                            const OwnerGeom& og, const PairMeta* pm_f, const uint64_t* pairs_f,
+                            const uint16_t* level, const PairMeta* pm_i, const uint64_t* pairs_i, uint64_t* res) {
+    if (lds > kOwnWideLds)
+        k_own_step<SR, RM, kOwnThreadsWide><<<grid, kOwnThreadsWide, lds, st>>>(sr, rm, og, pm_f, pairs_f, level,
+                                                                                pm_i, pairs_i, res);
+    else
+        k_own_step<SR, RM><<<grid, kOwnThreads, lds, st>>>(sr, rm, og, pm_f, pairs_f, level, pm_i, pairs_i, res);
+}
+
 // The closing owner step of an update call: S3..S5 of its last batch.
 inline void owner_close(OwnerBufs* own, const Geom& g, uint32_t* fat, uint32_t* slim, hipStream_t st,
                         Profiler* prof) {
     if (!own->pending) return;
     const uint32_t prev = own->cur ^ 1u, pprev = (own->pmc + 2u) % 3u;
     Timed tm(prof, st, SF_K_OWN_FINAL, 0);
-    k_own_step<OneSketch, LoneRanges><<<g.d * own->og.R, kOwnThreads, own_step_lds(g, own->og), st>>>(
-        OneSketch{g, fat, slim}, LoneRanges{}, own->og, own->pm[pprev], own->pairs[prev], own->level, nullptr,
-        nullptr, own->res);
+    launch_own_step(g.d * own->og.R, own_step_lds(g, own->og), st, OneSketch{g, fat, slim}, LoneRanges{}, own->og,
+                    own->pm[pprev], own->pairs[prev], own->level, nullptr, nullptr, own->res);
     own->pending = false;
 }
 
@@ -472,10 +489,9 @@ void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool de
         }
         {
             Timed tm(prof, st, SF_K_OWN_STEP, cnt);
-            k_own_step<SR, LoneRanges><<<og.d * og.R, kOwnThreads, own_step_lds(sr.g, og), st>>>(
-                sr, LoneRanges{}, og, own->pending ? own->pm[pprev] : nullptr,
-                own->pending ? own->pairs[prev] : nullptr, own->level, ins ? own->pm[pset] : nullptr,
-                ins ? own->pairs[set] : nullptr, own->res);
+            launch_own_step(og.d * og.R, own_step_lds(sr.g, og), st, sr, LoneRanges{}, og,
+                            own->pending ? own->pm[pprev] : nullptr, own->pending ? own->pairs[prev] : nullptr,
+                            own->level, ins ? own->pm[pset] : nullptr, ins ? own->pairs[set] : nullptr, own->res);
         }
         if (ins) {
             Timed tm(prof, st, SF_K_LEVEL, cnt);
@@ -499,16 +515,16 @@ void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool de
         if (ins) {
             {
                 Timed tm(prof, st, SF_K_OWN_STEP, cnt);
-                k_own_step<SR, TableRanges><<<og.d * og.R, kOwnThreads, lds_bytes, st>>>(
-                    sr, sub_rm, og, nullptr, nullptr, own->level, own->pm[0], own->pairs[0], own->res);
+                launch_own_step(og.d * og.R, lds_bytes, st, sr, sub_rm, og, nullptr, nullptr, own->level, own->pm[0],
+                                own->pairs[0], own->res);
             }
             Timed tm(prof, st, SF_K_LEVEL, cnt);
             k_level<D><<<tiles, kPairThreads, 0, st>>>(own->pm[0], ent_key, sub_rm, own->pos, cap, own->res,
                                                        og.d, own->level);
         }
         Timed tm(prof, st, SF_K_OWN_FINAL, cnt);
-        k_own_step<SR, TableRanges><<<og.d * og.R, kOwnThreads, lds_bytes, st>>>(
-            sr, sub_rm, og, own->pm[0], own->pairs[0], own->level, nullptr, nullptr, own->res);
+        launch_own_step(og.d * og.R, lds_bytes, st, sr, sub_rm, og, own->pm[0], own->pairs[0], own->level, nullptr,
+                        nullptr, own->res);
     }
     (void)del;
     (void)ps;

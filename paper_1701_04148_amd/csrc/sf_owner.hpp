@@ -50,7 +50,9 @@ constexpr uint32_t kCountThreads = 256;  // threads of k_pair_count
 constexpr uint32_t kMaxCols = 16384;     // columns: 2 op types x d rows x R ranges
 constexpr uint32_t kMaxRanges = 1024;    // ranges per row
 constexpr uint32_t kOwnCounters = 8192;  // Fat counters of one range (its records fit 64 KiB of LDS)
-constexpr uint32_t kOwnThreads = 256;
+constexpr uint32_t kOwnThreads = 256;    // threads of an owner workgroup ...
+constexpr uint32_t kOwnThreadsWide = 512;  // ... whose range takes more than kOwnWideLds bytes of LDS
+constexpr size_t kOwnWideLds = 24u << 10;
 
 __host__ __device__ constexpr uint32_t pair_tile(uint32_t nv) {
     const uint32_t per = (nv + kPairTiles - 1) / kPairTiles;
@@ -362,8 +364,8 @@ __global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restri
 //                res[p] = (A, growth, Bpost), each capped at 65535 (T is
 //                capped there, so the caps change no T)
 // The range is read once and written once per step.
-template <class SR, class RM>
-__global__ __launch_bounds__(kOwnThreads) void k_own_step(SR sr, RM rm, OwnerGeom og,
+template <class SR, class RM, uint32_t NT = kOwnThreads>
+__global__ __launch_bounds__(NT) void k_own_step(SR sr, RM rm, OwnerGeom og,
                                                           const PairMeta* __restrict__ pm_f,
                                                           const uint64_t* __restrict__ pairs_f,
                                                           const uint16_t* __restrict__ level,
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(SR sr, RM rm, OwnerGeo
                                                           const uint64_t* __restrict__ pairs_i,
                                                           uint64_t* __restrict__ res) {
     extern __shared__ uint32_t L[];  // ncells records of rs words
-    constexpr uint32_t T = kOwnThreads;
+    constexpr uint32_t T = NT;
     constexpr uint32_t K = 4;   // this batch's insert pairs per thread held in registers (more: through res)
     constexpr uint32_t KF = 4;  // the previous batch's insert pairs per thread held in registers (more: a loop)
     constexpr uint32_t KD = 2;  // ... and its delete pairs
@@ -426,9 +428,9 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(SR sr, RM rm, OwnerGeo
         const uint4* src = reinterpret_cast<const uint4*>(rec0);
         uint4* dst = reinterpret_cast<uint4*>(L);
 #pragma unroll 4
-        for (uint32_t i = threadIdx.x; i < n4; i += kOwnThreads) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < n4; i += T) dst[i] = src[i];
 #pragma unroll 4
-        for (uint32_t i = 4 * n4 + threadIdx.x; i < nw; i += kOwnThreads) L[i] = rec0[i];
+        for (uint32_t i = 4 * n4 + threadIdx.x; i < nw; i += T) L[i] = rec0[i];
     }
     __syncthreads();
     if (fi0 != fi1 || fd0 != fd1) {
@@ -504,9 +506,9 @@ __global__ __launch_bounds__(kOwnThreads) void k_own_step(SR sr, RM rm, OwnerGeo
         uint4* dst = reinterpret_cast<uint4*>(rec0);
         const uint4* src = reinterpret_cast<const uint4*>(L);
 #pragma unroll 4
-        for (uint32_t i = threadIdx.x; i < n4; i += kOwnThreads) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < n4; i += T) dst[i] = src[i];
 #pragma unroll 4
-        for (uint32_t i = 4 * n4 + threadIdx.x; i < nw; i += kOwnThreads) rec0[i] = L[i];
+        for (uint32_t i = 4 * n4 + threadIdx.x; i < nw; i += T) rec0[i] = L[i];
     }
 }
 
