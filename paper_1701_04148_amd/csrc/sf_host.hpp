@@ -276,7 +276,23 @@ struct OwnerBufs {
     void mark(hipError_t e) {
         if (e != hipSuccess && err == hipSuccess) err = e;
     }
+    // One stream: a batch's k_level waits to share a launch with the next
+    // batch's k_part_count; level_flush launches it alone (call end, path
+    // switch).
+    bool level_due = false;
+    uint32_t level_pset = 0, level_tiles = 0, cap = 0;
+    const void* level_keys = nullptr;
+    void (*level_flush)(OwnerBufs*, hipStream_t) = nullptr;
 };
+
+// k_level of the deferred batch on its own.
+template <int D, int KB>
+void flush_level(OwnerBufs* o, hipStream_t st) {
+    k_level<D, KB, false, LoneRanges><<<o->level_tiles, kPairThreads, 0, st>>>(
+        o->pm[o->level_pset], static_cast<const MKey<KB, false>*>(o->level_keys), LoneRanges{}, o->pos, o->cap,
+        o->res, o->og.d, o->level);
+    o->level_due = false;
+}
 
 // LDS of one owner step: the range's records.
 inline size_t own_step_lds(const Geom& g, const OwnerGeom& og) {
@@ -299,6 +315,7 @@ inline void launch_own_step(unsigned grid, size_t lds, hipStream_t st, const SR&
 // The closing owner step of an update call: S3..S5 of its last batch.
 inline void owner_close(OwnerBufs* own, const Geom& g, uint32_t* fat, uint32_t* slim, hipStream_t st,
                         Profiler* prof) {
+    if (own->level_due) own->level_flush(own, st);
     if (!own->pending) return;
     const uint32_t prev = own->cur ^ 1u, pprev = (own->pmc + 2u) % 3u;
     Timed tm(prof, st, SF_K_OWN_FINAL, 0);
@@ -372,7 +389,27 @@ struct MergeRun {
         if (wide) part_groups = blocks_for(cnt, kPartOpsWide);
         {
             Timed tm(prof, ps, SF_K_PARTITION, cnt);
-            if (wide)
+            bool counted = false;
+            if constexpr (!G) {
+                // the previous batch's k_level rides along (one stream only)
+                if (own && own->level_due && ps == st) {
+                    const unsigned grid = part_groups + own->level_tiles;
+                    if (wide)
+                        k_part_count_level<KB, P, kPartOpsWide, D><<<grid, kPartThreads, 0, ps>>>(
+                            plan, hist, nb_log2, part_groups, own->pm[own->level_pset], ent_key, own->pos, cap,
+                            own->res, own->og.d, own->level);
+                    else
+                        k_part_count_level<KB, P, kPartOps, D><<<grid, kPartThreads, 0, ps>>>(
+                            plan, hist, nb_log2, part_groups, own->pm[own->level_pset], ent_key, own->pos, cap,
+                            own->res, own->og.d, own->level);
+                    own->level_due = false;
+                    counted = true;
+                } else if (own && own->level_due) {
+                    own->level_flush(own, st);
+                }
+            }
+            if (counted) {
+            } else if (wide)
                 k_part_count<KB, G, P, kPartOpsWide><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, nb_log2);
             else
                 k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, nb_log2);
@@ -493,7 +530,15 @@ void MergeRun<KB, G>::launch_owner(uint32_t cnt, const SR& sr, bool ins, bool de
                             own->pending ? own->pm[pprev] : nullptr, own->pending ? own->pairs[prev] : nullptr,
                             own->level, ins ? own->pm[pset] : nullptr, ins ? own->pairs[set] : nullptr, own->res);
         }
-        if (ins) {
+        if (ins && !two && !(prof && prof->on)) {
+            // one stream: T of this batch is taken in the next batch's first launch
+            // (or alone when the call or the path ends there)
+            own->level_due = true;
+            own->level_pset = pset;
+            own->level_tiles = tiles;
+            own->level_keys = ent_key;
+            own->level_flush = &flush_level<D, KB>;
+        } else if (ins) {
             Timed tm(prof, st, SF_K_LEVEL, cnt);
             k_level<D><<<tiles, kPairThreads, 0, st>>>(own->pm[pset], ent_key, LoneRanges{}, own->pos, cap,
                                                        own->res, og.d, own->level);

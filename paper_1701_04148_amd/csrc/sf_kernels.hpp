@@ -571,12 +571,13 @@ __device__ __forceinline__ uint32_t xcd_row(uint32_t b, uint32_t n) {
 }
 
 // Counts the ops of every bucket in each group's tile.
-template <int KB, bool G, class P, uint32_t OPS = kPartOps>
-__global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* __restrict__ hist_out,
-                                                         uint32_t nb_log2) {
+// The histogram of tile blk (of ntiles): one workgroup of kPartThreads.
+template <int KB, bool G, class P, uint32_t OPS>
+__device__ __forceinline__ void part_count_tile(const P& plan, uint32_t* __restrict__ hist_out, uint32_t nb_log2,
+                                                uint32_t blk, uint32_t ntiles) {
     __shared__ uint32_t hist[2 * kMaxBuckets];
     const uint32_t nbt = 2u << nb_log2;
-    const Work w = plan.at(blockIdx.x, OPS);
+    const Work w = plan.at(blk, OPS);
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < w.count; t += kPartThreads) {
@@ -584,8 +585,14 @@ __global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* _
         atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2, w.g)], 1u);
     }
     __syncthreads();
-    const uint32_t row = xcd_row(blockIdx.x, gridDim.x);
+    const uint32_t row = xcd_row(blk, ntiles);
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist_out[size_t(row) * nbt + b] = hist[b];
+}
+
+template <int KB, bool G, class P, uint32_t OPS = kPartOps>
+__global__ __launch_bounds__(kPartThreads) void k_part_count(P plan, uint32_t* __restrict__ hist_out,
+                                                         uint32_t nb_log2) {
+    part_count_tile<KB, G, P, OPS>(plan, hist_out, nb_log2, blockIdx.x, gridDim.x);
 }
 
 // Column scans of hist: 64 buckets per workgroup, one per lane, so that a

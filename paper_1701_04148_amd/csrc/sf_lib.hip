@@ -301,6 +301,8 @@ int owner_alloc(sf_sketch* s) {
     s->own.pairs[0] = reinterpret_cast<uint64_t*>(ob);
     s->own.pairs[1] = reinterpret_cast<uint64_t*>(ob + sz.pairs / 2);
     s->own.pos = reinterpret_cast<uint32_t*>(ob + sz.pairs);
+    s->own.cap = uint32_t(s->cfg.batch_ops);
+    s->own.level_due = false;
     s->own.res = reinterpret_cast<uint64_t*>(ob + sz.pairs + sz.pos);
     s->own.level = reinterpret_cast<uint16_t*>(ob + sz.pairs + sz.pos + sz.res);
     s->own.hmat = reinterpret_cast<uint32_t*>(ob + sz.pairs + sz.pos + sz.res + sz.level);

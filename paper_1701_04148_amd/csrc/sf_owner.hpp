@@ -305,23 +305,24 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
     }
 }
 
-// T of every insert entry from its d pairs.  One workgroup per tile of the
-// pair partition, so the runs its pairs were written in serve its entries.
-template <int D, int KB, bool G, class RM>
-__global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restrict__ pm,
-                                                        const MKey<KB, G>* __restrict__ ent_key, RM rm,
-                                                        const uint32_t* __restrict__ pos, uint32_t pos_stride,
-                                                        const uint64_t* __restrict__ res, uint32_t d_rt,
-                                                        uint16_t* __restrict__ level) {
-    constexpr uint32_t E = kPairTileMax / kPairThreads;
+// T of every insert entry of tile blk from its d pairs, NT threads.  The
+// tiles are those of the pair partition, so the runs its pairs were written
+// in serve its entries.
+template <uint32_t NT, int D, int KB, bool G, class RM>
+__device__ __forceinline__ void level_tile(uint32_t blk, const PairMeta* __restrict__ pm,
+                                           const MKey<KB, G>* __restrict__ ent_key, RM rm,
+                                           const uint32_t* __restrict__ pos, uint32_t pos_stride,
+                                           const uint64_t* __restrict__ res, uint32_t d_rt,
+                                           uint16_t* __restrict__ level) {
+    constexpr uint32_t E = kPairTileMax / NT;
     const uint32_t ni = pm->n_ins, T = pair_tile(ni + pm->n_del);
-    const uint32_t lo = blockIdx.x * T;
+    const uint32_t lo = blk * T;
     if (lo >= ni) return;
     const uint32_t hi = min(ni, lo + T), d = D ? uint32_t(D) : d_rt;
     bool in[E];  // an insert entry of an owner-computed sketch (its pairs hold its snapshots)
 #pragma unroll
     for (uint32_t j = 0; j < E; j++) {
-        const uint32_t e = lo + j * kPairThreads + threadIdx.x;
+        const uint32_t e = lo + j * NT + threadIdx.x;
         in[j] = e < hi && rm.has(mkey_sketch<KB, G>(ent_key[e < hi ? e : lo]));
     }
     uint32_t m0[E], dl[E], bm[E];
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restri
         uint32_t ps[E];
 #pragma unroll
         for (uint32_t j = 0; j < E; j++) {
-            const uint32_t e = lo + j * kPairThreads + threadIdx.x;
+            const uint32_t e = lo + j * NT + threadIdx.x;
             ps[j] = in[j] ? pos[size_t(i) * pos_stride + e] : 0u;
         }
 #pragma unroll
@@ -344,11 +345,41 @@ __global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restri
     }
 #pragma unroll
     for (uint32_t j = 0; j < E; j++) {
-        const uint32_t e = lo + j * kPairThreads + threadIdx.x;
+        const uint32_t e = lo + j * NT + threadIdx.x;
         if (!in[j]) continue;
         const uint32_t rise = m0[j] + dl[j], lvl = max(m0[j], bm[j]);
         level[e] = uint16_t(min(min(rise, lvl), kSlimMax));
     }
+}
+
+template <int D, int KB, bool G, class RM>
+__global__ __launch_bounds__(kPairThreads) void k_level(const PairMeta* __restrict__ pm,
+                                                        const MKey<KB, G>* __restrict__ ent_key, RM rm,
+                                                        const uint32_t* __restrict__ pos, uint32_t pos_stride,
+                                                        const uint64_t* __restrict__ res, uint32_t d_rt,
+                                                        uint16_t* __restrict__ level) {
+    level_tile<kPairThreads, D, KB, G, RM>(blockIdx.x, pm, ent_key, rm, pos, pos_stride, res, d_rt, level);
+}
+
+// A lone sketch on one stream: k_level of batch k and k_part_count of batch
+// k + 1 in one launch (the first count_tiles workgroups count, the others
+// take level tiles).  Neither reads what the other writes, and both are too
+// short to fill the GPU alone.
+template <int KB, class P, uint32_t OPS, int D>
+__global__ __launch_bounds__(kPartThreads) void k_part_count_level(P plan, uint32_t* __restrict__ hist_out,
+                                                                   uint32_t nb_log2, uint32_t count_tiles,
+                                                                   const PairMeta* __restrict__ pm,
+                                                                   const MKey<KB, false>* __restrict__ ent_key,
+                                                                   const uint32_t* __restrict__ pos,
+                                                                   uint32_t pos_stride,
+                                                                   const uint64_t* __restrict__ res, uint32_t d_rt,
+                                                                   uint16_t* __restrict__ level) {
+    if (blockIdx.x < count_tiles) {
+        part_count_tile<KB, false, P, OPS>(plan, hist_out, nb_log2, blockIdx.x, count_tiles);
+        return;
+    }
+    level_tile<kPartThreads, D, KB, false, LoneRanges>(blockIdx.x - count_tiles, pm, ent_key, LoneRanges{}, pos,
+                                                       pos_stride, res, d_rt, level);
 }
 
 // One owner step of one (row, range), its records staged in LDS (the range's
