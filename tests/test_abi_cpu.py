@@ -74,7 +74,12 @@ def test_footprint_and_budget():
 
 
 def test_dead_handles_rejected():
-    for fn in ("sf_destroy", "sf_sync", "sf_reset"):
-        assert getattr(sf.lib(), fn)(None) == sf.SF_ESTATE
+    for fn in ("sf_destroy", "sf_sync", "sf_reset", "sf_merge_path", "sf_owner_range", "sf_group_merge_path",
+               "sf_group_destroy", "sf_pool_destroy"):
+        assert getattr(sf.lib(), fn)(None) == sf.SF_ESTATE, fn
+    assert sf.lib().sf_set_streams(None, 0) == sf.SF_ESTATE
+    assert sf.lib().sf_set_owner_range(None, 0) == sf.SF_ESTATE
+    assert sf.lib().sf_group_set_owner_ratio(None, 1.0) == sf.SF_ESTATE
+    assert sf.lib().sf_group_set_merge(None, 1) == sf.SF_ESTATE
     assert sf.lib().sf_insert(None, None, 0) == sf.SF_ESTATE
     assert sf.lib().sf_query(ctypes.c_void_p(12345), None, 0, None) == sf.SF_ESTATE

@@ -178,6 +178,8 @@ def test_owner_two_streams_uniform_ops():
     say("[case] two streams, insert then delete calls")
     sk = sf.Sketch(4, 1024, 4, batch_ops=2048)
     sk.set_merge(3)
+    with pytest.raises(sf.SFError):
+        sk.set_streams(2)
     sk.set_streams(1)
     sk.insert(dev_keys(keys))
     sk.delete(dev_keys(dels))
