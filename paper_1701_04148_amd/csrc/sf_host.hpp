@@ -455,7 +455,7 @@ struct MergeRun {
     template <int D, class SR>
     void launch_entries(unsigned eg, unsigned xg, uint32_t cnt, const SR& sr, bool ins, bool del, hipStream_t st,
                         Profiler* prof) const {
-        constexpr bool kRowsPerXcd = D > 0 && kXcds % D == 0;
+        constexpr bool kRowsPerXcd = D > 0 && kXcds % (D > 0 ? D : 1) == 0;
         if (ins) {
             {
                 Timed tm(prof, st, SF_K_SNAPSHOT, cnt);
