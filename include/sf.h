@@ -403,8 +403,18 @@ int sf_pool_export_fat(sf_pool *p, uint32_t slot, uint32_t *out, uint64_t out_el
 int sf_pool_sync(sf_pool *p);
 int sf_pool_set_tile(sf_pool *p, uint32_t tile_ops);
 /* As sf_set_merge for the pool's later launches (default 1); (key, slot)
- * pairs are merged across a sub-round of at most 2^24 ops (or batch_ops). */
+ * pairs are merged across a sub-round of at most 2^24 ops (or batch_ops).
+ * With batch-wide merging, pools whose slots hold at most 64 MiB of records
+ * run a request batch of at least ratio * w ops (sf_pool_set_owner_ratio,
+ * default 1) owner-computes: its slot's (row, range) tiles staged in LDS, a
+ * sub-round's owner batches at most 2^22 ops and min(1024, 8192 / d) ranges
+ * per row; the other batches of the sub-round take the atomic entry kernels.
+ * The owner buffers are part of the shared buffers (fewer slots fit the
+ * budget).  Results are the same on either path. */
 int sf_pool_set_merge(sf_pool *p, int batch_wide);
+/* The owner ratio above; SF_EINVAL for a pool without the owner path or a
+ * ratio outside [0, 1e6] (0: every batch that fits the owner buffers). */
+int sf_pool_set_owner_ratio(sf_pool *p, double ratio);
 /* As sf_merge_stats, summed over all launches of the pool; waits for it. */
 int sf_pool_merge_stats(sf_pool *p, uint64_t *insert_entries, uint64_t *delete_entries);
 

@@ -108,6 +108,7 @@ SIGNATURES = {
     "sf_pool_sync": (_I, [_P]),
     "sf_pool_set_tile": (_I, [_P, ctypes.c_uint32]),
     "sf_pool_set_merge": (_I, [_P, _I]),
+    "sf_pool_set_owner_ratio": (_I, [_P, ctypes.c_double]),
     "sf_pool_merge_stats": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "sf_strerror": (ctypes.c_char_p, [_I]),
     "sf_last_error": (ctypes.c_char_p, []),
@@ -673,6 +674,11 @@ class SketchPool:
     def set_merge(self, batch_wide: bool):
         """Merge duplicate (key, slot) pairs across each sub-round (True, the default) or per tile."""
         _check(lib().sf_pool_set_merge(self._h, int(bool(batch_wide))), "sf_pool_set_merge")
+
+    def set_owner_ratio(self, ratio: float):
+        """Batches of at least ratio * w ops take the owner-computes path (pools whose slots hold
+        at most 64 MiB of records; default 1)."""
+        _check(lib().sf_pool_set_owner_ratio(self._h, float(ratio)), "sf_pool_set_owner_ratio")
 
     def merge_stats(self):
         """(insert entries, delete entries) emitted by the batch-wide merge so far, all launches."""

@@ -13,13 +13,19 @@
 //
 // Update sub-rounds take the batch-merge path by default (duplicate (key,
 // slot) pairs merged across the sub-round, S1..S5 once per merged entry);
-// merged sub-rounds hold at most 2^24 ops, or one batch if larger.
+// merged sub-rounds hold at most 2^24 ops, or one batch if larger.  For slots
+// of at most 64 MiB of records, a request batch of at least owner_ratio * w
+// ops takes owner-computes S1..S5 (its slot's (row, range) tiles staged in
+// LDS) and the others the atomic entry kernels, in the same sub-round; a
+// sub-round's owner batches hold at most 2^22 ops, and its range table
+// travels in the descriptor ring beside its tiles.
 //
 // Tile descriptors of in-flight launches live in a device ring; a region is
 // reused only after the launch that reads it has completed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <deque>
 #include <mutex>
 #include <string>
@@ -71,6 +77,12 @@ struct sf_pool {
     uint64_t done_upto;  // every ticket <= done_upto has completed
     std::vector<hipEvent_t> spare;
     Profiler prof;
+    // owner-computes S1..S5 (slots whose records are small enough to stream)
+    bool owner_ok = false;
+    double own_ratio = 1.0;        // a batch is owner-computed when its ops >= own_ratio * w
+    uint64_t owner_ops = 0;        // owner batches' ops per sub-round at most
+    OwnerGeom own_og{};
+    OwnerBufs own{};
 };
 
 namespace {
@@ -88,12 +100,39 @@ constexpr uint64_t kHistExtra = 1024;            // partial tiles (one per reque
 
 struct PoolLayout {
     uint64_t slot_bytes, per_slot, shared, round_ops, merge_round, mkey;
+    bool owner = false;
+    OwnerGeom og{};
+    uint64_t owner_ops = 0, pairs = 0, pos = 0, res = 0, level = 0, hmat = 0, pmeta = 0;
 };
 
 struct SubRound {
     uint32_t first, tiles;
     uint64_t ops;
+    uint32_t ranges = 0;           // owner path: ranges per row of its owner batches
+    bool atomic_side = false;      // ... beside batches on the atomic entry kernels
+    uint64_t table = 0;            // ... offset of its range table (words) in the launch's table area
 };
+
+constexpr uint64_t kPoolOwnerSlotBytes = 64ull << 20;  // slots whose records the owner path may stream
+constexpr uint64_t kPoolOwnerOps = 1ull << 22;         // owner batches' ops per sub-round
+
+// Owner layout of a pool's slots: one slot's ranges as large as a range's Fat
+// counters allow, all of them within one sub-round's range table.
+bool pool_owner_geom(const sf_config* c, OwnerGeom* og) {
+    if (uint64_t(c->d) * c->w * (c->z + 1) * 4 > kPoolOwnerSlotBytes) return false;
+    uint32_t zbits = 0;
+    while ((1ull << zbits) < c->z) zbits++;
+    uint32_t sh = 4;
+    while ((2ull << sh) * c->z <= kOwnCounters && ((2ull << sh) << zbits) <= 65536) sh++;
+    if ((1ull << sh) * c->z > kOwnCounters || ((1ull << sh) << zbits) > 65536) return false;
+    const uint32_t qcap = std::min<uint32_t>(kMaxRanges, kMaxCols / (2 * c->d));
+    if (((uint64_t(c->w) + (1ull << sh) - 1) >> sh) > qcap) return false;
+    *og = OwnerGeom{};
+    og->cr_shift = sh;
+    og->zbits = zbits;
+    og->d = c->d;
+    return true;
+}
 
 PoolLayout pool_layout(const sf_config* c, uint64_t round_ops) {
     PoolLayout L;
@@ -108,6 +147,21 @@ PoolLayout pool_layout(const sf_config* c, uint64_t round_ops) {
                2 * round256(L.merge_round * L.mkey) + round256(L.merge_round * 4) + round256(sizeof(MergeMeta)) +
                round256(part_groups_max(L.merge_round, kHistExtra) * 2 * kMaxBuckets * 4) +
                round256(merge_chunks_max(L.merge_round) * sizeof(MergeChunk));
+    L.owner = pool_owner_geom(c, &L.og);
+    if (L.owner) {
+        // pairs and their snapshots for the owner batches; positions and T
+        // for every entry of a sub-round; column counts for all its tiles
+        const uint64_t d = c->d, mr = L.merge_round;
+        const uint32_t qcap = std::min<uint32_t>(kMaxRanges, kMaxCols / (2 * c->d));
+        L.owner_ops = std::min(mr, kPoolOwnerOps);
+        L.pairs = round256(d * L.owner_ops * 8);
+        L.pos = round256(d * mr * 4);
+        L.res = round256(d * L.owner_ops * 8);
+        L.level = round256(mr * 2);
+        L.hmat = round256(uint64_t(pair_tiles_max(uint32_t(mr))) * 2 * d * qcap * 4);
+        L.pmeta = round256(sizeof(PairMeta));
+        L.shared += L.pairs + L.pos + L.res + L.level + L.hmat + L.pmeta;
+    }
     return L;
 }
 
@@ -149,11 +203,11 @@ int ring_alloc(sf_pool* p, size_t k, size_t* begin) {
 
 template <int KB>
 void launch_updates(sf_pool* p, const TileDesc* d_tiles, const std::vector<SubRound>& subs,
-                    const std::vector<TileDesc>& host) {
-    const MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(p->part), static_cast<MKey<KB, true>*>(p->ent_key),
-                                 p->ent_cnt, p->meta, p->hist, p->chunks, uint32_t(p->merge_round), p->bpre,
-                                 p->asnap,
-                                 uint32_t(p->round_ops)};
+                    const std::vector<TileDesc>& host, const uint32_t* d_tables) {
+    MergeRun<KB, true> run{static_cast<MKey<KB, true>*>(p->part), static_cast<MKey<KB, true>*>(p->ent_key),
+                           p->ent_cnt, p->meta, p->hist, p->chunks, uint32_t(p->merge_round), p->bpre,
+                           p->asnap,
+                           uint32_t(p->round_ops)};
     const SketchTable table{p->d_desc};
     for (auto& sr : subs) {
         bool ins = false, del = false;
@@ -164,6 +218,18 @@ void launch_updates(sf_pool* p, const TileDesc* d_tiles, const std::vector<SubRo
         }
         const ListPlan<KB> plan{d_tiles + sr.first, p->d_desc};
         const uint32_t cnt = uint32_t(sr.ops);
+        run.own = nullptr;
+        if (p->merge && sr.ranges) {  // owner-computed batches in this sub-round
+            const uint32_t* tab = d_tables + sr.table;
+            run.own = &p->own;
+            run.side_atomic = sr.atomic_side;
+            run.sub_og = p->own_og;
+            run.sub_og.R = sr.ranges;
+            run.sub_og.ncol = 2 * p->own_og.d * sr.ranges;
+            run.sub_og.xcd = (kXcds % p->own_og.d == 0 && (p->own_og.d * sr.ranges) % kXcds == 0) ? 1u : 0u;
+            run.sub_rm = TableRanges{tab, tab + p->slots, tab + p->slots + sr.ranges};
+            run.max_z = p->cfg.z;
+        }
         if (!p->merge) {
             Steps<ListPlan>::by_rows<KB>(p->cfg.d, p->tile_j, plan, sr.tiles, ins, del, p->bpre, p->asnap,
                                         uint32_t(p->round_ops), p->stream, &p->prof, cnt);
@@ -254,6 +320,25 @@ int sf_pool_create(const sf_config* cfg, uint32_t max_slots, uint64_t round_ops,
     p->hist_groups = part_groups_max(L.merge_round, kHistExtra);
     q += round256(p->hist_groups * 2 * kMaxBuckets * 4);
     p->chunks = reinterpret_cast<MergeChunk*>(q);
+    q += round256(merge_chunks_max(L.merge_round) * sizeof(MergeChunk));
+    if (L.owner) {
+        p->owner_ok = true;
+        p->owner_ops = L.owner_ops;
+        p->own_og = L.og;
+        p->own.og = L.og;
+        p->own.pairs[0] = reinterpret_cast<uint64_t*>(q);
+        q += L.pairs;
+        p->own.pos = reinterpret_cast<uint32_t*>(q);
+        q += L.pos;
+        p->own.res = reinterpret_cast<uint64_t*>(q);
+        q += L.res;
+        p->own.level = reinterpret_cast<uint16_t*>(q);
+        q += L.level;
+        p->own.hmat = reinterpret_cast<uint32_t*>(q);
+        q += L.hmat;
+        p->own.pm[0] = reinterpret_cast<PairMeta*>(q);
+        q += L.pmeta;
+    }
     p->desc.resize(slots);
     const Geom geo = geom_of(cfg);
     for (uint64_t i = 0; i < slots; i++) {
@@ -354,23 +439,44 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
     const uint64_t limit = p->merge ? p->merge_round : p->round_ops;
     const uint64_t max_tiles = p->merge ? p->hist_groups : ~0ull;
     const uint64_t b = p->cfg.batch_ops;
+    // owner path: a batch of at least own_ratio * w ops (and at most the owner
+    // buffers' share of a sub-round) streams its slot's ranges; a sub-round
+    // holds at most qcap ranges per row of such batches
+    const bool owner = p->merge && p->owner_ok;
+    const uint32_t qcap = owner ? std::min<uint32_t>(kMaxRanges, kMaxCols / (2 * p->cfg.d)) : 0u;
+    const uint32_t slot_ranges =
+        owner ? uint32_t((uint64_t(p->cfg.w) + (1ull << p->own_og.cr_shift) - 1) >> p->own_og.cr_shift) : 0u;
+    auto owns = [&](uint64_t cnt) {
+        return owner && cnt <= p->owner_ops && double(cnt) >= p->own_ratio * double(p->cfg.w);
+    };
     std::vector<TileDesc> tiles;
     std::vector<SubRound> subs;
     uint64_t rounds = 0;
     for (uint32_t r = 0; r < n; r++)
         if (reqs[r].kind != SF_REQ_QUERY) rounds = std::max(rounds, (reqs[r].n + b - 1) / b);
     for (uint64_t k = 0; k < rounds; k++) {
-        uint64_t used = 0;
-        uint32_t first = uint32_t(tiles.size());
+        uint64_t used = 0, own_used = 0;
+        uint32_t first = uint32_t(tiles.size()), nq = 0;
+        bool side = false;
         for (uint32_t r = 0; r < n; r++) {
             const sf_request& q = reqs[r];
             if (q.kind == SF_REQ_QUERY || k * b >= q.n) continue;
             const uint64_t lo = k * b, cnt = std::min(b, q.n - lo);
             const uint64_t ntiles = (cnt + tile_ops - 1) / tile_ops;
-            if (used && (used + cnt > limit || tiles.size() - first + ntiles > max_tiles)) {
-                subs.push_back({first, uint32_t(tiles.size()) - first, used});
+            const bool o = owns(cnt);
+            if (used && (used + cnt > limit || tiles.size() - first + ntiles > max_tiles ||
+                         (o && (nq + slot_ranges > qcap || own_used + cnt > p->owner_ops)))) {
+                subs.push_back({first, uint32_t(tiles.size()) - first, used, nq, side});
                 first = uint32_t(tiles.size());
-                used = 0;
+                used = own_used = 0;
+                nq = 0;
+                side = false;
+            }
+            if (o) {
+                nq += slot_ranges;
+                own_used += cnt;
+            } else {
+                side = side || owner;
             }
             const uint32_t mode = q.kind == SF_REQ_UPDATE ? kOpsArray
                                   : q.kind == SF_REQ_DELETE ? kAllDelete : kAllInsert;
@@ -386,9 +492,32 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
             }
             used += cnt;
         }
-        if (uint32_t(tiles.size()) > first) subs.push_back({first, uint32_t(tiles.size()) - first, used});
+        if (uint32_t(tiles.size()) > first) subs.push_back({first, uint32_t(tiles.size()) - first, used, nq, side});
     }
     const size_t n_update_tiles = tiles.size();
+    // range tables of the owner sub-rounds: per slot its first range (~0:
+    // none), then per range its slot and its index in that slot
+    std::vector<uint32_t> tab;
+    for (auto& sr : subs) {
+        if (!sr.ranges) continue;
+        sr.table = tab.size();
+        tab.resize(sr.table + p->slots + 2ull * sr.ranges, ~0u);
+        uint32_t* qbase = tab.data() + sr.table;
+        uint32_t* qsk = qbase + p->slots;
+        uint32_t* qr = qsk + sr.ranges;
+        uint32_t qn = 0;
+        for (uint32_t t = sr.first; t < sr.first + sr.tiles;) {
+            const uint32_t slot = tiles[t].sketch;
+            uint64_t cnt = 0;  // the request's batch: its consecutive tiles
+            for (; t < sr.first + sr.tiles && tiles[t].sketch == slot; t++) cnt += tiles[t].count;
+            if (!owns(cnt)) continue;
+            qbase[slot] = qn;
+            for (uint32_t i = 0; i < slot_ranges; i++, qn++) {
+                qsk[qn] = slot;
+                qr[qn] = i;
+            }
+        }
+    }
     for (uint32_t r = 0; r < n; r++) {
         const sf_request& q = reqs[r];
         if (q.kind != SF_REQ_QUERY) continue;
@@ -402,6 +531,12 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
             tiles.push_back(t);
         }
     }
+    const size_t n_query_tiles = tiles.size() - n_update_tiles;
+    // the tables ride in the descriptor ring after the tiles (same lifetime)
+    const size_t tab_tiles = (tab.size() * 4 + sizeof(TileDesc) - 1) / sizeof(TileDesc);
+    const size_t tab_first = tiles.size();
+    tiles.resize(tiles.size() + tab_tiles, TileDesc{});
+    if (tab_tiles) std::memcpy(tiles.data() + tab_first, tab.data(), tab.size() * 4);
     size_t begin = 0;
     if (!tiles.empty() && (rc = ring_alloc(p, tiles.size(), &begin))) return rc;
     sf_pool::Flight f;
@@ -414,12 +549,12 @@ int sf_pool_launch(sf_pool* p, const sf_request* reqs, uint32_t n, uint64_t* tic
         e = hipMemcpyAsync(p->d_ring + begin, f.host.data(), f.host.size() * sizeof(TileDesc),
                            hipMemcpyHostToDevice, p->stream);
     if (e != hipSuccess) return device_fail(e, "tile upload");
-    if (kb == 4) launch_updates<4>(p, p->d_ring + begin, subs, f.host);
-    else launch_updates<13>(p, p->d_ring + begin, subs, f.host);
-    const size_t n_query_tiles = f.host.size() - n_update_tiles;
+    const uint32_t* d_tables = reinterpret_cast<const uint32_t*>(p->d_ring + begin + tab_first);
+    if (kb == 4) launch_updates<4>(p, p->d_ring + begin, subs, f.host, d_tables);
+    else launch_updates<13>(p, p->d_ring + begin, subs, f.host, d_tables);
     if (n_query_tiles) {
         uint64_t items = 0;
-        for (size_t t = n_update_tiles; t < f.host.size(); t++) items += f.host[t].count;
+        for (size_t t = n_update_tiles; t < n_update_tiles + n_query_tiles; t++) items += f.host[t].count;
         Timed tm(&p->prof, p->stream, SF_K_QUERY, items);
         if (kb == 4) {
             const ListPlan<4> plan{p->d_ring + begin + n_update_tiles, p->d_desc};
@@ -519,6 +654,14 @@ int sf_pool_set_tile(sf_pool* p, uint32_t tile_ops) {
 int sf_pool_set_merge(sf_pool* p, int batch_wide) {
     if (!live(p)) return fail(SF_ESTATE, "pool handle is not live");
     p->merge = batch_wide != 0;
+    return SF_OK;
+}
+
+int sf_pool_set_owner_ratio(sf_pool* p, double ratio) {
+    if (!live(p)) return fail(SF_ESTATE, "pool handle is not live");
+    if (!p->owner_ok) return fail(SF_EINVAL, "this pool's slots do not take the owner-computes path");
+    if (!(ratio >= 0.0 && ratio <= 1e6)) return fail(SF_EINVAL, "owner ratio must be in [0, 1e6]");
+    p->own_ratio = ratio;
     return SF_OK;
 }
 

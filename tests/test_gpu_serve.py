@@ -29,7 +29,7 @@ def _key_fn(w, pool_t):
     return lambda r: joined[(r.stream, r.seq)] if r.pieces else pool_t[r.off:r.off + r.n]
 
 
-def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15, merge=True):
+def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15, merge=True, ratio=None):
     import torch
     pool_t = torch.from_numpy(w.pool.view(np.int32)).cuda()
     key_of = _key_fn(w, pool_t)
@@ -40,6 +40,8 @@ def _run_mixed(w, max_slots, realtime, max_launch_keys=1 << 15, merge=True):
              for s in range(w.n_streams)}
     pool = sf.SketchPool(sf.make_config(**CFG), max_slots=max_slots)
     pool.set_merge(merge)
+    if ratio is not None:
+        pool.set_owner_ratio(ratio)
     srv = Server(pool, max_launch_keys=max_launch_keys, max_in_flight=3)
     st = srv.run(w.requests, key_of=key_of,
                  out_of=lambda r: outs[index[id(r)]], export_to=lambda s: slims[s], realtime=realtime)
@@ -87,11 +89,16 @@ def _oracle_stream(w, stream):
     return ref.slim(), ref.fat(), ans
 
 
-@pytest.mark.parametrize("realtime,merge", [(False, True), (True, True), (False, False)])
-def test_alone_equals_mixed_and_oracle(realtime, merge):
+@pytest.mark.parametrize("realtime,merge,ratio", [(False, True, None), (True, True, None), (False, False, None),
+                                                  (False, True, 0.0), (False, True, 0.5), (False, True, 1e6)])
+def test_alone_equals_mixed_and_oracle(realtime, merge, ratio):
+    """A request batch of at least ratio * w ops (default 1) takes the owner-computes path, the
+    others in its sub-round the atomic kernels; every ratio gives the oracle's state (the lone
+    runs keep the default ratio)."""
     w = _workload()
-    say(f"[case] serving mix realtime={realtime} merge={merge}: {len(w.requests)} requests, {w.n_streams} streams")
-    st, res, ans = _run_mixed(w, max_slots=8, realtime=realtime, merge=merge)
+    say(f"[case] serving mix realtime={realtime} merge={merge} ratio={ratio}: {len(w.requests)} requests, "
+        f"{w.n_streams} streams")
+    st, res, ans = _run_mixed(w, max_slots=8, realtime=realtime, merge=merge, ratio=ratio)
     say(f"  launches {st.launches}, mean {st.mean_requests_per_launch:.1f} req/launch, "
         f"latency {st.latency_ms}, peak resident {st.peak_resident}")
     assert st.peak_resident <= 8 and st.launches > 1 and st.mean_requests_per_launch > 1
@@ -162,4 +169,10 @@ def test_pool_rejects_bad_requests():
     t = pool.launch([(a, sf.SF_REQ_INSERT, keys, None, None)])
     pool.wait(t)
     assert pool.done(t)
+    with pytest.raises(sf.SFError):
+        pool.set_owner_ratio(-1.0)
     pool.close()
+    big = sf.SketchPool(sf.make_config(8, 1 << 21, 4, 4, 1, 1 << 20), max_slots=1)   # 320 MiB slots
+    with pytest.raises(sf.SFError):
+        big.set_owner_ratio(1.0)                                                      # no owner path
+    big.close()
