@@ -531,6 +531,13 @@ def run_serve(args, torch, np, sf, sfgen, shape_name, w=None):
     budget = 64 << 30
     pool = sf.SketchPool(cfg, hbm_budget_bytes=budget)
     pool.set_merge(args.merge != "tile")
+    owner_ratio = None
+    if args.merge != "tile":
+        try:
+            pool.set_owner_ratio(args.pool_owner_ratio)
+            owner_ratio = args.pool_owner_ratio
+        except sf.SFError:
+            pass  # slots too large for the owner path: atomic entry kernels throughout
     slots, _ = pool.capacity()
     dev = torch.device("cuda:0")
     keys = torch.from_numpy(w.pool.view(np.int32)).to(dev)
@@ -605,6 +612,7 @@ def run_serve(args, torch, np, sf, sfgen, shape_name, w=None):
                        f"occurrences), per-stream sketch d={shape['d']} Fat {shape['d']}x{shape['w'] * 4} u32, "
                        f"64 GiB HBM budget ({slots} resident sketches)",
            "saturation_mitems_s": round(sat.keys_per_s / 1e6, 2), "slots": slots,
+           "owner_ratio": owner_ratio,
            "oracle_checked_streams": check, "oracle_checked_query_answers": verified, "sweep": sweep}
     if head:
         out.update({"offered_load": head["offered_load"], "value": head["value"], "unit": "Mitems/s",
@@ -870,6 +878,8 @@ def main():
                     help="1024-sketch leg: skip the one-sketch-per-launch comparison (profiling runs)")
     ap.add_argument("--multi-shape-out", default="", help="write the 1024-sketch leg's batch sizes and group shape")
     ap.add_argument("--multi-shape-in", default="", help="run the 1024-sketch leg with a shape written before")
+    ap.add_argument("--pool-owner-ratio", type=float, default=0.5,
+                    help="serving pools: request batches of at least ratio * w ops take the owner path")
     ap.add_argument("--group-owner-ratio", type=float, default=0.0,
                     help="1024-sketch leg without autotuning: sf_group_set_owner_ratio")
     ap.add_argument("--group-round-ops", type=int, default=0,

@@ -406,7 +406,7 @@ int sf_pool_set_tile(sf_pool *p, uint32_t tile_ops);
  * pairs are merged across a sub-round of at most 2^24 ops (or batch_ops).
  * With batch-wide merging, pools whose slots hold at most 64 MiB of records
  * run a request batch of at least ratio * w ops (sf_pool_set_owner_ratio,
- * default 1) owner-computes: its slot's (row, range) tiles staged in LDS, a
+ * default 0.5) owner-computes: its slot's (row, range) tiles staged in LDS, a
  * sub-round's owner batches at most 2^22 ops and min(1024, 8192 / d) ranges
  * per row; the other batches of the sub-round take the atomic entry kernels.
  * The owner buffers are part of the shared buffers (fewer slots fit the

@@ -677,7 +677,7 @@ class SketchPool:
 
     def set_owner_ratio(self, ratio: float):
         """Batches of at least ratio * w ops take the owner-computes path (pools whose slots hold
-        at most 64 MiB of records; default 1)."""
+        at most 64 MiB of records; default 0.5)."""
         _check(lib().sf_pool_set_owner_ratio(self._h, float(ratio)), "sf_pool_set_owner_ratio")
 
     def merge_stats(self):

@@ -79,7 +79,7 @@ struct sf_pool {
     Profiler prof;
     // owner-computes S1..S5 (slots whose records are small enough to stream)
     bool owner_ok = false;
-    double own_ratio = 1.0;        // a batch is owner-computed when its ops >= own_ratio * w
+    double own_ratio = 0.5;        // a batch is owner-computed when its ops >= own_ratio * w
     uint64_t owner_ops = 0;        // owner batches' ops per sub-round at most
     OwnerGeom own_og{};
     OwnerBufs own{};

@@ -92,7 +92,7 @@ def _oracle_stream(w, stream):
 @pytest.mark.parametrize("realtime,merge,ratio", [(False, True, None), (True, True, None), (False, False, None),
                                                   (False, True, 0.0), (False, True, 0.5), (False, True, 1e6)])
 def test_alone_equals_mixed_and_oracle(realtime, merge, ratio):
-    """A request batch of at least ratio * w ops (default 1) takes the owner-computes path, the
+    """A request batch of at least ratio * w ops (default 0.5) takes the owner-computes path, the
     others in its sub-round the atomic kernels; every ratio gives the oracle's state (the lone
     runs keep the default ratio)."""
     w = _workload()
