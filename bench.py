@@ -1082,12 +1082,8 @@ def main():
         if "cpu_baseline" in multi:
             result["sketches_1024"]["cpu_baseline"] = multi["cpu_baseline"]
         torch.cuda.empty_cache()
-    if not args.no_serve:
-        w = serve_workload(args, sfgen)
-        shapes = ("flows", "small") if args.serve_shape == "both" else (args.serve_shape,)
-        for sh in shapes:
-            result["serving" if sh == "flows" else f"serving_{sh}"] = run_serve(args, torch, np, sf, sfgen, sh, w)
-
+    # the legs' oracle runs end before the serving loop starts: its host-side
+    # request loop then has the host to itself
     for leg, fut in jobs.items():
         log(f"[bench] waiting for the oracle of leg {leg} ...")
         orc = fut.result()
@@ -1098,6 +1094,12 @@ def main():
         leg_out[leg].update(cpu_baseline=cb, accuracy=orc.get("accuracy"), parity_full_size=True)
         log(f"[bench] {leg}: oracle {json.dumps(cb)}")
     pool.shutdown()
+
+    if not args.no_serve:
+        w = serve_workload(args, sfgen)
+        shapes = ("flows", "small") if args.serve_shape == "both" else (args.serve_shape,)
+        for sh in shapes:
+            result["serving" if sh == "flows" else f"serving_{sh}"] = run_serve(args, torch, np, sf, sfgen, sh, w)
     if leg_out:
         result["legs"] = leg_out
     print(json.dumps(result), flush=True)
