@@ -16,12 +16,18 @@
 // Merged sub-rounds hold at most kMergeRound ops (or one sketch's batch, if
 // larger): larger sub-rounds mean fewer launches, but past 2^24 ops the 512
 // buckets per op type span several LDS chunks each and fewer duplicates merge.
+// When every sketch has the same d and z, S1..S5 run owner-computes: each
+// sub-round numbers its sketches' cell ranges in a table of its own, and one
+// workgroup per (row, range) stages the range's records in LDS (sf_owner.hpp);
+// a sketch whose batch is sparse for its width (owner ratio) keeps the atomic
+// entry kernels in the same sub-round.
 //
-// Device memory (one allocation): every sketch's cell records (Fat bucket
-// and Slim working copy of a cell side by side), the sketch table, export
-// staging (largest dense Fat), the snapshot scratch
-// ([d_max][round_ops] uint32 + uint16), the merge buffers (partitioned keys,
-// entries, counts for one merged sub-round) and a growable tile table.
+// Device memory: one allocation holds every sketch's cell records (Fat
+// bucket and Slim working copy of a cell side by side), the sketch table,
+// export staging (largest dense Fat), the snapshot scratch
+// ([d_max][round_ops] uint32 + uint16) and the merge buffers (partitioned
+// keys, entries, counts for one merged sub-round); the owner path's buffers
+// are a second one, and the tile and range tables grow as needed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
