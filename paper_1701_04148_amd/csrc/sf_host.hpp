@@ -421,16 +421,31 @@ struct MergeRun {
             else
                 k_part_colscan_tall<uint32_t><<<blocks_for(2 * nb, kScanBuckets), kScanBuckets * kScanSegs, 0, ps>>>(
                     hist, part_groups, 2 * nb, meta);
-            k_part_start<KB, G><<<1, 2 * nb / kStartPer, 0, ps>>>(meta, chunks);
             bool done = false;
-            if constexpr (kWideOk) {
-                if (wide) {
-                    k_part_scatter<KB, G, P, kPartOpsWide><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, meta,
-                                                                                               part, nb_log2);
+            if constexpr (!G) {
+                // all buckets in use: the layout workgroup rides in the scatter launch
+                if (nb == kMaxBuckets) {
+                    if (wide)
+                        k_part_scatter_start<KB, P, kPartOpsWide><<<part_groups + 1, kPartThreads, 0, ps>>>(
+                            plan, hist, meta, chunks, part, nb_log2, part_groups);
+                    else
+                        k_part_scatter_start<KB, P, kPartOps><<<part_groups + 1, kPartThreads, 0, ps>>>(
+                            plan, hist, meta, chunks, part, nb_log2, part_groups);
                     done = true;
                 }
             }
-            if (!done) k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, meta, part, nb_log2);
+            if (!done) {
+                k_part_start<KB, G><<<1, 2 * nb / kStartPer, 0, ps>>>(meta, chunks);
+                if constexpr (kWideOk) {
+                    if (wide) {
+                        k_part_scatter<KB, G, P, kPartOpsWide><<<part_groups, kPartThreads, 0, ps>>>(
+                            plan, hist, meta, part, nb_log2);
+                        done = true;
+                    }
+                }
+                if (!done)
+                    k_part_scatter<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, meta, part, nb_log2);
+            }
         }
         {
             Timed tm(prof, ps, SF_K_MERGE, cnt);

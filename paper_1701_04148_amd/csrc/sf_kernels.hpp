@@ -733,9 +733,9 @@ constexpr uint32_t kStartPer = 2;
 constexpr uint32_t kBigChunks = 8, kBigList = 64;
 static_assert(2 * kMaxBuckets / kStartPer <= 1024, "k_part_start is one workgroup");
 static_assert((2 * kMaxBuckets) % kPartThreads == 0, "k_part_scatter gives each thread whole buckets");
+// The bucket layout of one batch, one workgroup of nbt / 2 threads.
 template <int KB, bool G>
-__global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(MergeMeta* __restrict__ meta,
-                                                                            MergeChunk* __restrict__ chunks) {
+__device__ __forceinline__ void part_start_block(MergeMeta* __restrict__ meta, MergeChunk* __restrict__ chunks) {
     constexpr uint32_t K = MergeShape<KB, G>::kChunk, H = K / 2, P = kStartPer;
     static_assert(P == 2, "the group-end lookup below assumes two buckets per thread");
     __shared__ uint32_t tmp[16];
@@ -823,14 +823,23 @@ __global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(Merg
     }
 }
 
+template <int KB, bool G>
+__global__ __launch_bounds__(2 * kMaxBuckets / kStartPer) void k_part_start(MergeMeta* __restrict__ meta,
+                                                                            MergeChunk* __restrict__ chunks) {
+    part_start_block<KB, G>(meta, chunks);
+}
+
 // Scatters the keys into their buckets (order inside a bucket is free).
 // uint32 keys are first sorted by bucket inside the group (LDS), so that the
 // group writes each bucket's keys as one contiguous run; wider keys go
 // straight to their slots.
-template <int KB, bool G, class P, uint32_t OPS = kPartOps>
-__global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uint32_t* __restrict__ offs,
-                                                         const MergeMeta* __restrict__ meta,
-                                                         MKey<KB, G>* __restrict__ part, uint32_t nb_log2) {
+// One partition tile, block blk of ntiles.  LOCAL_STARTS: the bucket starts
+// come from a scan of the bucket totals here, not from k_part_start.
+template <int KB, bool G, class P, uint32_t OPS, bool LOCAL_STARTS>
+__device__ __forceinline__ void part_scatter_tile(const P& plan, const uint32_t* __restrict__ offs,
+                                                  const MergeMeta* __restrict__ meta,
+                                                  MKey<KB, G>* __restrict__ part, uint32_t nb_log2, uint32_t blk,
+                                                  uint32_t ntiles) {
     constexpr uint32_t R = OPS / kPartThreads;  // keys per thread
     constexpr bool kStage = sizeof(MKey<KB, G>) <= 8;
     __shared__ uint32_t hist[2 * kMaxBuckets];       // local counts, then the group's first global slot
@@ -839,7 +848,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
     __shared__ MKey<KB, G> stage[kStage ? OPS : 1];
     __shared__ uint16_t sbk[kStage ? OPS : 1];
     const uint32_t nbt = 2u << nb_log2;
-    const Work w = plan.at(blockIdx.x, OPS);
+    const Work w = plan.at(blk, OPS);
     MKey<KB, G> k[R];
     uint32_t bk[R], rank[R];
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
@@ -873,8 +882,17 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
             lstart[t * kPer + e] = run;
             run += v[e];
         }
-        const uint32_t row = xcd_row(blockIdx.x, gridDim.x);
-        for (uint32_t b = t; b < nbt; b += kPartThreads) hist[b] = meta->start[b] + offs[size_t(row) * nbt + b];
+        const uint32_t row = xcd_row(blk, ntiles);
+        if constexpr (LOCAL_STARTS) {
+            // nbt = 2 * kPartThreads: thread t owns buckets 2t and 2t + 1
+            const uint32_t a0 = meta->total[2 * t], a1 = meta->total[2 * t + 1];
+            __syncthreads();  // tmp is free again (the scan above read it)
+            const uint32_t ex = block_scan(a0 + a1, AddOp{}, 0u, tmp) - (a0 + a1);
+            hist[2 * t] = ex + offs[size_t(row) * nbt + 2 * t];
+            hist[2 * t + 1] = ex + a0 + offs[size_t(row) * nbt + 2 * t + 1];
+        } else {
+            for (uint32_t b = t; b < nbt; b += kPartThreads) hist[b] = meta->start[b] + offs[size_t(row) * nbt + b];
+        }
         __syncthreads();
 #pragma unroll
         for (uint32_t r = 0; r < R; r++) {
@@ -892,8 +910,15 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
         }
     } else {
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads)
-            hist[b] = meta->start[b] + offs[size_t(xcd_row(blockIdx.x, gridDim.x)) * nbt + b];
+        const uint32_t row = xcd_row(blk, ntiles), t = threadIdx.x;
+        if constexpr (LOCAL_STARTS) {
+            const uint32_t a0 = meta->total[2 * t], a1 = meta->total[2 * t + 1];
+            const uint32_t ex = block_scan(a0 + a1, AddOp{}, 0u, tmp) - (a0 + a1);
+            hist[2 * t] = ex + offs[size_t(row) * nbt + 2 * t];
+            hist[2 * t + 1] = ex + a0 + offs[size_t(row) * nbt + 2 * t + 1];
+        } else {
+            for (uint32_t b = t; b < nbt; b += kPartThreads) hist[b] = meta->start[b] + offs[size_t(row) * nbt + b];
+        }
         __syncthreads();
 #pragma unroll
         for (uint32_t r = 0; r < R; r++) {
@@ -901,6 +926,32 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uin
             if (t < w.count) part[hist[bk[r]] + rank[r]] = k[r];
         }
     }
+}
+
+template <int KB, bool G, class P, uint32_t OPS = kPartOps>
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter(P plan, const uint32_t* __restrict__ offs,
+                                                               const MergeMeta* __restrict__ meta,
+                                                               MKey<KB, G>* __restrict__ part, uint32_t nb_log2) {
+    part_scatter_tile<KB, G, P, OPS, false>(plan, offs, meta, part, nb_log2, blockIdx.x, gridDim.x);
+}
+
+// A lone sketch's batch with all 2 * kMaxBuckets buckets of staged uint32
+// keys: the last workgroup lays the buckets and merge chunks out (as
+// k_part_start does), the others scatter their tiles with the bucket starts
+// scanned from the totals themselves, so no launch sits between the column
+// scan and the scatter.  Neither side reads what the other writes.
+template <int KB, class P, uint32_t OPS>
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter_start(P plan, const uint32_t* __restrict__ offs,
+                                                                     MergeMeta* __restrict__ meta,
+                                                                     MergeChunk* __restrict__ chunks,
+                                                                     MKey<KB, false>* __restrict__ part,
+                                                                     uint32_t nb_log2, uint32_t ntiles) {
+    static_assert(2 * kMaxBuckets / kStartPer == kPartThreads, "the layout workgroup is a partition workgroup");
+    if (blockIdx.x == ntiles) {
+        part_start_block<KB, false>(meta, chunks);
+        return;
+    }
+    part_scatter_tile<KB, false, P, OPS, true>(plan, offs, meta, part, nb_log2, blockIdx.x, ntiles);
 }
 
 // Merges one chunk and emits its entries (key, count).  cap = entry capacity
