@@ -512,6 +512,12 @@ struct MergeMeta {                    // device-side bookkeeping of one batch
 // side by the entry kernels -- share a narrow range of row-0 cell records
 // that stays in cache.  With a sketch table it is the top log2(nb) bits of
 // the key's hash.  (The merge table's slot comes from a different hash.)
+// floor(h * 2^nb_log2 / w) for widths that are no power of two, kept out of
+// line: a 64-bit division inlined once per key bloats the partition kernels.
+__device__ __noinline__ uint32_t bucket_div(uint32_t h, uint32_t nb_log2, uint32_t w) {
+    return uint32_t((uint64_t(h) << nb_log2) / w);
+}
+
 template <int KB, bool G>
 __device__ __forceinline__ uint32_t bucket_of(const MKey<KB, G>& k, bool del, uint32_t nb_log2, const Geom& g) {
     uint32_t b;
@@ -520,7 +526,10 @@ __device__ __forceinline__ uint32_t bucket_of(const MKey<KB, G>& k, bool del, ui
     } else {
         uint32_t h, f;
         split(g, Mixed<KB>(k.k).row(g.seed_base), h, f);
-        b = uint32_t((uint64_t(h) << nb_log2) / g.w);
+        if (g.pow2)  // floor(h * nb / w) with both powers of two
+            b = g.w_shift >= nb_log2 ? h >> (g.w_shift - nb_log2) : h << (nb_log2 - g.w_shift);
+        else
+            b = bucket_div(h, nb_log2, g.w);
     }
     return b + (del ? (1u << nb_log2) : 0u);
 }
@@ -570,19 +579,49 @@ __device__ __forceinline__ uint32_t xcd_row(uint32_t b, uint32_t n) {
     return x * q + min(x, r) + b / 8u;
 }
 
+// The thread's R keys of a partition tile (kPartThreads apart) and their op
+// types, every load issued before any is used: the loop bodies hold no
+// branch, so they stay in one basic block.  Slots past the tile's end load
+// its first key and must be skipped by the caller (t >= w.count).
+template <int KB, bool G, uint32_t R>
+__device__ __forceinline__ void load_tile_keys(const Work& w, MKey<KB, G> (&k)[R], bool (&del)[R]) {
+    uint32_t opb[R];
+    if (w.mode == kOpsArray) {
+#pragma unroll
+        for (uint32_t r = 0; r < R; r++) {
+            const uint32_t t = r * kPartThreads + threadIdx.x;
+            opb[r] = w.ops[t < w.count ? t : 0u];
+        }
+    } else {
+#pragma unroll
+        for (uint32_t r = 0; r < R; r++) opb[r] = w.mode == kAllDelete ? 1u : 0u;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; r++) {
+        const uint32_t t = r * kPartThreads + threadIdx.x;
+        k[r] = mkey<KB, G>(load_key<KB>(w.keys, t < w.count ? t : 0u), w.sketch);
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; r++) del[r] = opb[r] != 0;
+}
+
 // Counts the ops of every bucket in each group's tile.
 // The histogram of tile blk (of ntiles): one workgroup of kPartThreads.
 template <int KB, bool G, class P, uint32_t OPS>
 __device__ __forceinline__ void part_count_tile(const P& plan, uint32_t* __restrict__ hist_out, uint32_t nb_log2,
                                                 uint32_t blk, uint32_t ntiles) {
+    constexpr uint32_t R = OPS / kPartThreads;  // keys per thread (a tile holds at most OPS)
     __shared__ uint32_t hist[2 * kMaxBuckets];
     const uint32_t nbt = 2u << nb_log2;
     const Work w = plan.at(blk, OPS);
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
+    MKey<KB, G> k[R];
+    bool del[R];
+    if (w.count) load_tile_keys<KB, G, R>(w, k, del);
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < w.count; t += kPartThreads) {
-        const MKey<KB, G> k = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
-        atomicAdd(&hist[bucket_of<KB, G>(k, is_delete(w.ops, t, w.mode), nb_log2, w.g)], 1u);
+#pragma unroll
+    for (uint32_t r = 0; r < R; r++) {
+        if (r * kPartThreads + threadIdx.x < w.count) atomicAdd(&hist[bucket_of<KB, G>(k[r], del[r], nb_log2, w.g)], 1u);
     }
     __syncthreads();
     const uint32_t row = xcd_row(blk, ntiles);
@@ -850,8 +889,10 @@ __device__ __forceinline__ void part_scatter_tile(const P& plan, const uint32_t*
     const uint32_t nbt = 2u << nb_log2;
     const Work w = plan.at(blk, OPS);
     MKey<KB, G> k[R];
+    bool del[R];
     uint32_t bk[R], rank[R];
     for (uint32_t b = threadIdx.x; b < nbt; b += kPartThreads) hist[b] = 0;
+    if (w.count) load_tile_keys<KB, G, R>(w, k, del);
     __syncthreads();
 #pragma unroll
     for (uint32_t r = 0; r < R; r++) {
@@ -859,8 +900,7 @@ __device__ __forceinline__ void part_scatter_tile(const P& plan, const uint32_t*
         bk[r] = 0;
         rank[r] = 0;
         if (t < w.count) {
-            k[r] = mkey<KB, G>(load_key<KB>(w.keys, t), w.sketch);
-            bk[r] = bucket_of<KB, G>(k[r], is_delete(w.ops, t, w.mode), nb_log2, w.g);
+            bk[r] = bucket_of<KB, G>(k[r], del[r], nb_log2, w.g);
             rank[r] = atomicAdd(&hist[bk[r]], 1u);   // place among the group's keys of the bucket
         }
     }
