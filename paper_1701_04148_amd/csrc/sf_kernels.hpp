@@ -1038,17 +1038,22 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
     // about two slots per key (at least one per thread): a small chunk clears
     // and probes a small table
     const uint32_t slots = min(kSlots, max(kThreads, 2 * n));
+    // the chunk's keys in flight before any is used (slots past its end load
+    // its first key and stay invalid)
+    MKey<KB, G> k[J] = {};
+    if (n) {
+#pragma unroll
+        for (int j = 0; j < J; j++) {
+            const uint32_t idx = uint32_t(j) * kThreads + threadIdx.x;
+            k[j] = part[first + (idx < n ? idx : 0u)];
+        }
+    }
     for (uint32_t i = threadIdx.x; i < slots; i += kThreads) L.slot[i] = kEmpty;
     if (threadIdx.x == 0) nloc = 0;
-    __syncthreads();
-    MKey<KB, G> k[J];
 #pragma unroll
     for (int j = 0; j < J; j++) {
         const uint32_t idx = uint32_t(j) * kThreads + threadIdx.x;
-        if (idx < n) {
-            k[j] = part[first + idx];
-            L.key[idx] = k[j];
-        }
+        if (idx < n) L.key[idx] = k[j];
     }
     __syncthreads();
     uint32_t made[J];                             // slots this thread created (one per new key)
@@ -1097,15 +1102,23 @@ __global__ __launch_bounds__((MergeShape<KB, G>::kThreads)) void k_merge(const M
             __syncthreads();                      // every count has been read from the table
             for (uint32_t i = threadIdx.x; i < ncnt; i += kThreads) L.slot[i] = 0;
             __syncthreads();
+            // every snapshot gather in flight before any is stored (a thread
+            // without the entry reads cell 0 and drops it)
+            uint32_t hc[J], fc[J], sa[J], sb[J];
+#pragma unroll
+            for (int j = 0; j < J; j++) {
+                split(sd.g, Mixed<KB>(k[j].k).row(sd.g.seed_base), hc[j], fc[j]);
+                const bool e = made[j] != kEmpty;
+                const uint32_t* rec = sd.fat + size_t(e ? hc[j] : 0u) * sd.g.rs;  // row 0
+                sa[j] = rec[z];
+                sb[j] = rec[e ? fc[j] : 0u];
+            }
 #pragma unroll
             for (int j = 0; j < J; j++) {
                 if (made[j] == kEmpty) continue;
-                uint32_t h, f;
-                split(sd.g, Mixed<KB>(k[j].k).row(sd.g.seed_base), h, f);
-                const uint32_t* rec = sd.fat + size_t(h) * sd.g.rs;  // row 0
-                asnap[eid[j]] = uint16_t(rec[z]);
-                bpre[eid[j]] = rec[f];
-                atomicAdd(&L.slot[(h - lo) * z + f], ecnt[j]);
+                asnap[eid[j]] = uint16_t(sa[j]);
+                bpre[eid[j]] = sb[j];
+                atomicAdd(&L.slot[(hc[j] - lo) * z + fc[j]], ecnt[j]);
             }
             __syncthreads();                      // every snapshot read before a counter moves
             for (uint32_t i = threadIdx.x; i < ncnt; i += kThreads) {

@@ -241,22 +241,31 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_scatter(const MergeMeta* 
     const uint32_t d = og.d, R = og.R, nc = 2 * R;
     const uint32_t cmask = (1u << og.cr_shift) - 1;
     for (uint32_t c = threadIdx.x; c < nc; c += kPairThreads) cnt[c] = 0;
-    __syncthreads();
     uint32_t eid[E], c16[E], col[E], code[E], rank[E];
     bool own[E];  // the entry's sketch is owner-computed (always, for a lone sketch)
+    MKey<KB, G> mk[E];
+    uint32_t ec[E];
+    // every entry's key and count in flight before any is used (slots past
+    // the tile's end load its first entry and are skipped below)
 #pragma unroll
     for (uint32_t j = 0; j < E; j++) {
         const uint32_t t = j * kPairThreads + threadIdx.x;
-        eid[j] = 0;
+        eid[j] = entry_of(lo + (t < n ? t : 0u), ni, cap);
+        mk[j] = ent_key[eid[j]];
+        ec[j] = ent_cnt[eid[j]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < E; j++) {
+        const uint32_t t = j * kPairThreads + threadIdx.x;
         own[j] = false;
         c16[j] = col[j] = code[j] = rank[j] = 0;
         if (t < n) {
-            eid[j] = entry_of(lo + t, ni, cap);
-            const MKey<KB, G> m = ent_key[eid[j]];
+            const MKey<KB, G>& m = mk[j];
             const uint32_t sk = mkey_sketch<KB, G>(m);
             own[j] = rm.has(sk);
             if (own[j]) {
-                c16[j] = ent_cnt[eid[j]] & ~kRow0Done;
+                c16[j] = ec[j] & ~kRow0Done;
                 const Geom g = sr.of(sk).g;
                 uint32_t h, f;
                 split(g, Mixed<KB>(m.k).row(g.seed_base + i), h, f);
@@ -320,10 +329,15 @@ __device__ __forceinline__ void level_tile(uint32_t blk, const PairMeta* __restr
     if (lo >= ni) return;
     const uint32_t hi = min(ni, lo + T), d = D ? uint32_t(D) : d_rt;
     bool in[E];  // an insert entry of an owner-computed sketch (its pairs hold its snapshots)
+    // Every load below is unconditional, at an index that always exists (the
+    // tile's first entry, pair 0) where the entry is not one of these, so
+    // that all of a loop's loads are in flight together; the values loaded
+    // for such slots are never used.
 #pragma unroll
     for (uint32_t j = 0; j < E; j++) {
         const uint32_t e = lo + j * NT + threadIdx.x;
-        in[j] = e < hi && rm.has(mkey_sketch<KB, G>(ent_key[e < hi ? e : lo]));
+        const MKey<KB, G> m = ent_key[e < hi ? e : lo];
+        in[j] = (e < hi) & rm.has(mkey_sketch<KB, G>(m));
     }
     uint32_t m0[E], dl[E], bm[E];
 #pragma unroll
@@ -333,11 +347,11 @@ __device__ __forceinline__ void level_tile(uint32_t blk, const PairMeta* __restr
 #pragma unroll
         for (uint32_t j = 0; j < E; j++) {
             const uint32_t e = lo + j * NT + threadIdx.x;
-            ps[j] = in[j] ? pos[size_t(i) * pos_stride + e] : 0u;
+            ps[j] = pos[size_t(i) * pos_stride + (in[j] ? e : lo)];
         }
 #pragma unroll
         for (uint32_t j = 0; j < E; j++) {
-            const uint64_t r = in[j] ? res[ps[j]] : 0ull;
+            const uint64_t r = res[in[j] ? ps[j] : 0u];
             m0[j] = min(m0[j], uint32_t(r) & 0xffffu);
             dl[j] = min(dl[j], uint32_t(r >> 16) & 0xffffu);
             bm[j] = min(bm[j], uint32_t(r >> 32) & 0xffffu);
