@@ -441,40 +441,46 @@ __global__ __launch_bounds__(NT) void k_own_step(SR sr, RM rm, OwnerGeom og,
     auto cell_of = [&](uint64_t pr) { return ((uint32_t(pr >> 32) & 0xffffu) >> og.zbits) * rs; };
     auto slot_of = [&](uint64_t pr) { return uint32_t(pr >> 32) & zmask; };
     // The pairs (and the T of the previous batch's inserts) do not depend on
-    // the records: their loads go out first, so that they overlap the staging
-    // of the range instead of following it.
-    uint64_t qf[KF], qd[KD], qi[K];
+    // the records: their loads go out first, then the range's, so that all of
+    // them are in flight together.  Each load is unconditional inside a
+    // uniform branch (a slot past the column's end reloads its last pair and
+    // is skipped below): a load guarded per lane would be waited for at once.
+    uint64_t qf[KF] = {}, qd[KD] = {}, qi[K] = {};
+    if (fi0 != fi1) {
 #pragma unroll
-    for (uint32_t k = 0; k < KF; k++) {
-        const uint32_t p = fi0 + k * T + threadIdx.x;
-        qf[k] = p < fi1 ? pairs_f[p] : 0ull;
+        for (uint32_t k = 0; k < KF; k++) qf[k] = pairs_f[min(fi0 + k * T + threadIdx.x, fi1 - 1)];
     }
+    if (fd0 != fd1) {
 #pragma unroll
-    for (uint32_t k = 0; k < KD; k++) {
-        const uint32_t p = fd0 + k * T + threadIdx.x;
-        qd[k] = p < fd1 ? pairs_f[p] : 0ull;
+        for (uint32_t k = 0; k < KD; k++) qd[k] = pairs_f[min(fd0 + k * T + threadIdx.x, fd1 - 1)];
     }
+    if (i0 != i1) {
 #pragma unroll
-    for (uint32_t k = 0; k < K; k++) {
-        const uint32_t p = i0 + k * T + threadIdx.x;
-        qi[k] = p < i1 ? pairs_i[p] : 0ull;
+        for (uint32_t k = 0; k < K; k++) qi[k] = pairs_i[min(i0 + k * T + threadIdx.x, i1 - 1)];
     }
-    uint32_t lv[KF];
-#pragma unroll
-    for (uint32_t k = 0; k < KF; k++) {
-        const uint32_t p = fi0 + k * T + threadIdx.x;
-        lv[k] = p < fi1 ? uint32_t(level[uint32_t(qf[k])]) : 0u;
-    }
-    // the range in 16-byte pieces where it is 16-byte aligned, several loads in
-    // flight per thread
+    // the range in 16-byte pieces where it is 16-byte aligned: the first U per
+    // thread held in registers, the rest (larger ranges) copied by a loop
+    constexpr uint32_t U = 6;
     const bool vec = (reinterpret_cast<uintptr_t>(rec0) & 15u) == 0;
     const uint32_t n4 = vec ? nw / 4 : 0u;
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // a native vector: stays in registers
+    const v4u* src4 = reinterpret_cast<const v4u*>(rec0);
+    v4u sv[U];  // (read only where u * T + threadIdx.x < n4)
+    if (n4) {
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) sv[u] = src4[min(u * T + threadIdx.x, n4 - 1)];
+    }
+    uint32_t lv[KF] = {};
+    if (fi0 != fi1) {
+#pragma unroll
+        for (uint32_t k = 0; k < KF; k++) lv[k] = level[uint32_t(qf[k])];
+    }
     {
-        const uint4* src = reinterpret_cast<const uint4*>(rec0);
-        uint4* dst = reinterpret_cast<uint4*>(L);
-#pragma unroll 4
-        for (uint32_t i = threadIdx.x; i < n4; i += T) dst[i] = src[i];
-#pragma unroll 4
+        v4u* dst = reinterpret_cast<v4u*>(L);
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++)
+            if (u * T + threadIdx.x < n4) dst[u * T + threadIdx.x] = sv[u];
+        for (uint32_t i = U * T + threadIdx.x; i < n4; i += T) dst[i] = src4[i];
         for (uint32_t i = 4 * n4 + threadIdx.x; i < nw; i += T) L[i] = rec0[i];
     }
     __syncthreads();
