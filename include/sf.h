@@ -180,8 +180,11 @@ int sf_query_slim_noalloc(const uint16_t *slim, const sf_config *cfg, const void
 
 /* Slim export, the structure sent to the collector (Sections 1 and 3): d*w
  * uint16 counters, row-major [d][w].  out may be host or device memory with
- * room for out_elems >= d*w elements.  Synchronous.  The sketch keeps its
- * own copy of what it exported, for sf_query. */
+ * room for out_elems >= d*w elements.  A host destination is complete when
+ * the call returns; a device destination is written in order on the
+ * sketch's stream (work later on that stream sees it; another stream must
+ * synchronise first, e.g. with sf_sync).  The sketch keeps its own copy of
+ * what it exported, for sf_query. */
 int sf_export_slim(sf_sketch *sk, uint16_t *out, uint64_t out_elems);
 
 /* Fat export, the Fat-subsketch of Section 3.4's structure (d arrays of w

@@ -737,8 +737,10 @@ int sf_export_slim(sf_sketch* s, uint16_t* out, uint64_t out_elems) {
     } else if (!host) {
         e = hipMemcpyAsync(out, s->view, cells * 2, hipMemcpyDeviceToDevice, s->stream);
     }
+    // a host destination is complete on return; a device one is written in
+    // order on the sketch's stream, like every other device output
     if (e == hipSuccess && host) e = hipMemcpyAsync(out, s->view, cells * 2, hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess && host) e = hipStreamSynchronize(s->stream);
     return e == hipSuccess ? SF_OK : device_fail(e, "sf_export_slim");
 }
 
