@@ -347,6 +347,31 @@ def test_query_reads_exported_copy_only_while_fresh():
     sk.close()
 
 
+def test_device_export_is_stream_ordered():
+    """A device-destination sf_export_slim returns without waiting for its kernel;
+    work queued after it on the same stream -- sf_query_slim reading the exported
+    buffer, then another update and export into that buffer -- sees its result.
+    w = 2^20 so that the export (4M cells) is still running when the call returns."""
+    import torch
+    d, w, z, b = 4, 1 << 20, 4, 1 << 17
+    rng = np.random.default_rng(23)
+    keys, ops, uni = random_turnstile(rng, 300_000, 40_000, 0.1)
+    half = keys.shape[0] // 2
+    ref = oracle.Sketch(d, w, z)
+    sk = sf.Sketch(d, w, z, batch_ops=b)
+    dev16 = torch.empty(d * w, dtype=torch.int16, device="cuda")
+    q = dev_keys(uni)
+    out = torch.empty(uni.shape[0], dtype=torch.int32, device="cuda")
+    for lo, hi in ((0, half), (half, keys.shape[0])):
+        sk.update(dev_keys(keys[lo:hi]), torch.from_numpy(ops[lo:hi]).cuda())
+        sf.sf_export_slim(sk._h, dev16)           # ordered on the sketch's (null) stream
+        sf.sf_query_slim(dev16, sk.cfg, q, out)   # the same stream: reads the finished copy
+        assert ref.batch(keys[lo:hi], ops[lo:hi], b, checked=True) == 0
+        assert_same(out.cpu().numpy().view(np.uint32), ref.query(uni), "query of the exported copy")
+        assert_same(dev16.cpu().numpy().view(np.uint16).reshape(d, w), ref.slim(), "exported Slim")
+    sk.close()
+
+
 def test_empty_and_tiny_inputs():
     import torch
     sk = sf.Sketch(4, 64, 4, batch_ops=8)
