@@ -413,9 +413,9 @@ struct MergeRun {
                 k_part_count<KB, G, P, kPartOpsWide><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, nb_log2);
             else
                 k_part_count<KB, G, P><<<part_groups, kPartThreads, 0, ps>>>(plan, hist, nb_log2);
-            // one lane per bucket pays off for 512..1024 rows; fewer rows (small
+            // one lane per bucket pays off for 256..1024 rows; fewer rows (small
             // batches) or more (sketch tables) spread better over segments
-            if (part_groups >= kScanWaves * kScanRowsReg / 2 && part_groups <= kScanWaves * kScanRowsReg)
+            if (part_groups >= kScanWaves * kScanRowsReg / 4 && part_groups <= kScanWaves * kScanRowsReg)
                 k_part_colscan<uint32_t><<<blocks_for(2 * nb, kScanCols), kScanCols * kScanWaves, 0, ps>>>(
                     hist, part_groups, 2 * nb, meta);
             else
